@@ -1,0 +1,75 @@
+"""Seeded synthetic inputs shared by the oracle side and the GPU side.
+
+This module holds no arithmetic of the method: it only turns (seed, index)
+counters into pseudo-random numbers, so that the CPU oracle and the GPU
+library can be fed bit-identical right-hand sides and initial blocks.
+
+Generator: SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014), used counter-style: the value with index
+``i`` under seed ``s`` is ``mix(s + (i + 1) * 0x9E3779B97F4A7C15)`` with the
+published two-round xor-shift-multiply finaliser.  Uniforms take the top 53
+bits; Gaussians use the Box-Muller transform of two consecutive uniforms.
+
+The paper only says its initial approximations are pseudo-random (Section 2
+model problem); the distributions used here are the workload recipe of the
+benchmarks (uniform [-1, 1) right-hand sides, standard normal LOBPCG blocks).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Raw 64-bit outputs with indices start .. start+count-1 (uint64 array)."""
+    with np.errstate(over="ignore"):
+        idx = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + idx * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Doubles in [0, 1) from the top 53 bits."""
+    z = splitmix64(seed, start, count)
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def uniform_pm1(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Doubles in [-1, 1): the right-hand-side distribution of the workloads."""
+    return 2.0 * uniform01(seed, count, start) - 1.0
+
+
+def gaussian(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Standard normal doubles by Box-Muller on uniform pairs (2i, 2i+1)."""
+    z = splitmix64(seed, 2 * start, 2 * count)
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    u1 = 1.0 - u[0::2]          # (0, 1]: keeps log finite
+    u2 = u[1::2]
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def rhs(nx: int, ny: int, nz: int, seed: int) -> np.ndarray:
+    """Right-hand side b ~ U[-1, 1), flattened with x fastest (index i + nx*(j + ny*k))."""
+    return uniform_pm1(seed, nx * ny * nz)
+
+
+def block(n: int, m: int, seed: int) -> np.ndarray:
+    """Initial LOBPCG block, n rows by m columns, column-major (column c is entries c*n .. c*n+n-1).
+
+    Returned as an (m, n) C-contiguous array, i.e. one row per column vector.
+    """
+    return gaussian(seed, n * m).reshape(m, n)
+
+
+def box_dims(count: int, lo: int, hi: int, seed: int) -> list:
+    """``count`` boxes with nx, ny, nz drawn uniformly from the integers lo..hi inclusive."""
+    u = uniform01(seed, 3 * count)
+    d = lo + np.floor(u * (hi - lo + 1)).astype(np.int64)
+    d = np.minimum(d, hi)
+    return [tuple(int(v) for v in d[3 * i:3 * i + 3]) for i in range(count)]
