@@ -1,0 +1,154 @@
+/*
+ * smg.h -- C ABI of the MI355X (gfx950) SMG-preconditioned Krylov library.
+ *
+ * Problem (Section 2 of Bouwmeester, Dougherty and Knyazev, "Nonsymmetric
+ * multigrid preconditioning for conjugate gradient methods"): the 7-point
+ * negative Laplacian A on an nx*ny*nz brick with homogeneous Dirichlet
+ * boundary,
+ *     (A x)_{ijk} = cx(2x_{ijk} - x_{i-1jk} - x_{i+1jk}) + cy(...j...) + cz(...k...),
+ * neighbours outside the brick counted as zero.  The paper uses unit grid
+ * size (cx = cy = cz = 1); a unit cube with n interior points per axis has
+ * c = (n+1)^2.
+ *
+ * Preconditioner T (Section 3): one V-cycle of semicoarsening multigrid
+ * (SMG) from a zero initial guess, with plane relaxation as the smoother at
+ * every level and independent pre- and post-smoothing counts:
+ *   - z is coarsened by two (coarse planes are the odd fine planes), with
+ *     linear prolongation P, restriction P^T and Galerkin operators P^T A P;
+ *   - a smoothing step is one zebra sweep: every plane of one colour gets the
+ *     correction x_k += V2_k((b - A x)_k), then the other colour; pre-sweeps
+ *     take the colours in the order F (even) then C (odd), post-sweeps in
+ *     reverse, so that equal counts give a symmetric operator (Section 1);
+ *   - V2_k is one 2D V-cycle of the same construction in y on plane k's
+ *     operator, with x-lines relaxed zebra-wise by exact tridiagonal solves
+ *     and one exact line solve on its coarsest level.
+ * pre = post gives a symmetric positive definite T; post = 0 gives the
+ * nonsymmetric preconditioner that the paper studies.
+ *
+ * Solvers: Algorithm 1 of Section 2 with beta from equation (1) (pcg_solve),
+ * equation (2) (fpcg_solve) or beta = 0 (psd_solve); LOBPCG (Section 4) for
+ * the m smallest eigenpairs.
+ *
+ * Memory: every vector argument is a DEVICE pointer to FP64 data laid out
+ * with index i + nx*(j + ny*k) (x fastest); a block of nrhs vectors is
+ * column-major with leading dimension ld >= nx*ny*nz.  The caller owns every
+ * buffer, including the device workspace handed to smg_setup; the library
+ * never frees caller memory and allocates no device memory of its own.
+ * `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work
+ * on `stream`; solvers synchronise it before returning their info.
+ * A handle is not thread-safe; distinct handles are independent.
+ *
+ * Return codes: SMG_OK (0); SMG_NOT_CONVERGED (1, outputs valid);
+ * SMG_EINVAL (-1); SMG_EWORKSPACE (-2); SMG_EHIP (-3); SMG_EBREAKDOWN (-4, a
+ * zero or non-finite denominator in the recurrence); SMG_ENONFINITE (-5, a
+ * non-finite input).  No exception or abort crosses this interface.
+ */
+#ifndef SMG_H
+#define SMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SMG_OK = 0,
+    SMG_NOT_CONVERGED = 1,
+    SMG_EINVAL = -1,
+    SMG_EWORKSPACE = -2,
+    SMG_EHIP = -3,
+    SMG_EBREAKDOWN = -4,
+    SMG_ENONFINITE = -5
+};
+
+/* Storage/arithmetic precision of the SMG hierarchy.  The Krylov recurrences,
+ * dot products and LOBPCG's Rayleigh-Ritz always run in FP64; with F32 or
+ * BF16 the preconditioner converts r to that precision on entry and s back to
+ * FP64 on exit (BF16: bfloat16 storage, FP32 arithmetic). */
+enum { SMG_PREC_F64 = 0, SMG_PREC_F32 = 1, SMG_PREC_BF16 = 2 };
+
+enum { SMG_PRECOND_SMG = 0, SMG_PRECOND_NONE = 1 };
+
+typedef struct smg_grid {
+    int32_t nx, ny, nz;     /* brick size, each >= 1, nx <= 512 */
+    double cx, cy, cz;      /* axis coefficients, each > 0 */
+} smg_grid;
+
+typedef struct smg_opts {
+    int32_t pre, post;              /* 3D smoothing counts, 0..8 each */
+    int32_t inner_pre, inner_post;  /* 2D plane-cycle counts; -1 inherits pre/post */
+    int32_t order;                  /* 0: pre F then C (default); 1: pre C then F */
+    int32_t precision;              /* SMG_PREC_* */
+} smg_opts;
+
+typedef struct krylov_opts {
+    double rtol;            /* stop when ||r_k||_2 <= rtol*||b||_2 (recursive r) */
+    int32_t max_iter;       /* >= 0 */
+    int32_t precond;        /* SMG_PRECOND_SMG or SMG_PRECOND_NONE (T = I) */
+    int32_t x0_zero;        /* 1: ignore the contents of x and start from 0 */
+    int32_t reserved;
+    double *history;        /* HOST, nullable, max_iter+1 entries: ||r_k||/||b|| */
+    double *history_c;      /* HOST, nullable, max_iter entries: sqrt|(s_k,r_k)| / sqrt|(s_0,r_0)| */
+} krylov_opts;
+
+typedef struct krylov_info {
+    int32_t iters;          /* number of x updates performed */
+    int32_t status;         /* same value as the return code */
+    double rel_res;         /* ||r||_2/||b||_2 of the recursive residual */
+    double true_rel_res;    /* ||b - A x||_2/||b||_2 recomputed at exit */
+    double solve_seconds;   /* wall time of the iteration, host clock */
+} krylov_info;
+
+typedef struct smg_handle smg_handle;
+
+/* Bytes of device workspace smg_setup needs for this grid and options when
+ * smg_apply is called with up to max_nrhs right-hand sides at once (the
+ * single-vector Krylov solvers need max_nrhs >= 1).  Host-only; no GPU work. */
+int smg_workspace_bytes(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, size_t *bytes);
+
+/* Builds the SMG hierarchy (Galerkin coefficients in z and, per plane, in y;
+ * Thomas factor tables of every distinct line operator) inside the caller's
+ * device workspace `ws` of `ws_bytes` bytes (>= smg_workspace_bytes) and
+ * returns a handle in *out.  The workspace must stay valid and untouched
+ * until smg_destroy. */
+int smg_setup(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, void *ws, size_t ws_bytes,
+              void *stream, smg_handle **out);
+
+/* s = T r for nrhs vectors (1 <= nrhs <= max_nrhs), leading dimension ld.
+ * r is read only; r and s must not overlap. */
+int smg_apply(smg_handle *h, const double *r, double *s, int32_t nrhs, int64_t ld, void *stream);
+
+/* y = A x for nrhs vectors; x and y must not overlap. */
+int smg_matvec(smg_handle *h, const double *x, double *y, int32_t nrhs, int64_t ld, void *stream);
+
+/* Algorithm 1, Section 2.  b and x are single device vectors of nx*ny*nz
+ * doubles; x holds x0 on entry (unless o->x0_zero) and the iterate on exit.
+ * pcg_solve: beta from equation (1); fpcg_solve: equation (2), evaluated as
+ * -alpha_{k-1} (s_k, A p_{k-1}) = (s_k, r_k - r_{k-1}); psd_solve: beta = 0.
+ * Returns SMG_OK when converged, SMG_NOT_CONVERGED when max_iter was reached. */
+int pcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream);
+int fpcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream);
+int psd_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream);
+
+/* Releases the host-side handle (the caller's workspace is not freed). */
+int smg_destroy(smg_handle *h);
+
+/* Static message for a return code. */
+const char *smg_strerror(int status);
+
+/* Per-kernel timing of the most frequently launched SMG kernel family
+ * (zebra x-line relaxation): runs `reps` V-cycles of nrhs = 1 on `r`/`s`,
+ * timing every launch of that kernel with HIP events on `stream`, and
+ * returns the launch count per V-cycle, the summed kernel milliseconds per
+ * V-cycle and the algorithmic bytes per V-cycle of those launches (line
+ * right-hand side, neighbour lines and result, once each). */
+int smg_profile_line_relax(smg_handle *h, const double *r, double *s, int32_t reps, void *stream,
+                           int32_t *launches, double *kernel_ms, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMG_H */

@@ -1,0 +1,281 @@
+// Vector kernels of Algorithm 1 (Section 2) for gfx950.
+//
+// Each Krylov step outside the preconditioner is three fused HBM passes:
+//   dots      (s_k, r_k) and, for equation (2), (s_k, q_{k-1}) where
+//             q_{k-1} = A p_{k-1}, so that (s_k, r_k - r_{k-1}) = -alpha_{k-1}(s_k, q_{k-1});
+//   p/q       p_k = s_k + beta_k p_{k-1} into the other p buffer, q_k = A p_k from
+//             the same neighbour loads, and (p_k, q_k);
+//   x/r       x += alpha p, r -= alpha q, and ||r||^2.
+// Reductions are deterministic: a fixed grid of kRedBlocks blocks writes one
+// partial per block (wave shuffles, then LDS across the block's waves), and
+// a one-block finalize kernel sums the partials in a fixed order and advances
+// the scalar recurrence on the device.
+#include "smg_internal.h"
+
+namespace smg {
+
+namespace {
+
+constexpr int kRB = 256;   // threads per reduction block
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sums v over the block; the result is valid in thread 0.
+__device__ inline double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) s += lds[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// (A x) at point c = (i, j, k) of the 7-point operator
+__device__ inline double a7(const double *x, long long c, int i, int j, int k, int nx, int ny, int nz, double cx,
+                            double cy, double cz)
+{
+    const long long pl = static_cast<long long>(nx) * ny;
+    double v = (2.0 * (cx + cy + cz)) * x[c];
+    if (i > 0) v -= cx * x[c - 1];
+    if (i < nx - 1) v -= cx * x[c + 1];
+    if (j > 0) v -= cy * x[c - nx];
+    if (j < ny - 1) v -= cy * x[c + nx];
+    if (k > 0) v -= cz * x[c - pl];
+    if (k < nz - 1) v -= cz * x[c + pl];
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_matvec7(const double *x, double *y, long long ld, int nx, int ny, int nz,
+                                                 double cx, double cy, double cz)
+{
+    const int c2 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c2 >= nx * ny) return;
+    const int k = blockIdx.y, r = blockIdx.z;
+    const int i = c2 % nx, j = c2 / nx;
+    const long long c = static_cast<long long>(k) * nx * ny + c2;
+    y[r * ld + c] = a7(x + r * ld, c, i, j, k, nx, ny, nz, cx, cy, cz);
+}
+
+__global__ __launch_bounds__(kRB) void k_init_resid(const double *b, const double *x, double *r, int x_zero, int nx,
+                                                    int ny, int nz, double cx, double cy, double cz,
+                                                    double *partials)
+{
+    __shared__ double lds[kRB / 64];
+    const long long n = static_cast<long long>(nx) * ny * nz;
+    double rr = 0.0, bb = 0.0;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const double bv = b[c];
+        double rv = bv;
+        if (!x_zero) {
+            const int i = static_cast<int>(c % nx);
+            const long long t = c / nx;
+            const int j = static_cast<int>(t % ny), k = static_cast<int>(t / ny);
+            rv -= a7(x, c, i, j, k, nx, ny, nz, cx, cy, cz);
+        }
+        r[c] = rv;
+        rr += rv * rv;
+        bb += bv * bv;
+    }
+    rr = block_sum(rr, lds);
+    bb = block_sum(bb, lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = rr;
+        partials[kRedBlocks + blockIdx.x] = bb;
+    }
+}
+
+__global__ __launch_bounds__(kRB) void k_dots_sr_sq(const double *s, const double *r, const double *q, int want_sq,
+                                                    long long n, double *partials)
+{
+    __shared__ double lds[kRB / 64];
+    double sr = 0.0, sq = 0.0;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const double sv = s[c];
+        sr += sv * r[c];
+        if (want_sq) sq += sv * q[c];
+    }
+    sr = block_sum(sr, lds);
+    sq = block_sum(sq, lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = sr;
+        partials[kRedBlocks + blockIdx.x] = sq;
+    }
+}
+
+__global__ __launch_bounds__(kRB) void k_update_p_q(const double *s, const double *p_old, double *p_new, double *q,
+                                                    const KScalars *sc, int nx, int ny, int nz, double cx, double cy,
+                                                    double cz, double *partials)
+{
+    __shared__ double lds[kRB / 64];
+    const double beta = sc->beta;
+    const long long pl = static_cast<long long>(nx) * ny;
+    const long long n = pl * nz;
+    double pq = 0.0;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int i = static_cast<int>(c % nx);
+        const long long t = c / nx;
+        const int j = static_cast<int>(t % ny), k = static_cast<int>(t / ny);
+        // p_k at c and at its neighbours, formed from s_k and p_{k-1}
+        auto pv = [&](long long cc) { return beta == 0.0 ? s[cc] : s[cc] + beta * p_old[cc]; };
+        const double p0 = pv(c);
+        double qv = (2.0 * (cx + cy + cz)) * p0;
+        if (i > 0) qv -= cx * pv(c - 1);
+        if (i < nx - 1) qv -= cx * pv(c + 1);
+        if (j > 0) qv -= cy * pv(c - nx);
+        if (j < ny - 1) qv -= cy * pv(c + nx);
+        if (k > 0) qv -= cz * pv(c - pl);
+        if (k < nz - 1) qv -= cz * pv(c + pl);
+        p_new[c] = p0;
+        q[c] = qv;
+        pq += p0 * qv;
+    }
+    pq = block_sum(pq, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = pq;
+}
+
+__global__ __launch_bounds__(kRB) void k_update_xr(double *x, double *r, const double *p, const double *q,
+                                                   const KScalars *sc, long long n, double *partials)
+{
+    __shared__ double lds[kRB / 64];
+    const double alpha = sc->alpha;
+    double rr = 0.0;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+        x[c] += alpha * p[c];
+        const double rv = r[c] - alpha * q[c];
+        r[c] = rv;
+        rr += rv * rv;
+    }
+    rr = block_sum(rr, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = rr;
+}
+
+__device__ inline double sum_partials(const double *p, double *lds)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += p[i];
+    return block_sum(v, lds);
+}
+
+// method: 0 = PCG (1), 1 = FPCG (2), 2 = PSD
+__global__ __launch_bounds__(kRB) void k_finalize(int which, int method, int k, const double *partials,
+                                                  KScalars *sc)
+{
+    __shared__ double lds[kRB / 64];
+    const double v0 = sum_partials(partials, lds);
+    const double v1 = (which <= 1) ? sum_partials(partials + kRedBlocks, lds) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (which == 0) {
+        sc->rr = v0;
+        sc->bb = v1;
+        sc->breakdown = 0;
+        sc->sr_prev = 0.0;
+        sc->alpha_prev = 0.0;
+    } else if (which == 1) {
+        sc->sr = v0;
+        sc->sq = v1;
+        double beta = 0.0;
+        if (k > 0 && method == 0) beta = v0 / sc->sr_prev;
+        if (k > 0 && method == 1) beta = -sc->alpha_prev * v1 / sc->sr_prev;
+        if (!isfinite(beta) || !isfinite(v0)) sc->breakdown = 1;
+        sc->beta = beta;
+    } else if (which == 2) {
+        sc->pq = v0;
+        const double alpha = sc->sr / v0;
+        if (!isfinite(alpha)) sc->breakdown = 1;
+        sc->alpha = alpha;
+        sc->alpha_prev = alpha;
+        sc->sr_prev = sc->sr;
+    } else {
+        sc->rr = v0;
+    }
+}
+
+__global__ void k_copy(const double *src, double *dst, long long n)
+{
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x)
+        dst[c] = src[c];
+}
+
+__global__ void k_fill(double *dst, double v, long long n)
+{
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x)
+        dst[c] = v;
+}
+
+}  // namespace
+
+void launch_fill(double *dst, double v, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill, dim3(kRedBlocks), dim3(256), 0, st, dst, v, static_cast<long long>(n));
+}
+
+void launch_matvec7(const double *x, double *y, long long ld, int nrhs, int nx, int ny, int nz, double cx, double cy,
+                    double cz, hipStream_t st)
+{
+    const dim3 grid((nx * ny + 255) / 256, nz, nrhs);
+    hipLaunchKernelGGL(k_matvec7, grid, dim3(256), 0, st, x, y, ld, nx, ny, nz, cx, cy, cz);
+}
+
+void launch_init_resid(const double *b, const double *x, double *r, int x_zero, int nx, int ny, int nz, double cx,
+                       double cy, double cz, double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_resid, dim3(kRedBlocks), dim3(kRB), 0, st, b, x, r, x_zero, nx, ny, nz, cx, cy, cz,
+                       partials);
+}
+
+void launch_dots_sr_sq(const double *s, const double *r, const double *q, int want_sq, size_t n, double *partials,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dots_sr_sq, dim3(kRedBlocks), dim3(kRB), 0, st, s, r, q, want_sq,
+                       static_cast<long long>(n), partials);
+}
+
+void launch_update_p_q(const double *s, const double *p_old, double *p_new, double *q, const KScalars *sc, int nx,
+                       int ny, int nz, double cx, double cy, double cz, double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update_p_q, dim3(kRedBlocks), dim3(kRB), 0, st, s, p_old, p_new, q, sc, nx, ny, nz, cx, cy,
+                       cz, partials);
+}
+
+void launch_update_xr(double *x, double *r, const double *p, const double *q, const KScalars *sc, size_t n,
+                      double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update_xr, dim3(kRedBlocks), dim3(kRB), 0, st, x, r, p, q, sc, static_cast<long long>(n),
+                       partials);
+}
+
+void launch_finalize(int which, int method, int k, const double *partials, KScalars *sc, KScalars *host_copy,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRB), 0, st, which, method, k, partials, sc);
+    if (host_copy) (void)hipMemcpyAsync(host_copy, sc, sizeof(KScalars), hipMemcpyDeviceToHost, st);
+}
+
+void launch_copy(const double *src, double *dst, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy, dim3(kRedBlocks), dim3(256), 0, st, src, dst, static_cast<long long>(n));
+}
+
+void launch_true_resid(const double *b, const double *x, double *tmp, int nx, int ny, int nz, double cx, double cy,
+                       double cz, double *partials, hipStream_t st)
+{
+    launch_init_resid(b, x, tmp, 0, nx, ny, nz, cx, cy, cz, partials, st);
+}
+
+}  // namespace smg

@@ -1,0 +1,768 @@
+// Host side of the SMG library: setup, V-cycle schedule, Krylov loops, C ABI.
+//
+// Setup follows the Section 3 reading of SMG: z-semicoarsening with Galerkin
+// coarse operators.  Because the prolongation acts on the plane index only,
+// every level stays block-tridiagonal with blocks in span{T2, I}, so a level
+// is four scalars per plane (C_K = ca*T2 + cb*I, U_K = ua*T2 + ub*I).  The
+// same construction in y turns every plane operator alpha*T2 + beta*I into a
+// 2D hierarchy of x-line blocks in span{Tx, I}.  Planes with equal (ca, cb)
+// share one 2D hierarchy ("plane type") and lines with equal (la, lb) share
+// one Thomas factor table, so the tables are a few hundred KB even at 384^3.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <utility>
+
+#include "smg_internal.h"
+
+using namespace smg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxSmooth = 8;
+constexpr int kMaxNx = 512;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int levels_of(int n)
+{
+    int L = 1;
+    while (n > 1) {
+        n /= 2;
+        ++L;
+    }
+    return L;
+}
+
+// Galerkin coarsening of a block-tridiagonal operator with diagonal blocks
+// D_f = da[f]*S + db[f]*I and couplings O_f = oa[f]*S + ob[f]*I (f <-> f+1)
+// under linear interpolation from the odd points:
+//   D^c_K = 1/4 D_{2K} + D_{2K+1} + 1/4 D_{2K+2} + O_{2K} + O_{2K+1}
+//   O^c_K = 1/2 O_{2K+1} + 1/4 D_{2K+2} + 1/2 O_{2K+2}
+// (terms naming a block past the end are absent).
+struct BlockTri {
+    std::vector<double> da, db, oa, ob;   // oa/ob have size n (last entry unused)
+    int n() const { return static_cast<int>(da.size()); }
+};
+
+BlockTri galerkin(const BlockTri &f)
+{
+    const int n = f.n(), nc = n / 2;
+    BlockTri c;
+    c.da.assign(nc, 0.0);
+    c.db.assign(nc, 0.0);
+    c.oa.assign(nc, 0.0);
+    c.ob.assign(nc, 0.0);
+    for (int K = 0; K < nc; ++K) {
+        const int f0 = 2 * K, f1 = 2 * K + 1, f2 = 2 * K + 2;
+        double a = 0.25 * f.da[f0] + f.da[f1] + f.oa[f0];
+        double b = 0.25 * f.db[f0] + f.db[f1] + f.ob[f0];
+        if (f2 < n) {
+            a += 0.25 * f.da[f2] + f.oa[f1];
+            b += 0.25 * f.db[f2] + f.ob[f1];
+        }
+        c.da[K] = a;
+        c.db[K] = b;
+        if (K + 1 < nc) {
+            c.oa[K] = 0.5 * f.oa[f1] + 0.25 * f.da[f2] + 0.5 * f.oa[f2];
+            c.ob[K] = 0.5 * f.ob[f1] + 0.25 * f.db[f2] + 0.5 * f.ob[f2];
+        }
+    }
+    return c;
+}
+
+struct Layout {
+    size_t pcoef, lcoef, uniq, fac;        // tables
+    std::vector<size_t> xl, bl;             // 3D levels >= 1
+    std::vector<size_t> x2, b2;             // 2D batch buffers per 2D level
+    size_t rlo, slo;                        // low-precision level-0 in/out
+    size_t kr, ks, kp0, kp1, kq, part, sc;  // Krylov
+    size_t total;
+};
+
+}  // namespace
+
+struct smg_handle {
+    smg_grid g;
+    smg_opts o;
+    int ipre, ipost;
+    int max_nrhs;
+    size_t N;
+    int E, nxp;
+    std::vector<int> nz;          // 3D level sizes
+    std::vector<size_t> pc_off;   // PlaneCoef row offset per 3D level
+    std::vector<int> ny2;         // 2D level sizes (shared by every plane)
+    std::vector<int> lev2_off;    // line row offset per 2D level
+    int lines_total;
+    int nptypes, nfac, P2;
+    size_t elem;                  // bytes per stored value
+    char *ws;
+    Layout L;
+    KScalars *host_sc;            // pinned host mirror of the device scalars
+    // profiling of the line-relax kernel family
+    bool prof;
+    std::vector<hipEvent_t> ev;
+    int ev_used;
+    double prof_bytes;
+    template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
+};
+
+namespace {
+
+int check_grid(const smg_grid *g, const smg_opts *o)
+{
+    if (!g || !o) return SMG_EINVAL;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nx > kMaxNx) return SMG_EINVAL;
+    if (!(g->cx > 0.0) || !(g->cy > 0.0) || !(g->cz > 0.0)) return SMG_EINVAL;
+    if (!std::isfinite(g->cx) || !std::isfinite(g->cy) || !std::isfinite(g->cz)) return SMG_EINVAL;
+    if (o->pre < 0 || o->post < 0 || o->pre > kMaxSmooth || o->post > kMaxSmooth) return SMG_EINVAL;
+    if (o->inner_pre < -1 || o->inner_post < -1 || o->inner_pre > kMaxSmooth || o->inner_post > kMaxSmooth)
+        return SMG_EINVAL;
+    if (o->order != 0 && o->order != 1) return SMG_EINVAL;
+    if (o->precision < SMG_PREC_F64 || o->precision > SMG_PREC_BF16) return SMG_EINVAL;
+    return SMG_OK;
+}
+
+size_t elem_size(int prec) { return prec == SMG_PREC_F64 ? 8 : prec == SMG_PREC_F32 ? 4 : 2; }
+size_t arith_size(int prec) { return prec == SMG_PREC_F64 ? 8 : 4; }
+
+// Table sizes need the dedup counts, which depend only on the grid; the
+// host part of the setup is cheap, so sizing runs it too.
+struct Tables {
+    std::vector<int> nz;
+    std::vector<BlockTri> lev3;
+    std::vector<std::pair<double, double>> ptypes;   // (ca, cb) per plane type
+    std::vector<std::vector<int>> ptype_of;          // per level, per plane
+    std::vector<int> ny2, lev2_off;
+    int lines_total = 0;
+    // per plane type: concatenated 2D level rows (la, lb, va, vb, fac)
+    std::vector<double> line_rows;                    // 4 doubles per row
+    std::vector<int> line_fac;
+    std::vector<std::pair<double, double>> uniq;      // (la, lb) per Thomas table
+};
+
+Tables build_tables(const smg_grid &g)
+{
+    Tables t;
+    BlockTri f;
+    f.da.assign(g.nz, 1.0);
+    f.db.assign(g.nz, 2.0 * g.cz);
+    f.oa.assign(g.nz, 0.0);
+    f.ob.assign(g.nz, -g.cz);
+    t.lev3.push_back(f);
+    while (t.lev3.back().n() > 1) t.lev3.push_back(galerkin(t.lev3.back()));
+    for (auto &L : t.lev3) t.nz.push_back(L.n());
+
+    std::map<std::pair<double, double>, int> pmap;
+    for (auto &L : t.lev3) {
+        std::vector<int> pt(L.n());
+        for (int k = 0; k < L.n(); ++k) {
+            auto key = std::make_pair(L.da[k], L.db[k]);
+            auto it = pmap.find(key);
+            if (it == pmap.end()) {
+                it = pmap.emplace(key, static_cast<int>(t.ptypes.size())).first;
+                t.ptypes.push_back(key);
+            }
+            pt[k] = it->second;
+        }
+        t.ptype_of.push_back(pt);
+    }
+
+    int n = g.ny;
+    t.ny2.push_back(n);
+    while (n > 1) {
+        n /= 2;
+        t.ny2.push_back(n);
+    }
+    t.lines_total = 0;
+    for (int v : t.ny2) {
+        t.lev2_off.push_back(t.lines_total);
+        t.lines_total += v;
+    }
+
+    std::map<std::pair<double, double>, int> fmap;
+    for (auto &pt : t.ptypes) {
+        const double alpha = pt.first, beta = pt.second;
+        BlockTri l0;
+        l0.da.assign(g.ny, alpha * g.cx);
+        l0.db.assign(g.ny, 2.0 * alpha * g.cy + beta);
+        l0.oa.assign(g.ny, 0.0);
+        l0.ob.assign(g.ny, -alpha * g.cy);
+        BlockTri cur = l0;
+        for (size_t l = 0; l < t.ny2.size(); ++l) {
+            if (l > 0) cur = galerkin(cur);
+            for (int j = 0; j < cur.n(); ++j) {
+                const bool last = j == cur.n() - 1;
+                t.line_rows.push_back(cur.da[j]);
+                t.line_rows.push_back(cur.db[j]);
+                t.line_rows.push_back(last ? 0.0 : cur.oa[j]);
+                t.line_rows.push_back(last ? 0.0 : cur.ob[j]);
+                auto key = std::make_pair(cur.da[j], cur.db[j]);
+                auto it = fmap.find(key);
+                if (it == fmap.end()) {
+                    it = fmap.emplace(key, static_cast<int>(t.uniq.size())).first;
+                    t.uniq.push_back(key);
+                }
+                t.line_fac.push_back(it->second);
+            }
+        }
+    }
+    return t;
+}
+
+Layout make_layout(const smg_grid &g, const smg_opts &o, int max_nrhs, const Tables &t, int nxp)
+{
+    Layout L{};
+    const size_t es = elem_size(o.precision), as = arith_size(o.precision);
+    const size_t N = static_cast<size_t>(g.nx) * g.ny * g.nz;
+    const size_t pl = static_cast<size_t>(g.nx) * g.ny;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = off;
+        off = align_up(off + bytes);
+        return r;
+    };
+    size_t nplanes = 0;
+    for (int v : t.nz) nplanes += v;
+    const size_t pcsz = as == 8 ? sizeof(PlaneCoef<double>) : sizeof(PlaneCoef<float>);
+    const size_t lcsz = as == 8 ? sizeof(LineCoef<double>) : sizeof(LineCoef<float>);
+    const size_t fsz = as == 8 ? sizeof(Fac<double>) : sizeof(Fac<float>);
+    L.pcoef = take(nplanes * pcsz);
+    L.lcoef = take(t.ptypes.size() * t.lines_total * lcsz);
+    L.uniq = take(t.uniq.size() * lcsz);
+    L.fac = take(t.uniq.size() * nxp * fsz);
+    L.xl.assign(t.nz.size(), 0);
+    L.bl.assign(t.nz.size(), 0);
+    for (size_t l = 1; l < t.nz.size(); ++l) {
+        L.xl[l] = take(static_cast<size_t>(max_nrhs) * pl * t.nz[l] * es);
+        L.bl[l] = take(static_cast<size_t>(max_nrhs) * pl * t.nz[l] * es);
+    }
+    const size_t P2 = (g.nz + 1) / 2;
+    for (size_t l = 0; l < t.ny2.size(); ++l) {
+        const size_t sz = static_cast<size_t>(max_nrhs) * P2 * g.nx * t.ny2[l] * es;
+        L.x2.push_back(take(sz));
+        L.b2.push_back(take(sz));
+    }
+    if (o.precision != SMG_PREC_F64) {
+        L.rlo = take(static_cast<size_t>(max_nrhs) * N * es);
+        L.slo = take(static_cast<size_t>(max_nrhs) * N * es);
+    }
+    L.kr = take(N * 8);
+    L.ks = take(N * 8);
+    L.kp0 = take(N * 8);
+    L.kp1 = take(N * 8);
+    L.kq = take(N * 8);
+    L.part = take(2 * kRedBlocks * 8);
+    L.sc = take(sizeof(KScalars));
+    L.total = off;
+    return L;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+template <typename T, typename A>
+struct VCycle {
+    smg_handle *h;
+    hipStream_t st;
+    int nrhs;
+    T *x0;
+    const T *b0;
+    long long ld0;
+
+    struct Batch {          // a set of planes handled by one batched 2D cycle
+        int np, kmul, koff;
+        const PlaneCoef<A> *pc;
+        T *x;
+        long long xps, xrs;
+        const T *b;
+        long long bps, brs;
+    };
+
+    long long pl() const { return static_cast<long long>(h->g.nx) * h->g.ny; }
+    long long nl(int l) const { return pl() * h->nz[l]; }
+    T *X(int l) const { return l == 0 ? x0 : h->at<T>(h->L.xl[l]); }
+    T *B(int l) const { return l == 0 ? const_cast<T *>(b0) : h->at<T>(h->L.bl[l]); }
+    long long LD(int l) const { return l == 0 ? ld0 : nl(l); }
+    const PlaneCoef<A> *PC(int l) const { return h->at<PlaneCoef<A>>(h->L.pcoef) + h->pc_off[l]; }
+    const LineCoef<A> *LC(int l2) const { return h->at<LineCoef<A>>(h->L.lcoef) + h->lev2_off[l2]; }
+    long long ps2(int l2) const { return static_cast<long long>(h->g.nx) * h->ny2[l2]; }
+    long long rs2(int l2) const { return static_cast<long long>(h->P2) * ps2(l2); }
+
+    void line_relax(const Batch &bt, int l2, T *x, long long xps, long long xrs, const T *b, long long bps,
+                    long long brs, int colour, int nbr_zero)
+    {
+        LineRelaxArgs<T, A> a{};
+        a.x = x; a.b = b;
+        a.xps = xps; a.xrs = xrs; a.bps = bps; a.brs = brs;
+        a.nx = h->g.nx;
+        a.ny = h->ny2[l2];
+        a.colour = colour;
+        a.nq = a.ny == 1 ? 1 : (colour == 0 ? (a.ny + 1) / 2 : a.ny / 2);
+        a.np = bt.np; a.nrhs = nrhs; a.kmul = bt.kmul; a.koff = bt.koff;
+        a.pc = bt.pc;
+        a.lc = LC(l2);
+        a.lines_total = h->lines_total;
+        a.fac = h->at<Fac<A>>(h->L.fac);
+        a.nxp = h->nxp;
+        a.nbr_zero = nbr_zero || a.ny == 1;
+        int slot = -1;
+        if (h->prof && h->ev_used + 2 <= static_cast<int>(h->ev.size())) {
+            slot = h->ev_used;
+            h->ev_used += 2;
+            (void)hipEventRecord(h->ev[slot], st);
+        }
+        launch_line_relax<T, A>(a, st);
+        if (slot >= 0) {
+            (void)hipEventRecord(h->ev[slot + 1], st);
+            const double lines = a.nbr_zero ? 2.0 * a.nq : static_cast<double>(a.nq + a.ny);
+            h->prof_bytes += lines * a.nx * sizeof(T) * a.np * a.nrhs;
+        }
+    }
+
+    void v2(const Batch &bt, int l2)
+    {
+        const int ny = h->ny2[l2];
+        T *x = l2 == 0 ? bt.x : h->at<T>(h->L.x2[l2]);
+        const T *b = l2 == 0 ? bt.b : h->at<T>(h->L.b2[l2]);
+        const long long xps = l2 == 0 ? bt.xps : ps2(l2), xrs = l2 == 0 ? bt.xrs : rs2(l2);
+        const long long bps = l2 == 0 ? bt.bps : ps2(l2), brs = l2 == 0 ? bt.brs : rs2(l2);
+        if (ny == 1) {
+            line_relax(bt, l2, x, xps, xrs, b, bps, brs, 0, 1);
+            return;
+        }
+        const int first = h->o.order == 0 ? 0 : 1, second = 1 - first;
+        for (int s = 0; s < h->ipre; ++s) {
+            line_relax(bt, l2, x, xps, xrs, b, bps, brs, first, s == 0);
+            line_relax(bt, l2, x, xps, xrs, b, bps, brs, second, 0);
+        }
+        const int x_zero = h->ipre == 0;
+        Restrict2Args<T, A> ra{};
+        ra.x = x; ra.b = b; ra.bc = h->at<T>(h->L.b2[l2 + 1]);
+        ra.xps = xps; ra.xrs = xrs; ra.bps = bps; ra.brs = brs;
+        ra.cps = ps2(l2 + 1); ra.crs = rs2(l2 + 1);
+        ra.nx = h->g.nx; ra.ny = ny; ra.nyc = h->ny2[l2 + 1];
+        ra.np = bt.np; ra.nrhs = nrhs; ra.kmul = bt.kmul; ra.koff = bt.koff;
+        ra.pc = bt.pc; ra.lc = LC(l2); ra.lines_total = h->lines_total;
+        ra.x_zero = x_zero;
+        launch_restrict2<T, A>(ra, st);
+        v2(bt, l2 + 1);
+        Prolong2Args<T, A> pa{};
+        pa.x = x; pa.xc = h->at<T>(h->L.x2[l2 + 1]);
+        pa.xps = xps; pa.xrs = xrs; pa.cps = ps2(l2 + 1); pa.crs = rs2(l2 + 1);
+        pa.nx = h->g.nx; pa.ny = ny; pa.nyc = h->ny2[l2 + 1];
+        pa.np = bt.np; pa.nrhs = nrhs; pa.x_zero = x_zero;
+        launch_prolong2<T, A>(pa, st);
+        for (int s = 0; s < h->ipost; ++s) {
+            line_relax(bt, l2, x, xps, xrs, b, bps, brs, second, 0);
+            line_relax(bt, l2, x, xps, xrs, b, bps, brs, first, 0);
+        }
+    }
+
+    // one zebra half-sweep over the planes of one colour at 3D level l
+    void sweep3(int l, int colour, bool all_zero, bool self_zero)
+    {
+        const int nz = h->nz[l];
+        const int np = colour == 0 ? (nz + 1) / 2 : nz / 2;
+        if (np == 0) return;
+        T *X0 = X(l);
+        const T *B0 = B(l);
+        const long long p = pl(), ld = LD(l);
+        Batch bt{np, 2, colour, PC(l), nullptr, 0, 0, nullptr, 0, 0};
+        if (all_zero) {            // x = 0: the plane right-hand sides are b itself
+            bt.x = X0 + colour * p; bt.xps = 2 * p; bt.xrs = ld;
+            bt.b = B0 + colour * p; bt.bps = 2 * p; bt.brs = ld;
+            v2(bt, 0);
+            return;
+        }
+        Resid3Args<T, A> ra{};
+        ra.x = X0; ra.b = B0; ra.r = h->at<T>(h->L.b2[0]);
+        ra.xrs = ld; ra.brs = ld; ra.rps = p; ra.rrs = rs2(0);
+        ra.nx = h->g.nx; ra.ny = h->g.ny; ra.nz = nz; ra.np = np; ra.nrhs = nrhs;
+        ra.kmul = 2; ra.koff = colour;
+        ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
+        ra.pc = PC(l);
+        ra.self_zero = self_zero;
+        launch_resid3<T, A>(ra, st);
+        bt.b = ra.r; bt.bps = p; bt.brs = rs2(0);
+        if (self_zero) {           // own planes still zero: write the solve in place
+            bt.x = X0 + colour * p; bt.xps = 2 * p; bt.xrs = ld;
+            v2(bt, 0);
+            return;
+        }
+        bt.x = h->at<T>(h->L.x2[0]); bt.xps = p; bt.xrs = rs2(0);
+        v2(bt, 0);
+        Correct3Args<T, A> ca{};
+        ca.x = X0; ca.y = bt.x; ca.xrs = ld; ca.yps = p; ca.yrs = rs2(0);
+        ca.nx = h->g.nx; ca.ny = h->g.ny; ca.np = np; ca.nrhs = nrhs; ca.kmul = 2; ca.koff = colour;
+        launch_correct3<T, A>(ca, st);
+    }
+
+    void v3(int l)
+    {
+        const int nz = h->nz[l];
+        if (nz == 1) {
+            Batch bt{1, 1, 0, PC(l), X(l), pl(), LD(l), B(l), pl(), LD(l)};
+            v2(bt, 0);
+            return;
+        }
+        const int first = h->o.order == 0 ? 0 : 1, second = 1 - first;
+        for (int s = 0; s < h->o.pre; ++s) {
+            sweep3(l, first, s == 0, s == 0);
+            sweep3(l, second, false, s == 0);
+        }
+        const int x_zero = h->o.pre == 0;
+        Restrict3Args<T, A> ra{};
+        ra.x = X(l); ra.b = B(l); ra.bc = B(l + 1);
+        ra.xrs = LD(l); ra.brs = LD(l); ra.crs = nl(l + 1);
+        ra.nx = h->g.nx; ra.ny = h->g.ny; ra.nz = nz; ra.nzc = h->nz[l + 1]; ra.nrhs = nrhs;
+        ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
+        ra.pc = PC(l);
+        ra.x_zero = x_zero;
+        launch_restrict3<T, A>(ra, st);
+        v3(l + 1);
+        Prolong3Args<T, A> pa{};
+        pa.x = X(l); pa.xc = X(l + 1); pa.xrs = LD(l); pa.crs = nl(l + 1);
+        pa.nx = h->g.nx; pa.ny = h->g.ny; pa.nz = nz; pa.nzc = h->nz[l + 1]; pa.nrhs = nrhs;
+        pa.x_zero = x_zero;
+        launch_prolong3<T, A>(pa, st);
+        for (int s = 0; s < h->o.post; ++s) {
+            sweep3(l, second, false, false);
+            sweep3(l, first, false, false);
+        }
+    }
+};
+
+template <typename T, typename A>
+void run_vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
+{
+    VCycle<T, A> vc{h, st, nrhs, nullptr, nullptr, 0};
+    if constexpr (sizeof(T) == 8) {
+        vc.x0 = reinterpret_cast<T *>(s);
+        vc.b0 = reinterpret_cast<const T *>(r);
+        vc.ld0 = ld;
+        vc.v3(0);
+    } else {
+        T *rlo = h->at<T>(h->L.rlo), *slo = h->at<T>(h->L.slo);
+        launch_convert_in<T>(r, ld, rlo, static_cast<long long>(h->N), h->N, nrhs, st);
+        vc.x0 = slo;
+        vc.b0 = rlo;
+        vc.ld0 = static_cast<long long>(h->N);
+        vc.v3(0);
+        launch_convert_out<T>(slo, static_cast<long long>(h->N), s, ld, h->N, nrhs, st);
+    }
+}
+
+void vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
+{
+    switch (h->o.precision) {
+    case SMG_PREC_F64: run_vcycle<double, double>(h, r, s, nrhs, ld, st); break;
+    case SMG_PREC_F32: run_vcycle<float, float>(h, r, s, nrhs, ld, st); break;
+    default: run_vcycle<bf16, float>(h, r, s, nrhs, ld, st); break;
+    }
+}
+
+template <typename A>
+int upload_tables(smg_handle *h, const Tables &t, hipStream_t st)
+{
+    std::vector<PlaneCoef<A>> pc;
+    for (size_t l = 0; l < t.lev3.size(); ++l) {
+        const BlockTri &L = t.lev3[l];
+        for (int k = 0; k < L.n(); ++k) {
+            PlaneCoef<A> c{};
+            c.ca = static_cast<A>(L.da[k]);
+            c.cb = static_cast<A>(L.db[k]);
+            c.ua = k + 1 < L.n() ? static_cast<A>(L.oa[k]) : A(0);
+            c.ub = k + 1 < L.n() ? static_cast<A>(L.ob[k]) : A(0);
+            c.pt = t.ptype_of[l][k];
+            pc.push_back(c);
+        }
+    }
+    std::vector<LineCoef<A>> lc(t.line_fac.size());
+    for (size_t i = 0; i < lc.size(); ++i) {
+        lc[i].la = static_cast<A>(t.line_rows[4 * i + 0]);
+        lc[i].lb = static_cast<A>(t.line_rows[4 * i + 1]);
+        lc[i].va = static_cast<A>(t.line_rows[4 * i + 2]);
+        lc[i].vb = static_cast<A>(t.line_rows[4 * i + 3]);
+        lc[i].fac = t.line_fac[i];
+    }
+    // Thomas tables are built on the device from FP64 (la, lb) pairs.
+    std::vector<LineCoef<double>> uq(t.uniq.size());
+    for (size_t i = 0; i < uq.size(); ++i) {
+        uq[i] = LineCoef<double>{};
+        uq[i].la = t.uniq[i].first;
+        uq[i].lb = t.uniq[i].second;
+    }
+    if (hipMemcpyAsync(h->ws + h->L.pcoef, pc.data(), pc.size() * sizeof(pc[0]), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(h->ws + h->L.lcoef, lc.data(), lc.size() * sizeof(lc[0]), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(h->ws + h->L.uniq, uq.data(), uq.size() * sizeof(uq[0]), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        return SMG_EHIP;
+    launch_thomas_tables<A>(h->at<LineCoef<double>>(h->L.uniq), h->nfac, h->g.nx, h->nxp, h->at<Fac<A>>(h->L.fac),
+                            st);
+    if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) return SMG_EHIP;
+    return SMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov (Algorithm 1)
+// ---------------------------------------------------------------------------
+int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_opts *o, krylov_info *info,
+           void *stream)
+{
+    if (!h || !b || !x || !o) return SMG_EINVAL;
+    if (o->max_iter < 0 || !(o->rtol >= 0.0)) return SMG_EINVAL;
+    if (o->precond != SMG_PRECOND_SMG && o->precond != SMG_PRECOND_NONE) return SMG_EINVAL;
+    hipStream_t st = as_stream(stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    const smg_grid &g = h->g;
+    const size_t n = h->N;
+    double *r = h->at<double>(h->L.kr), *s = h->at<double>(h->L.ks), *q = h->at<double>(h->L.kq);
+    double *pa = h->at<double>(h->L.kp0), *pb = h->at<double>(h->L.kp1);
+    double *part = h->at<double>(h->L.part);
+    KScalars *sc = h->at<KScalars>(h->L.sc);
+    KScalars *hs = h->host_sc;
+    krylov_info inf{};
+    auto finish = [&](int status) {
+        inf.status = status;
+        inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) *info = inf;
+        return status;
+    };
+    auto sync = [&]() { return hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess; };
+
+    if (o->x0_zero) launch_fill(x, 0.0, n, st);
+    launch_init_resid(b, x, r, o->x0_zero ? 1 : 0, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+    launch_finalize(0, method, 0, part, sc, hs, st);
+    if (!sync()) return finish(SMG_EHIP);
+    if (!std::isfinite(hs->rr) || !std::isfinite(hs->bb)) return finish(SMG_ENONFINITE);
+    const double bnorm = std::sqrt(hs->bb);
+    const double bden = bnorm > 0.0 ? bnorm : 1.0;
+    double rel = std::sqrt(hs->rr) / bden;
+    if (o->history) o->history[0] = rel;
+    double c0 = 0.0;
+    int k = 0, status = SMG_NOT_CONVERGED;
+    for (; k < o->max_iter && rel > o->rtol; ++k) {
+        if (o->precond == SMG_PRECOND_SMG)
+            vcycle(h, r, s, 1, static_cast<long long>(n), st);
+        else
+            launch_copy(r, s, n, st);
+        launch_dots_sr_sq(s, r, q, method == 1 && k > 0, n, part, st);
+        launch_finalize(1, method, k, part, sc, nullptr, st);
+        launch_update_p_q(s, pa, pb, q, sc, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+        launch_finalize(2, method, k, part, sc, nullptr, st);
+        launch_update_xr(x, r, pb, q, sc, n, part, st);
+        launch_finalize(3, method, k, part, sc, hs, st);
+        if (!sync()) return finish(SMG_EHIP);
+        std::swap(pa, pb);
+        if (hs->breakdown) {
+            inf.iters = k;
+            status = SMG_EBREAKDOWN;
+            break;
+        }
+        if (k == 0) c0 = std::sqrt(std::fabs(hs->sr));
+        if (o->history_c) o->history_c[k] = c0 > 0.0 ? std::sqrt(std::fabs(hs->sr)) / c0 : 0.0;
+        rel = std::sqrt(hs->rr) / bden;
+        if (o->history) o->history[k + 1] = rel;
+        if (!std::isfinite(rel)) {
+            status = SMG_EBREAKDOWN;
+            ++k;
+            break;
+        }
+    }
+    if (status != SMG_EBREAKDOWN) {
+        inf.iters = k;
+        status = rel <= o->rtol ? SMG_OK : SMG_NOT_CONVERGED;
+    } else {
+        inf.iters = k;
+    }
+    inf.rel_res = rel;
+    launch_true_resid(b, x, s, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+    launch_finalize(0, method, 0, part, sc, hs, st);
+    if (!sync()) return finish(SMG_EHIP);
+    inf.true_rel_res = std::sqrt(hs->rr) / bden;
+    return finish(status);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int smg_workspace_bytes(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, size_t *bytes)
+{
+    if (check_grid(g, o) != SMG_OK || max_nrhs < 1 || !bytes) return SMG_EINVAL;
+    try {
+        const Tables t = build_tables(*g);
+        const int E = (g->nx + 63) / 64;
+        *bytes = make_layout(*g, *o, max_nrhs, t, 64 * E).total;
+    } catch (...) {
+        return SMG_EINVAL;
+    }
+    return SMG_OK;
+}
+
+int smg_setup(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, void *ws, size_t ws_bytes, void *stream,
+              smg_handle **out)
+{
+    if (!out) return SMG_EINVAL;
+    *out = nullptr;
+    if (check_grid(g, o) != SMG_OK || max_nrhs < 1 || !ws) return SMG_EINVAL;
+    smg_handle *h = nullptr;
+    try {
+        const Tables t = build_tables(*g);
+        h = new smg_handle();
+        h->g = *g;
+        h->o = *o;
+        h->ipre = o->inner_pre < 0 ? o->pre : o->inner_pre;
+        h->ipost = o->inner_post < 0 ? o->post : o->inner_post;
+        h->max_nrhs = max_nrhs;
+        h->N = static_cast<size_t>(g->nx) * g->ny * g->nz;
+        h->E = (g->nx + 63) / 64;
+        h->nxp = 64 * h->E;
+        h->nz = t.nz;
+        size_t acc = 0;
+        for (int v : t.nz) {
+            h->pc_off.push_back(acc);
+            acc += v;
+        }
+        h->ny2 = t.ny2;
+        h->lev2_off = t.lev2_off;
+        h->lines_total = t.lines_total;
+        h->nptypes = static_cast<int>(t.ptypes.size());
+        h->nfac = static_cast<int>(t.uniq.size());
+        h->P2 = (g->nz + 1) / 2;
+        h->elem = elem_size(o->precision);
+        h->L = make_layout(*g, *o, max_nrhs, t, h->nxp);
+        if (ws_bytes < h->L.total) {
+            delete h;
+            return SMG_EWORKSPACE;
+        }
+        h->ws = static_cast<char *>(ws);
+        h->prof = false;
+        h->ev_used = 0;
+        h->prof_bytes = 0;
+        if (hipHostMalloc(reinterpret_cast<void **>(&h->host_sc), sizeof(KScalars), hipHostMallocDefault) !=
+            hipSuccess) {
+            delete h;
+            return SMG_EHIP;
+        }
+        const int rc = arith_size(o->precision) == 8 ? upload_tables<double>(h, t, as_stream(stream))
+                                                      : upload_tables<float>(h, t, as_stream(stream));
+        if (rc != SMG_OK) {
+            (void)hipHostFree(h->host_sc);
+            delete h;
+            return rc;
+        }
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return SMG_EINVAL;
+    }
+    *out = h;
+    return SMG_OK;
+}
+
+int smg_apply(smg_handle *h, const double *r, double *s, int32_t nrhs, int64_t ld, void *stream)
+{
+    if (!h || !r || !s || nrhs < 1 || nrhs > h->max_nrhs || ld < static_cast<int64_t>(h->N)) return SMG_EINVAL;
+    vcycle(h, r, s, nrhs, ld, as_stream(stream));
+    return hipGetLastError() == hipSuccess ? SMG_OK : SMG_EHIP;
+}
+
+int smg_matvec(smg_handle *h, const double *x, double *y, int32_t nrhs, int64_t ld, void *stream)
+{
+    if (!h || !x || !y || nrhs < 1 || ld < static_cast<int64_t>(h->N) || nrhs > 65535) return SMG_EINVAL;
+    launch_matvec7(x, y, ld, nrhs, h->g.nx, h->g.ny, h->g.nz, h->g.cx, h->g.cy, h->g.cz, as_stream(stream));
+    return hipGetLastError() == hipSuccess ? SMG_OK : SMG_EHIP;
+}
+
+int pcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream)
+{
+    return krylov(h, 0, b, x, o, info, stream);
+}
+
+int fpcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream)
+{
+    return krylov(h, 1, b, x, o, info, stream);
+}
+
+int psd_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream)
+{
+    return krylov(h, 2, b, x, o, info, stream);
+}
+
+int smg_destroy(smg_handle *h)
+{
+    if (!h) return SMG_EINVAL;
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    if (h->host_sc) (void)hipHostFree(h->host_sc);
+    delete h;
+    return SMG_OK;
+}
+
+const char *smg_strerror(int status)
+{
+    switch (status) {
+    case SMG_OK: return "ok";
+    case SMG_NOT_CONVERGED: return "maximum number of iterations reached";
+    case SMG_EINVAL: return "invalid argument";
+    case SMG_EWORKSPACE: return "workspace too small";
+    case SMG_EHIP: return "HIP runtime error";
+    case SMG_EBREAKDOWN: return "breakdown: zero or non-finite denominator";
+    case SMG_ENONFINITE: return "non-finite input";
+    default: return "unknown status";
+    }
+}
+
+int smg_profile_line_relax(smg_handle *h, const double *r, double *s, int32_t reps, void *stream,
+                           int32_t *launches, double *kernel_ms, double *bytes)
+{
+    if (!h || !r || !s || reps < 1 || !launches || !kernel_ms || !bytes) return SMG_EINVAL;
+    hipStream_t st = as_stream(stream);
+    // count launches of one V-cycle first
+    h->prof = true;
+    h->ev_used = 0;
+    h->prof_bytes = 0;
+    if (h->ev.empty()) {
+        h->ev.resize(2 * 4096);
+        for (auto &e : h->ev)
+            if (hipEventCreate(&e) != hipSuccess) return SMG_EHIP;
+    }
+    double ms_total = 0.0, bytes_total = 0.0;
+    int per_cycle = 0;
+    for (int rep = 0; rep < reps; ++rep) {
+        h->ev_used = 0;
+        h->prof_bytes = 0;
+        vcycle(h, r, s, 1, static_cast<long long>(h->N), st);
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            h->prof = false;
+            return SMG_EHIP;
+        }
+        per_cycle = h->ev_used / 2;
+        for (int i = 0; i < h->ev_used; i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) != hipSuccess) {
+                h->prof = false;
+                return SMG_EHIP;
+            }
+            ms_total += ms;
+        }
+        bytes_total += h->prof_bytes;
+    }
+    h->prof = false;
+    *launches = per_cycle;
+    *kernel_ms = ms_total / reps;
+    *bytes = bytes_total / reps;
+    return SMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+// Internal declarations of the SMG library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/smg.h"
+
+namespace smg {
+
+// bfloat16 storage: the upper half of an IEEE binary32, rounded to nearest even.
+struct bf16 {
+    uint16_t bits;
+};
+
+__host__ __device__ inline float bf16_to_f(bf16 v)
+{
+    union { uint32_t u; float f; } c;
+    c.u = static_cast<uint32_t>(v.bits) << 16;
+    return c.f;
+}
+
+__host__ __device__ inline bf16 f_to_bf16(float f)
+{
+    union { uint32_t u; float f; } c;
+    c.f = f;
+    uint32_t u = c.u;
+    bf16 r;
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+        r.bits = static_cast<uint16_t>((u >> 16) | 0x40u);   // quiet NaN
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        r.bits = static_cast<uint16_t>(u >> 16);
+    }
+    return r;
+}
+
+template <typename T> struct Arith { using type = T; };
+template <> struct Arith<bf16> { using type = float; };
+
+__device__ inline double ldv(const double *p) { return *p; }
+__device__ inline float ldv(const float *p) { return *p; }
+__device__ inline float ldv(const bf16 *p) { return bf16_to_f(*p); }
+__device__ inline void stv(double *p, double v) { *p = v; }
+__device__ inline void stv(float *p, float v) { *p = v; }
+__device__ inline void stv(bf16 *p, float v) { *p = f_to_bf16(v); }
+
+// Coefficients of one x-line of a 2D level: L_j = la*Tx + lb*I, coupling to
+// line j+1 V_j = va*Tx + vb*I, Thomas table index fac.
+template <typename A>
+struct LineCoef {
+    A la, lb, va, vb;
+    int fac;
+    int pad;
+};
+
+// Coefficients of one plane of a 3D level: C_K = ca*T2 + cb*I, coupling to
+// plane K+1 U_K = ua*T2 + ub*I, plane type pt (index of its 2D hierarchy).
+template <typename A>
+struct PlaneCoef {
+    A ca, cb, ua, ub;
+    int pt;
+    int pad;
+};
+
+// Thomas factors of one line operator: y_i = g_i f_i + h_i y_{i-1};
+// u_i = y_i + h_i u_{i+1}; padded entries are zero.
+template <typename A>
+struct Fac {
+    A g, h;
+};
+
+struct Level3 {
+    int nz;
+    size_t n;          // nx*ny*nz points
+    size_t pcoef_off;  // offset of this level's PlaneCoef rows
+};
+
+// Kernel argument blocks --------------------------------------------------
+
+template <typename T, typename A>
+struct LineRelaxArgs {
+    T *x;                    // 2D x of this level
+    const T *b;              // 2D right-hand side
+    long long xps, xrs;      // plane and rhs strides of x
+    long long bps, brs;      // plane and rhs strides of b
+    int nx, ny;              // line length, lines in this 2D level
+    int colour, nq;          // lines j = 2q + colour (or j = q when ny == 1)
+    int np, nrhs;            // planes in the batch, right-hand sides
+    int kmul, koff;          // 3D plane of batch plane p: k = p*kmul + koff
+    const PlaneCoef<A> *pc;  // this 3D level's plane rows
+    const LineCoef<A> *lc;   // line rows of 2D level l of plane type 0
+    int lines_total;         // line rows per plane type
+    const Fac<A> *fac;       // Thomas tables
+    int nxp;                 // padded table length
+    int nbr_zero;            // neighbour lines are known to be zero
+};
+
+template <typename T, typename A>
+struct Restrict2Args {
+    const T *x; const T *b; T *bc;
+    long long xps, xrs, bps, brs, cps, crs;
+    int nx, ny, nyc, np, nrhs, kmul, koff;
+    const PlaneCoef<A> *pc;
+    const LineCoef<A> *lc;
+    int lines_total;
+    int x_zero;
+};
+
+template <typename T, typename A>
+struct Prolong2Args {
+    T *x; const T *xc;
+    long long xps, xrs, cps, crs;
+    int nx, ny, nyc, np, nrhs;
+    int x_zero;
+};
+
+template <typename T, typename A>
+struct Resid3Args {
+    const T *x; const T *b; T *r;      // r: packed batch planes
+    long long xrs, brs, rps, rrs;       // x and b: whole 3D level, packed planes
+    int nx, ny, nz, np, nrhs, kmul, koff;
+    A cx, cy;
+    const PlaneCoef<A> *pc;
+    int self_zero;
+};
+
+template <typename T, typename A>
+struct Correct3Args {
+    T *x; const T *y;
+    long long xrs, yps, yrs;
+    int nx, ny, np, nrhs, kmul, koff;
+};
+
+template <typename T, typename A>
+struct Restrict3Args {
+    const T *x; const T *b; T *bc;
+    long long xrs, brs, crs;
+    int nx, ny, nz, nzc, nrhs;
+    A cx, cy;
+    const PlaneCoef<A> *pc;
+    int x_zero;             // x is known to be zero: bc = P^T b
+};
+
+template <typename T, typename A>
+struct Prolong3Args {
+    T *x; const T *xc;
+    long long xrs, crs;
+    int nx, ny, nz, nzc, nrhs;
+    int x_zero;             // x is known to be zero: x = P xc
+};
+
+// Launchers (smg_kernels.hip) ---------------------------------------------
+template <typename T, typename A>
+void launch_line_relax(const LineRelaxArgs<T, A> &a, hipStream_t st);
+template <typename T, typename A>
+void launch_restrict2(const Restrict2Args<T, A> &a, hipStream_t st);
+template <typename T, typename A>
+void launch_prolong2(const Prolong2Args<T, A> &a, hipStream_t st);
+template <typename T, typename A>
+void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st);
+template <typename T, typename A>
+void launch_correct3(const Correct3Args<T, A> &a, hipStream_t st);
+template <typename T, typename A>
+void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st);
+template <typename T, typename A>
+void launch_prolong3(const Prolong3Args<T, A> &a, hipStream_t st);
+template <typename A>
+void launch_thomas_tables(const LineCoef<double> *uniq_ab, int nfac, int nx, int nxp, Fac<A> *out, hipStream_t st);
+template <typename T>
+void launch_convert_in(const double *src, long long lds, T *dst, long long ldd, size_t n, int nrhs, hipStream_t st);
+template <typename T>
+void launch_convert_out(const T *src, long long lds, double *dst, long long ldd, size_t n, int nrhs, hipStream_t st);
+
+// Krylov / vector kernels (krylov_kernels.hip) ----------------------------
+struct KScalars {           // device-resident recurrence scalars
+    double sr, sr_prev, sq, pq, alpha, alpha_prev, beta, rr, bb;
+    int breakdown;
+    int pad;
+};
+
+constexpr int kRedBlocks = 1024;   // fixed grid of the first reduction stage
+
+void launch_matvec7(const double *x, double *y, long long ld, int nrhs, int nx, int ny, int nz,
+                    double cx, double cy, double cz, hipStream_t st);
+void launch_init_resid(const double *b, const double *x, double *r, int x_zero, int nx, int ny, int nz,
+                       double cx, double cy, double cz, double *partials, hipStream_t st);
+void launch_dots_sr_sq(const double *s, const double *r, const double *q, int want_sq, size_t n,
+                       double *partials, hipStream_t st);
+void launch_update_p_q(const double *s, const double *p_old, double *p_new, double *q, const KScalars *sc,
+                       int nx, int ny, int nz, double cx, double cy, double cz, double *partials, hipStream_t st);
+void launch_update_xr(double *x, double *r, const double *p, const double *q, const KScalars *sc, size_t n,
+                      double *partials, hipStream_t st);
+// finalize: stage 2 of the reductions and the scalar recurrence.
+// which: 0 = init (rr, bb), 1 = beta (sr, sq), 2 = alpha (pq), 3 = rr
+void launch_finalize(int which, int method, int k, const double *partials, KScalars *sc, KScalars *host_copy,
+                     hipStream_t st);
+void launch_copy(const double *src, double *dst, size_t n, hipStream_t st);
+void launch_fill(double *dst, double v, size_t n, hipStream_t st);
+void launch_true_resid(const double *b, const double *x, double *tmp, int nx, int ny, int nz, double cx,
+                       double cy, double cz, double *partials, hipStream_t st);
+
+}  // namespace smg

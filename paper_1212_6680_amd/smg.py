@@ -1,0 +1,199 @@
+"""Python binding of libsmg.so (argument marshalling only).
+
+Every name mirrors an entry point of ``include/smg.h``.  PyTorch provides the
+device memory (the workspace and every vector are torch CUDA tensors) and the
+current stream; all computation runs in the library's HIP kernels.  There is
+no fallback: if the shared library is missing or fails to load, this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmg.so")
+
+SMG_OK, SMG_NOT_CONVERGED = 0, 1
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+PRECOND = {"smg": 0, "none": 1}
+
+
+class SMGError(RuntimeError):
+    pass
+
+
+class smg_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("cx", C.c_double), ("cy", C.c_double), ("cz", C.c_double)]
+
+
+class smg_opts(C.Structure):
+    _fields_ = [("pre", C.c_int32), ("post", C.c_int32), ("inner_pre", C.c_int32),
+                ("inner_post", C.c_int32), ("order", C.c_int32), ("precision", C.c_int32)]
+
+
+class krylov_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32),
+                ("x0_zero", C.c_int32), ("reserved", C.c_int32),
+                ("history", C.POINTER(C.c_double)), ("history_c", C.POINTER(C.c_double))]
+
+
+class krylov_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("solve_seconds", C.c_double)]
+
+
+class lobpcg_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32)]
+
+
+class lobpcg_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("nconv", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmg.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SMGError(f"{LIB_PATH} is not built; run paper_1212_6680_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.smg_workspace_bytes.argtypes = [C.POINTER(smg_grid), C.POINTER(smg_opts), i32, C.POINTER(C.c_size_t)]
+        L.smg_setup.argtypes = [C.POINTER(smg_grid), C.POINTER(smg_opts), i32, p, C.c_size_t, p,
+                                C.POINTER(p)]
+        L.smg_apply.argtypes = [p, p, p, i32, i64, p]
+        L.smg_matvec.argtypes = [p, p, p, i32, i64, p]
+        for f in (L.pcg_solve, L.fpcg_solve, L.psd_solve):
+            f.argtypes = [p, p, p, C.POINTER(krylov_opts), C.POINTER(krylov_info), p]
+        L.smg_destroy.argtypes = [p]
+        L.smg_strerror.argtypes = [C.c_int]
+        L.smg_strerror.restype = C.c_char_p
+        L.smg_profile_line_relax.argtypes = [p, p, p, i32, p, C.POINTER(i32), C.POINTER(d), C.POINTER(d)]
+        if hasattr(L, "lobpcg_solve"):
+            L.lobpcg_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
+            L.lobpcg_solve.argtypes = [p, i32, p, C.POINTER(d), C.POINTER(d), p, C.c_size_t,
+                                       C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().smg_strerror(code).decode()
+
+
+def _check(code: int, what: str, ok=(SMG_OK,)):
+    if code not in ok:
+        raise SMGError(f"{what}: {strerror(code)} ({code})")
+    return code
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t: torch.Tensor, n: int | None = None):
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise SMGError("expected a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() < n:
+        raise SMGError("tensor too small")
+    return C.c_void_p(t.data_ptr())
+
+
+class Info(dict):
+    __getattr__ = dict.__getitem__
+
+
+class SMG:
+    """One SMG hierarchy on the GPU for an (nx, ny, nz) brick with coefficients c."""
+
+    def __init__(self, shape, c=(1.0, 1.0, 1.0), pre=1, post=1, inner_pre=-1, inner_post=-1, order=0,
+                 precision="f64", max_nrhs=1, device="cuda"):
+        L = lib()
+        self.shape = tuple(int(v) for v in shape)
+        self.n = self.shape[0] * self.shape[1] * self.shape[2]
+        self.grid = smg_grid(*self.shape, *[float(v) for v in c])
+        self.opts = smg_opts(pre, post, inner_pre, inner_post, order, PREC[precision])
+        self.max_nrhs = int(max_nrhs)
+        nbytes = C.c_size_t(0)
+        _check(L.smg_workspace_bytes(C.byref(self.grid), C.byref(self.opts), self.max_nrhs,
+                                     C.byref(nbytes)), "smg_workspace_bytes")
+        self.ws_bytes = nbytes.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(L.smg_setup(C.byref(self.grid), C.byref(self.opts), self.max_nrhs,
+                           C.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream(), C.byref(h)),
+               "smg_setup")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.smg_destroy(h)
+            self.h = None
+
+    def _ld(self, t):
+        return self.n if t.dim() <= 1 else t.stride(0)
+
+    def apply(self, r: torch.Tensor, s: torch.Tensor | None = None) -> torch.Tensor:
+        """s = T r; r is (n,) or (nrhs, n) (one vector per row)."""
+        nrhs = 1 if r.dim() == 1 else r.shape[0]
+        if s is None:
+            s = torch.empty_like(r)
+        _check(lib().smg_apply(self.h, _dptr(r), _dptr(s), nrhs, self._ld(r), _stream()), "smg_apply")
+        return s
+
+    def matvec(self, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().smg_matvec(self.h, _dptr(x), _dptr(y), nrhs, self._ld(x), _stream()), "smg_matvec")
+        return y
+
+    def _solve(self, fn, b, x, rtol, max_iter, precond, history):
+        if x is None:
+            x = torch.zeros_like(b)
+            x0_zero = 1
+        else:
+            x0_zero = 0
+        hist = (C.c_double * (max_iter + 1))() if history else None
+        histc = (C.c_double * max(max_iter, 1))() if history else None
+        o = krylov_opts(rtol, max_iter, PRECOND[precond], x0_zero, 0,
+                        C.cast(hist, C.POINTER(C.c_double)) if history else None,
+                        C.cast(histc, C.POINTER(C.c_double)) if history else None)
+        info = krylov_info()
+        code = fn(self.h, _dptr(b, self.n), _dptr(x, self.n), C.byref(o), C.byref(info), _stream())
+        _check(code, fn.__name__, ok=(SMG_OK, SMG_NOT_CONVERGED))
+        out = Info(iters=info.iters, status=info.status, rel_res=info.rel_res,
+                   true_rel_res=info.true_rel_res, seconds=info.solve_seconds)
+        if history:
+            out["history"] = list(hist[:info.iters + 1])
+            out["history_c"] = list(histc[:info.iters])
+        return x, out
+
+    def pcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False):
+        """Algorithm 1 with beta from equation (1)."""
+        return self._solve(lib().pcg_solve, b, x, rtol, max_iter, precond, history)
+
+    def fpcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False):
+        """Algorithm 1 with beta from equation (2)."""
+        return self._solve(lib().fpcg_solve, b, x, rtol, max_iter, precond, history)
+
+    def psd(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False):
+        """Algorithm 1 with beta = 0."""
+        return self._solve(lib().psd_solve, b, x, rtol, max_iter, precond, history)
+
+    def profile_line_relax(self, r: torch.Tensor, reps: int = 3):
+        """(launches per V-cycle, kernel ms per V-cycle, algorithmic bytes per V-cycle)."""
+        s = torch.empty_like(r)
+        nl, ms, by = C.c_int32(0), C.c_double(0), C.c_double(0)
+        _check(lib().smg_profile_line_relax(self.h, _dptr(r), _dptr(s), reps, _stream(),
+                                            C.byref(nl), C.byref(ms), C.byref(by)), "smg_profile_line_relax")
+        return nl.value, ms.value, by.value

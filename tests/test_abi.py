@@ -1,0 +1,73 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/smg.h, and rejects invalid arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1212_6680_amd import smg as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.lib()
+    names = _declared()
+    assert {"smg_setup", "smg_apply", "pcg_solve", "fpcg_solve", "psd_solve"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _ws(grid, opts, nrhs=1):
+    n = C.c_size_t(0)
+    rc = S.lib().smg_workspace_bytes(C.byref(grid), C.byref(opts), nrhs, C.byref(n))
+    return rc, n.value
+
+
+def test_workspace_query_and_invalid_arguments():
+    g = S.smg_grid(32, 32, 32, 1.0, 1.0, 1.0)
+    o = S.smg_opts(1, 0, -1, -1, 0, 0)
+    rc, n = _ws(g, o)
+    assert rc == 0 and n > 5 * 32 ** 3 * 8
+    rc2, n2 = _ws(g, o, 4)
+    assert rc2 == 0 and n2 > n
+    # FP32 and BF16 hierarchies need less than FP64 for a big batch
+    rc3, n3 = _ws(g, S.smg_opts(1, 0, -1, -1, 0, 1), 16)
+    rc4, n4 = _ws(g, S.smg_opts(1, 0, -1, -1, 0, 2), 16)
+    rc5, n5 = _ws(g, o, 16)
+    assert rc3 == rc4 == rc5 == 0 and n4 < n3 < n5
+    for bad in [S.smg_grid(0, 4, 4, 1, 1, 1), S.smg_grid(4, -1, 4, 1, 1, 1), S.smg_grid(513, 4, 4, 1, 1, 1),
+                S.smg_grid(4, 4, 4, 0.0, 1, 1), S.smg_grid(4, 4, 4, 1, float("nan"), 1)]:
+        assert _ws(bad, o)[0] == -1
+    for bado in [S.smg_opts(-1, 0, -1, -1, 0, 0), S.smg_opts(1, 9, -1, -1, 0, 0),
+                 S.smg_opts(1, 0, -2, -1, 0, 0), S.smg_opts(1, 0, -1, -1, 2, 0), S.smg_opts(1, 0, -1, -1, 0, 3)]:
+        assert _ws(g, bado)[0] == -1
+    assert _ws(g, o, 0)[0] == -1
+
+
+def test_setup_rejects_small_workspace_before_touching_the_device():
+    g = S.smg_grid(16, 16, 16, 1.0, 1.0, 1.0)
+    o = S.smg_opts(1, 1, -1, -1, 0, 0)
+    rc, n = _ws(g, o)
+    h = C.c_void_p()
+    fake = C.c_void_p(0x1000)   # never dereferenced: the size check comes first
+    assert S.lib().smg_setup(C.byref(g), C.byref(o), 1, fake, n - 1, None, C.byref(h)) == -2
+    assert not h.value
+    assert S.lib().smg_setup(C.byref(g), C.byref(o), 1, None, n, None, C.byref(h)) == -1
+
+
+def test_strerror():
+    assert S.strerror(0) == "ok"
+    assert "workspace" in S.strerror(-2)
+    assert S.strerror(12345) == "unknown status"

@@ -1,0 +1,131 @@
+"""GPU parity of the SMG preconditioner and the 7-point operator against the FP64 oracle.
+
+Every case is called through the C ABI (the ctypes binding) on seeded inputs
+shared with the oracle.  Tolerance: the V-cycle is a fixed sequence of
+well-conditioned FP64 operations (line solves of diagonally dominant SPD
+tridiagonals, stencils with O(1) row sums relative to the diagonal); the GPU
+evaluates the Thomas recurrences as lane scans and the prolongation sums in
+another order, so results differ from the oracle by rounding only.  The bar
+is a max-norm error of 1e-12 relative to the max-norm of the result.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _smg(shape, c, pre, post, **kw):
+    from paper_1212_6680_amd.smg import SMG
+    return SMG(shape, c, pre, post, **kw)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+SHAPES = [(1, 1, 1), (1, 1, 9), (7, 1, 1), (1, 6, 1), (5, 4, 3), (8, 8, 8), (16, 16, 16),
+          (33, 17, 9), (65, 3, 5), (64, 64, 2), (130, 6, 7), (17, 40, 33), (32, 32, 32)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_matvec_parity(shape):
+    n = shape[0]
+    c = ((n + 1.0) ** 2, 1.7 * (shape[1] + 1) ** 2, 0.9 * (shape[2] + 1) ** 2)
+    x = synth.rhs(*shape, seed=11)
+    ref = O.matvec(x, shape, c)
+    G = _smg(shape, c, 1, 1)
+    y = G.matvec(_dev(x)).cpu().numpy()
+    assert _relerr(y, ref) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("pp", [(1, 1), (1, 0)])
+def test_vcycle_parity(shape, pp):
+    c = tuple((v + 1.0) ** 2 for v in shape)
+    r = synth.rhs(*shape, seed=21)
+    ref = O.SMG(shape, c, *pp).apply(r)
+    s = _smg(shape, c, *pp).apply(_dev(r)).cpu().numpy()
+    assert _relerr(s, ref) <= TOL
+
+
+@pytest.mark.parametrize("kw", [dict(pre=2, post=1), dict(pre=0, post=1), dict(pre=1, post=2),
+                                dict(pre=1, post=0, order=1), dict(pre=1, post=1, order=1),
+                                dict(pre=1, post=0, inner_pre=1, inner_post=1),
+                                dict(pre=1, post=1, inner_pre=2, inner_post=0),
+                                dict(pre=0, post=0)])
+def test_vcycle_knobs_parity(kw):
+    shape = (37, 20, 23)
+    c = (1.0, 2.0, 0.5)
+    pre, post = kw.pop("pre"), kw.pop("post")
+    ref = O.SMG(shape, c, pre, post, kw.get("inner_pre", -1), kw.get("inner_post", -1), kw.get("order", 0))
+    r = synth.rhs(*shape, seed=5)
+    s = _smg(shape, c, pre, post, **kw).apply(_dev(r)).cpu().numpy()
+    assert _relerr(s, ref.apply(r)) <= TOL
+
+
+def test_vcycle_max_line_length():
+    shape = (512, 3, 4)
+    c = (1.0, 1.0, 1.0)
+    r = synth.rhs(*shape, seed=8)
+    for pp in [(1, 1), (1, 0)]:
+        ref = O.SMG(shape, c, *pp).apply(r)
+        assert _relerr(_smg(shape, c, *pp).apply(_dev(r)).cpu().numpy(), ref) <= TOL
+
+
+def test_batched_rhs_equal_single_rhs_bitwise():
+    shape, c = (24, 20, 18), (1.0, 1.0, 1.0)
+    R = np.stack([synth.rhs(*shape, seed=100 + i) for i in range(5)])
+    G = _smg(shape, c, 1, 0, max_nrhs=5)
+    Sb = G.apply(_dev(R)).cpu().numpy()
+    for i in range(5):
+        si = G.apply(_dev(R[i])).cpu().numpy()
+        assert np.array_equal(Sb[i], si)
+    # and with a leading dimension larger than n
+    Rp = np.zeros((3, np.prod(shape) + 64))
+    Rp[:, :np.prod(shape)] = R[:3]
+    Sp = G.apply(_dev(Rp)).cpu().numpy()
+    assert np.array_equal(Sp[:, :np.prod(shape)], Sb[:3])
+
+
+def test_repeatable_bitwise():
+    shape, c = (40, 33, 29), (1.0, 1.0, 1.0)
+    G = _smg(shape, c, 1, 1)
+    r = _dev(synth.rhs(*shape, seed=3))
+    a = G.apply(r).cpu().numpy()
+    b = G.apply(r).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_gpu_balanced_symmetric_unbalanced_not():
+    n = 24
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    u, v = synth.rhs(n, n, n, 1), synth.rhs(n, n, n, 2)
+    for pp, sym in [((1, 1), True), ((1, 0), False)]:
+        G = _smg(shape, c, *pp)
+        uBv = u @ G.apply(_dev(v)).cpu().numpy()
+        vBu = v @ G.apply(_dev(u)).cpu().numpy()
+        if sym:
+            assert abs(uBv - vBu) <= 1e-12 * abs(uBv)
+        else:
+            assert abs(uBv - vBu) > 1e-3 * abs(uBv)
+
+
+@pytest.mark.parametrize("n", [256])
+def test_vcycle_parity_full_size(n):
+    """The benchmark's brick (256^3, c = 257^2, seed 2): one full V-cycle of each smoothing."""
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    r = synth.rhs(n, n, n, 2)
+    for pp in [(1, 0), (1, 1)]:
+        ref = O.SMG(shape, c, *pp).apply(r)
+        s = _smg(shape, c, *pp).apply(_dev(r)).cpu().numpy()
+        assert _relerr(s, ref) <= TOL
