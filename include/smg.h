@@ -81,6 +81,8 @@ typedef struct smg_opts {
     int32_t inner_pre, inner_post;  /* 2D plane-cycle counts; -1 inherits pre/post */
     int32_t order;                  /* 0: pre F then C (default); 1: pre C then F */
     int32_t precision;              /* SMG_PREC_* */
+    int32_t kernel_mode;            /* 0: fused schedule where it applies (default);
+                                       1: one launch per stage (reference schedule) */
 } smg_opts;
 
 typedef struct krylov_opts {
@@ -132,20 +134,73 @@ int pcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, k
 int fpcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream);
 int psd_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream);
 
+typedef struct lobpcg_opts {
+    double rtol;            /* per-column ||A x - theta x||_2 / (|theta| ||x||_2) target */
+    int32_t max_iter;       /* >= 0 */
+    int32_t precond;        /* SMG_PRECOND_SMG or SMG_PRECOND_NONE */
+    int32_t guard;          /* >= 0 extra block columns iterated but not required to
+                               converge; they keep near-degenerate eigenvalues just
+                               above the m-th from slowing the last wanted columns */
+    int32_t reserved;
+} lobpcg_opts;
+
+typedef struct lobpcg_info {
+    int32_t iters;          /* iterations (block updates) performed */
+    int32_t nconv;          /* columns meeting rtol at exit */
+    int32_t status;         /* same value as the return code */
+    int32_t reserved;
+    double seconds;         /* wall time, host clock */
+} lobpcg_info;
+
+/* Bytes of device workspace lobpcg_solve needs for block size mb (the wanted
+ * m plus the guard columns): six N x 3mb blocks (basis S = [X W P], A S and
+ * their scratch copies), three N x mb blocks and small Gram buffers.  Host-only. */
+int lobpcg_workspace_bytes(smg_handle *h, int32_t mb, size_t *bytes);
+
+/* LOBPCG (Section 4) for the m smallest eigenpairs of A, preconditioned by
+ * the handle's SMG V-cycle (requires max_nrhs >= m + guard at setup) or
+ * unpreconditioned.  The block holds mb = m + o->guard columns.
+ * X: device, mb columns of nx*ny*nz doubles (ld = nx*ny*nz), the initial
+ * block on entry (must have full column rank) and the orthonormal Ritz vectors
+ * on exit.  lambda: host[mb], Ritz values ascending.  resnorms: host[mb],
+ * nullable, final relative residuals.  ws: device workspace of ws_bytes bytes
+ * (>= lobpcg_workspace_bytes(h, mb)).  Method: Rayleigh-Ritz on span{X, T R, P}
+ * with Cholesky-QR orthonormalisation; converged columns stay in the basis
+ * but stop generating directions.  Returns SMG_OK when the first m columns
+ * meet rtol, SMG_NOT_CONVERGED at max_iter. */
+int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *resnorms, void *ws,
+                 size_t ws_bytes, const lobpcg_opts *o, lobpcg_info *info, void *stream);
+
 /* Releases the host-side handle (the caller's workspace is not freed). */
 int smg_destroy(smg_handle *h);
 
 /* Static message for a return code. */
 const char *smg_strerror(int status);
 
-/* Per-kernel timing of the most frequently launched SMG kernel family
- * (zebra x-line relaxation): runs `reps` V-cycles of nrhs = 1 on `r`/`s`,
- * timing every launch of that kernel with HIP events on `stream`, and
- * returns the launch count per V-cycle, the summed kernel milliseconds per
- * V-cycle and the algorithmic bytes per V-cycle of those launches (line
- * right-hand side, neighbour lines and result, once each). */
-int smg_profile_line_relax(smg_handle *h, const double *r, double *s, int32_t reps, void *stream,
-                           int32_t *launches, double *kernel_ms, double *bytes);
+/* Kernel families of one V-cycle, for smg_profile_kernel. */
+enum {
+    SMG_KERNEL_LINE_RELAX = 0,  /* zebra x-line relaxation, one colour of one 2D level */
+    SMG_KERNEL_RESTRICT2 = 1,   /* 2D residual + restriction */
+    SMG_KERNEL_PROLONG2 = 2,    /* 2D prolongation + correction */
+    SMG_KERNEL_RESID3 = 3,      /* 3D residual of one plane colour */
+    SMG_KERNEL_CORRECT3 = 4,    /* 3D correction x_k += y_k */
+    SMG_KERNEL_RESTRICT3 = 5,   /* 3D residual + restriction */
+    SMG_KERNEL_PROLONG3 = 6,    /* 3D prolongation + correction */
+    SMG_KERNEL_DOWN2 = 7,       /* fused pre-smoothing + residual + restriction of a 2D level */
+    SMG_KERNEL_COARSE2 = 8,     /* LDS-resident 2D sub-cycle on the small levels */
+    SMG_KERNEL_CHAIN2 = 9,      /* 2D prolongation chain + 3D correction */
+    SMG_KERNEL_UP2 = 10,        /* fused prolongation + post-smoothing of a 2D level */
+    SMG_KERNEL_CHAIN3 = 11,     /* 3D prolongation chain */
+    SMG_KERNEL_COUNT = 12
+};
+
+/* Measurement: runs `reps` single-vector V-cycles s = T r and times every
+ * launch of kernel family `family` with dispatch-stamped HIP events on
+ * `stream`.  Returns the launches per V-cycle, their summed duration in ms
+ * per V-cycle, and their algorithmic bytes per V-cycle (every value a launch
+ * must read or write, counted once).  s is overwritten. */
+int smg_profile_kernel(smg_handle *h, int32_t family, const double *r, double *s, int32_t reps, void *stream,
+                       int32_t *launches, double *kernel_ms, double *bytes);
 
 #ifdef __cplusplus
 }

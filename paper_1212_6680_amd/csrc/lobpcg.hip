@@ -1,0 +1,527 @@
+// LOBPCG (Section 4) on gfx950 with the SMG V-cycle as preconditioner.
+//
+// The locally optimal block preconditioned conjugate gradient method
+// (Knyazev 2001) for the m smallest eigenpairs.  Per iteration:
+//   R = A X - X diag(theta); active columns J have relative residual > rtol;
+//   W = T R_J (one batched SMG V-cycle over |J| right-hand sides);
+//   S = [X, W, P_J] with W and P columns scaled to unit length;
+//   S, A S <- Cholesky QR, twice (drop P, then fall back to an eigen-based
+//   orthonormalisation of S^T S when the Gram matrix is numerically singular);
+//   Rayleigh-Ritz on S^T A S; X = S C_m, P = S_{W,P} C_{W,P; m}.
+// The only dense contractions are the tall-skinny Gram products S^T Y and
+// the block updates S C, which run on FP64 MFMA (v_mfma_f64_16x16x4f64);
+// the k x k (k <= 3m) Cholesky and eigen-decompositions run on the host.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dense_host.hpp"
+#include "smg_internal.h"
+
+using namespace smg;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kT = 64;      // output tile edge of the MFMA kernels
+constexpr int kK = 16;      // reduction slice staged in LDS per step
+constexpr int kLdsPad = 4;  // LDS row padding (doubles)
+
+// Partial Gram products over a slice of rows:
+//   part[z][i][j] = sum_{n in slice z} U[n + i*ldu] * V[n + j*ldv],  i < p, j < q.
+// Block: 4 waves; tile 64(i) x 64(j); wave w owns rows i in [16w, 16w+16).
+// MFMA 16x16x4 f64 operand layout: A[i][k] from lane i + 16k, B[k][j] from
+// lane j + 16k, D[i][j] in lane j + 16*(i%4), element i/4.
+__global__ __launch_bounds__(256) void k_gram_partial(const double *U, long long ldu, int p, const double *V,
+                                                      long long ldv, int q, long long n, long long slice,
+                                                      double *part)
+{
+    __shared__ double Us[kK][kT + kLdsPad];
+    __shared__ double Vs[kK][kT + kLdsPad];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+    const long long n_beg = static_cast<long long>(blockIdx.z) * slice;
+    const long long n_end = n_beg + slice < n ? n_beg + slice : n;
+    v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    const int lc = tid >> 2;          // staging: column within the tile
+    const int lr = (tid & 3) * 4;     // staging: first of 4 rows
+    for (long long n0 = n_beg; n0 < n_end; n0 += kK) {
+        const int ci = i0 + lc, cj = j0 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long long nn = n0 + lr + r;
+            const bool in = nn < n_end;
+            Us[lr + r][lc] = (in && ci < p) ? U[nn + ci * ldu] : 0.0;
+            Vs[lr + r][lc] = (in && cj < q) ? V[nn + cj * ldv] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kK / 4; ++kk) {
+            const int kr = 4 * kk + (lane >> 4);
+            const double a = Us[kr][16 * w + (lane & 15)];
+#pragma unroll
+            for (int jt = 0; jt < 4; ++jt) {
+                const double b = Vs[kr][16 * jt + (lane & 15)];
+                acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    double *out = part + static_cast<long long>(blockIdx.z) * p * q;
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+        const int j = j0 + 16 * jt + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 16 * w + 4 * r + (lane >> 4);
+            if (i < p && j < q) out[static_cast<long long>(i) * q + j] = acc[jt][r];
+        }
+    }
+}
+
+// G[i][j] = sum_z part[z][i][j] in a fixed order (deterministic).
+__global__ void k_gram_reduce(const double *part, int nz, int pq, double *G)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pq) return;
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[static_cast<long long>(z) * pq + e];
+    G[e] = s;
+}
+
+// Y[n + j*ldy] = sum_{i<k} U[n + i*ldu] * C[i*mo + j]  for j < mo (C row-major k x mo).
+// Computed as the transposed tile Y^T = C^T U^T so that each MFMA output row
+// is a contiguous run of 16 n: wave w owns n in [16w, 16w+16) of the tile.
+__global__ __launch_bounds__(256) void k_block_update(const double *U, long long ldu, int k, const double *C, int mo,
+                                                      double *Y, long long ldy, long long n)
+{
+    __shared__ double Ut[kK][kT + kLdsPad];
+    __shared__ double Ct[kK][kT + kLdsPad];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const long long n0 = static_cast<long long>(blockIdx.x) * kT;
+    const int j0 = blockIdx.y * kT;
+    v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int i0 = 0; i0 < k; i0 += kK) {
+        // stage U[n0 .. n0+63][i0 .. i0+15] as Ut[i][n] and C[i0..][j0..j0+63] as Ct[i][j]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r;         // 0 .. 1023
+            const int ii = e >> 6, nn = e & 63;  // Ut: 16 x 64
+            const long long ng = n0 + nn;
+            Ut[ii][nn] = (i0 + ii < k && ng < n) ? U[ng + (i0 + ii) * ldu] : 0.0;
+            const int jj = e & 63;
+            Ct[ii][jj] = (i0 + ii < k && j0 + jj < mo) ? C[static_cast<long long>(i0 + ii) * mo + j0 + jj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kK / 4; ++kk) {
+            const int kr = 4 * kk + (lane >> 4);
+            const double b = Ut[kr][16 * w + (lane & 15)];
+#pragma unroll
+            for (int jt = 0; jt < 4; ++jt) {
+                const double a = Ct[kr][16 * jt + (lane & 15)];
+                acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    const long long nn = n0 + 16 * w + (lane & 15);
+    if (nn >= n) return;
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = j0 + 16 * jt + 4 * r + (lane >> 4);
+            if (j < mo) Y[nn + j * ldy] = acc[jt][r];
+        }
+    }
+}
+
+// R[:, c] = AX[:, c] - theta[c] X[:, c]
+__global__ void k_block_resid(const double *AX, const double *X, const double *theta, double *R, long long ld,
+                              long long n, int m)
+{
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (e >= n || c >= m) return;
+    R[e + c * ld] = AX[e + c * ld] - theta[c] * X[e + c * ld];
+}
+
+// part[c][z] = sum over slice z of U[:, c] .* V[:, c]
+__global__ __launch_bounds__(256) void k_coldot_partial(const double *U, const double *V, long long ld, long long n,
+                                                        long long slice, double *part, int nslices)
+{
+    __shared__ double lds[4];
+    const int c = blockIdx.y, z = blockIdx.x;
+    const long long beg = static_cast<long long>(z) * slice;
+    const long long end = beg + slice < n ? beg + slice : n;
+    double s = 0.0;
+    for (long long e = beg + threadIdx.x; e < end; e += blockDim.x) s += U[e + c * ld] * V[e + c * ld];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[c * nslices + z] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+__global__ void k_coldot_reduce(const double *part, int nslices, int m, double *out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    double s = 0.0;
+    for (int z = 0; z < nslices; ++z) s += part[c * nslices + z];
+    out[c] = s;
+}
+
+// X[:, c] *= 1/sqrt(nrm2[c]) (and the same for AX when given)
+__global__ void k_scale_cols(double *X, double *AX, const double *nrm2, long long ld, long long n, int m)
+{
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (e >= n || c >= m) return;
+    const double f = 1.0 / sqrt(nrm2[c]);
+    X[e + c * ld] *= f;
+    if (AX) AX[e + c * ld] *= f;
+}
+
+// dst[:, c] = src[:, idx[c]]
+__global__ void k_gather_cols(const double *src, double *dst, const int *idx, long long ld, long long n, int m)
+{
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (e >= n || c >= m) return;
+    dst[e + c * ld] = src[e + static_cast<long long>(idx[c]) * ld];
+}
+
+inline unsigned nblk(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+struct LobLayout {
+    size_t S, AS, T, AT, P, AP, R, part, G, C, theta, cpart, cout, idx, total;
+    int nslices_gram, nslices_col;
+};
+
+size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+LobLayout lob_layout(size_t N, int m)
+{
+    LobLayout L{};
+    const size_t k3 = 3 * static_cast<size_t>(m);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t r = off;
+        off = al(off + b);
+        return r;
+    };
+    L.S = take(N * k3 * 8);
+    L.AS = take(N * k3 * 8);
+    L.T = take(N * k3 * 8);
+    L.AT = take(N * k3 * 8);
+    L.P = take(N * m * 8);
+    L.AP = take(N * m * 8);
+    L.R = take(N * m * 8);
+    const int tiles = static_cast<int>(((k3 + kT - 1) / kT) * ((k3 + kT - 1) / kT));
+    long long ns = 4096 / tiles;
+    ns = ns < 64 ? 64 : ns;
+    const long long maxs = static_cast<long long>((N + 1023) / 1024);
+    if (ns > maxs) ns = maxs < 1 ? 1 : maxs;
+    L.nslices_gram = static_cast<int>(ns);
+    L.part = take(static_cast<size_t>(ns) * k3 * k3 * 8);
+    L.G = take(k3 * k3 * 8);
+    L.C = take(k3 * 2 * m * 8 + k3 * k3 * 8);
+    L.theta = take(k3 * 8);
+    L.nslices_col = static_cast<int>(std::min<long long>(256, (N + 4095) / 4096));
+    if (L.nslices_col < 1) L.nslices_col = 1;
+    L.cpart = take(k3 * L.nslices_col * 8 * 2);
+    L.cout = take(k3 * 8 * 2);
+    L.idx = take(k3 * 4);
+    L.total = off;
+    return L;
+}
+
+struct Lob {
+    smg_handle *h;
+    hipStream_t st;
+    size_t N;
+    int m;
+    char *ws;
+    LobLayout L;
+    template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
+
+    bool ok() { return hipGetLastError() == hipSuccess; }
+
+    // host G (p x q row-major) = U^T V
+    bool gram(const double *U, int p, const double *V, int q, std::vector<double> &G)
+    {
+        const long long slice = (static_cast<long long>(N) + L.nslices_gram - 1) / L.nslices_gram;
+        const long long sl = (slice + kK - 1) / kK * kK;
+        const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
+        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(p, kT), nblk(q, kT), nz), dim3(256), 0, st, U,
+                           static_cast<long long>(N), p, V, static_cast<long long>(N), q,
+                           static_cast<long long>(N), sl, at<double>(L.part));
+        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 256)), dim3(256), 0, st,
+                           at<double>(L.part), nz, p * q, at<double>(L.G));
+        G.resize(static_cast<size_t>(p) * q);
+        if (hipMemcpyAsync(G.data(), at<double>(L.G), G.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+            return false;
+        return hipStreamSynchronize(st) == hipSuccess && ok();
+    }
+
+    // Y (N x mo) = U (N x k) C (k x mo, host row-major)
+    bool update(const double *U, int k, const std::vector<double> &C, int mo, double *Y)
+    {
+        if (hipMemcpyAsync(at<double>(L.C), C.data(), C.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+            return false;
+        hipLaunchKernelGGL(k_block_update, dim3(nblk(static_cast<long long>(N), kT), nblk(mo, kT)), dim3(256), 0, st,
+                           U, static_cast<long long>(N), k, at<double>(L.C), mo, Y, static_cast<long long>(N),
+                           static_cast<long long>(N));
+        // C is reused by the next call: wait before the host buffer changes
+        return hipStreamSynchronize(st) == hipSuccess && ok();
+    }
+
+    // out[c] = (U[:, c], V[:, c]) for c < mcols (device out)
+    void coldots(const double *U, const double *V, int mcols, double *out, double *part)
+    {
+        const int ns = L.nslices_col;
+        const long long slice = (static_cast<long long>(N) + ns - 1) / ns;
+        hipLaunchKernelGGL(k_coldot_partial, dim3(ns, mcols), dim3(256), 0, st, U, V, static_cast<long long>(N),
+                           static_cast<long long>(N), slice, part, ns);
+        hipLaunchKernelGGL(k_coldot_reduce, dim3(nblk(mcols, 64)), dim3(64), 0, st, part, ns, mcols, out);
+    }
+
+    void normalize(double *X, double *AX, int mcols)
+    {
+        double *nrm = at<double>(L.cout);
+        coldots(X, X, mcols, nrm, at<double>(L.cpart));
+        hipLaunchKernelGGL(k_scale_cols, dim3(nblk(static_cast<long long>(N), 256), mcols), dim3(256), 0, st, X, AX,
+                           nrm, static_cast<long long>(N), static_cast<long long>(N), mcols);
+    }
+
+    bool gather(const double *src, double *dst, const std::vector<int> &idx)
+    {
+        if (idx.empty()) return true;
+        if (hipMemcpyAsync(at<int>(L.idx), idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+            return false;
+        hipLaunchKernelGGL(k_gather_cols, dim3(nblk(static_cast<long long>(N), 256), static_cast<int>(idx.size())),
+                           dim3(256), 0, st, src, dst, at<int>(L.idx), static_cast<long long>(N),
+                           static_cast<long long>(N), static_cast<int>(idx.size()));
+        return hipStreamSynchronize(st) == hipSuccess && ok();
+    }
+
+    // Cholesky QR twice of S (N x k) with A S alike; S/AS and the scratch T/AT
+    // swap roles, so after two passes the result is back in S/AS.
+    int cholqr2(double *&S, double *&AS, double *&T, double *&AT, int k)
+    {
+        std::vector<double> G, Ct(static_cast<size_t>(k) * k);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (!gram(S, k, S, k, G)) return -1;
+            for (int i = 0; i < k; ++i)
+                for (int j = 0; j < i; ++j) G[i * k + j] = G[j * k + i] = 0.5 * (G[i * k + j] + G[j * k + i]);
+            if (!dense::cholesky(k, G.data())) return 0;
+            dense::inv_lower_transpose(k, G.data(), Ct.data());
+            if (!update(S, k, Ct, k, T) || !update(AS, k, Ct, k, AT)) return -1;
+            std::swap(S, T);
+            std::swap(AS, AT);
+        }
+        return 1;
+    }
+
+    // eigen-based orthonormalisation of S (N x k); returns the kept count
+    int svqb(double *&S, double *&AS, double *&T, double *&AT, int k)
+    {
+        std::vector<double> G;
+        if (!gram(S, k, S, k, G)) return -1;
+        std::vector<double> dinv(k), Gs(static_cast<size_t>(k) * k), V(static_cast<size_t>(k) * k), w(k);
+        for (int i = 0; i < k; ++i) {
+            const double d = std::sqrt(std::fabs(G[i * k + i]));
+            dinv[i] = d > 0 ? 1.0 / d : 1.0;
+        }
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j)
+                Gs[i * k + j] = 0.5 * (G[i * k + j] + G[j * k + i]) * dinv[i] * dinv[j];
+        if (!dense::sym_eig(k, Gs.data(), V.data(), w.data())) return -1;
+        const double wmax = w[k - 1];
+        std::vector<int> keep;
+        for (int j = 0; j < k; ++j)
+            if (w[j] > 1e-12 * wmax) keep.push_back(j);
+        const int kk = static_cast<int>(keep.size());
+        std::vector<double> Cm(static_cast<size_t>(k) * kk);
+        for (int i = 0; i < k; ++i)
+            for (int jj = 0; jj < kk; ++jj)
+                Cm[i * kk + jj] = dinv[i] * V[i * k + keep[jj]] / std::sqrt(w[keep[jj]]);
+        if (!update(S, k, Cm, kk, T) || !update(AS, k, Cm, kk, AT)) return -1;
+        std::swap(S, T);
+        std::swap(AS, AT);
+        return kk;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int lobpcg_workspace_bytes(smg_handle *h, int32_t m, size_t *bytes)
+{
+    if (!h || m < 1 || !bytes) return SMG_EINVAL;
+    size_t N = 0;
+    if (smg_handle_size(h, &N) != SMG_OK) return SMG_EINVAL;
+    *bytes = lob_layout(N, m).total;
+    return SMG_OK;
+}
+
+int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *resnorms, void *ws, size_t ws_bytes,
+                 const lobpcg_opts *o, lobpcg_info *info, void *stream)
+{
+    if (!h || !X || !lambda || !ws || !o || m < 1 || o->max_iter < 0 || !(o->rtol >= 0.0)) return SMG_EINVAL;
+    if (o->precond != SMG_PRECOND_SMG && o->precond != SMG_PRECOND_NONE) return SMG_EINVAL;
+    if (o->guard < 0) return SMG_EINVAL;
+    const int mw = m;     // wanted pairs; the block also carries the guard columns
+    m += o->guard;
+    size_t N = 0;
+    int32_t max_nrhs = 0;
+    if (smg_handle_size(h, &N) != SMG_OK || smg_handle_max_nrhs(h, &max_nrhs) != SMG_OK) return SMG_EINVAL;
+    if (o->precond == SMG_PRECOND_SMG && max_nrhs < m) return SMG_EINVAL;
+    if (static_cast<size_t>(m) > N) return SMG_EINVAL;
+    const auto t0 = std::chrono::steady_clock::now();
+    Lob lb{h, reinterpret_cast<hipStream_t>(stream), N, m, static_cast<char *>(ws), lob_layout(N, m)};
+    if (ws_bytes < lb.L.total) return SMG_EWORKSPACE;
+    hipStream_t st = lb.st;
+    lobpcg_info inf{};
+    auto finish = [&](int status) {
+        inf.status = status;
+        inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) *info = inf;
+        return status;
+    };
+    const long long ld = static_cast<long long>(N);
+    double *S = lb.at<double>(lb.L.S), *AS = lb.at<double>(lb.L.AS);
+    double *T = lb.at<double>(lb.L.T), *AT = lb.at<double>(lb.L.AT);
+    double *P = lb.at<double>(lb.L.P), *AP = lb.at<double>(lb.L.AP), *R = lb.at<double>(lb.L.R);
+    double *theta_d = lb.at<double>(lb.L.theta);
+
+    if (hipMemcpyAsync(S, X, N * m * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return finish(SMG_EHIP);
+    if (smg_matvec(h, S, AS, m, ld, stream) != SMG_OK) return finish(SMG_EHIP);
+    {
+        int rc = lb.cholqr2(S, AS, T, AT, m);
+        if (rc < 0) return finish(SMG_EHIP);
+        if (rc == 0) {
+            const int kk = lb.svqb(S, AS, T, AT, m);
+            if (kk < 0) return finish(SMG_EHIP);
+            if (kk < m) return finish(SMG_EBREAKDOWN);   // initial block is rank deficient
+        }
+    }
+    std::vector<double> G, V, w, theta(m);
+    // initial Rayleigh-Ritz on span(X)
+    if (!lb.gram(S, m, AS, m, G)) return finish(SMG_EHIP);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < i; ++j) G[i * m + j] = G[j * m + i] = 0.5 * (G[i * m + j] + G[j * m + i]);
+    V.resize(static_cast<size_t>(m) * m);
+    w.resize(m);
+    if (!dense::sym_eig(m, G.data(), V.data(), w.data())) return finish(SMG_EBREAKDOWN);
+    if (!lb.update(S, m, V, m, T) || !lb.update(AS, m, V, m, AT)) return finish(SMG_EHIP);
+    std::swap(S, T);
+    std::swap(AS, AT);
+    for (int i = 0; i < m; ++i) theta[i] = w[i];
+
+    bool have_p = false;
+    std::vector<double> rr(m), xx(m), res(m);
+    std::vector<int> active, all(m);
+    for (int i = 0; i < m; ++i) all[i] = i;
+    int it = 0;
+    int status = SMG_NOT_CONVERGED;
+    for (;; ++it) {
+        // residuals and their relative norms
+        if (hipMemcpyAsync(theta_d, theta.data(), m * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+            return finish(SMG_EHIP);
+        hipLaunchKernelGGL(k_block_resid, dim3(nblk(ld, 256), m), dim3(256), 0, st, AS, S, theta_d, R, ld, ld, m);
+        double *cout = lb.at<double>(lb.L.cout);
+        lb.coldots(R, R, m, cout, lb.at<double>(lb.L.cpart));
+        lb.coldots(S, S, m, cout + m, lb.at<double>(lb.L.cpart) + static_cast<size_t>(m) * lb.L.nslices_col);
+        std::vector<double> nr(2 * m);
+        if (hipMemcpyAsync(nr.data(), cout, 2 * m * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess || !lb.ok())
+            return finish(SMG_EHIP);
+        active.clear();
+        int wanted_left = 0;
+        for (int i = 0; i < m; ++i) {
+            res[i] = std::sqrt(nr[i]) / (std::fabs(theta[i]) * std::sqrt(nr[m + i]));
+            if (!std::isfinite(res[i])) return finish(SMG_EBREAKDOWN);
+            if (res[i] > o->rtol) {
+                active.push_back(i);
+                if (i < mw) ++wanted_left;
+            }
+        }
+        inf.nconv = mw - wanted_left;
+        if (wanted_left == 0) {
+            status = SMG_OK;
+            break;
+        }
+        if (it >= o->max_iter) break;
+        const int nj = static_cast<int>(active.size());
+        // W = T R_J into S[:, m : m+nj]
+        double *W = S + static_cast<size_t>(m) * N, *AW = AS + static_cast<size_t>(m) * N;
+        if (!lb.gather(R, T, active)) return finish(SMG_EHIP);
+        if (o->precond == SMG_PRECOND_SMG) {
+            if (smg_apply(h, T, W, nj, ld, stream) != SMG_OK) return finish(SMG_EHIP);
+        } else if (hipMemcpyAsync(W, T, N * nj * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+            return finish(SMG_EHIP);
+        }
+        lb.normalize(W, nullptr, nj);
+        if (smg_matvec(h, W, AW, nj, ld, stream) != SMG_OK) return finish(SMG_EHIP);
+        int k = m + nj;
+        if (have_p) {
+            double *Pj = S + static_cast<size_t>(k) * N, *APj = AS + static_cast<size_t>(k) * N;
+            if (!lb.gather(P, Pj, active) || !lb.gather(AP, APj, active)) return finish(SMG_EHIP);
+            lb.normalize(Pj, APj, nj);
+            k += nj;
+        }
+        int rc = lb.cholqr2(S, AS, T, AT, k);
+        if (rc < 0) return finish(SMG_EHIP);
+        if (rc == 0 && have_p) {
+            k = m + nj;
+            rc = lb.cholqr2(S, AS, T, AT, k);
+            if (rc < 0) return finish(SMG_EHIP);
+        }
+        if (rc == 0) {
+            k = lb.svqb(S, AS, T, AT, k);
+            if (k < 0) return finish(SMG_EHIP);
+            if (k < m) return finish(SMG_EBREAKDOWN);
+        }
+        // Rayleigh-Ritz on S^T A S
+        if (!lb.gram(S, k, AS, k, G)) return finish(SMG_EHIP);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < i; ++j) G[i * k + j] = G[j * k + i] = 0.5 * (G[i * k + j] + G[j * k + i]);
+        V.resize(static_cast<size_t>(k) * k);
+        w.resize(k);
+        if (!dense::sym_eig(k, G.data(), V.data(), w.data())) return finish(SMG_EBREAKDOWN);
+        for (int i = 0; i < m; ++i) theta[i] = w[i];
+        // [X_new | P_new] = S [C_m | C_m with the X rows zeroed]
+        std::vector<double> Ce(static_cast<size_t>(k) * 2 * m, 0.0);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < m; ++j) {
+                Ce[static_cast<size_t>(i) * 2 * m + j] = V[static_cast<size_t>(i) * k + j];
+                if (i >= m) Ce[static_cast<size_t>(i) * 2 * m + m + j] = V[static_cast<size_t>(i) * k + j];
+            }
+        if (!lb.update(S, k, Ce, 2 * m, T) || !lb.update(AS, k, Ce, 2 * m, AT)) return finish(SMG_EHIP);
+        std::swap(S, T);
+        std::swap(AS, AT);
+        if (hipMemcpyAsync(P, S + static_cast<size_t>(m) * N, N * m * 8, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(AP, AS + static_cast<size_t>(m) * N, N * m * 8, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+            return finish(SMG_EHIP);
+        have_p = true;
+    }
+    if (hipMemcpyAsync(X, S, N * m * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return finish(SMG_EHIP);
+    for (int i = 0; i < m; ++i) {
+        lambda[i] = theta[i];
+        if (resnorms) resnorms[i] = res[i];
+    }
+    inf.iters = it;
+    return finish(status);
+}
+
+}  // extern "C"

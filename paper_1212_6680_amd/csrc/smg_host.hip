@@ -77,7 +77,7 @@ BlockTri galerkin(const BlockTri &f)
 struct Layout {
     size_t pcoef, lcoef, uniq, fac;        // tables
     std::vector<size_t> xl, bl;             // 3D levels >= 1
-    std::vector<size_t> x2, b2;             // 2D batch buffers per 2D level
+    std::vector<size_t> x2, b2, y2;         // 2D batch buffers per 2D level
     size_t rlo, slo;                        // low-precision level-0 in/out
     size_t kr, ks, kp0, kp1, kq, part, sc;  // Krylov
     size_t total;
@@ -99,11 +99,18 @@ struct smg_handle {
     int lines_total;
     int nptypes, nfac, P2;
     size_t elem;                  // bytes per stored value
+    // fused schedule: first LDS-resident 2D level, its LDS bytes, strip sizes
+    bool fused;
+    int l0;
+    size_t coarse_lds;
+    int S_down, S_up;
     char *ws;
     Layout L;
     KScalars *host_sc;            // pinned host mirror of the device scalars
-    // profiling of the line-relax kernel family
+    // per-kernel profiling: launches of family prof_family get dispatch-stamped
+    // events and their algorithmic bytes are summed
     bool prof;
+    int prof_family;
     std::vector<hipEvent_t> ev;
     int ev_used;
     double prof_bytes;
@@ -123,11 +130,38 @@ int check_grid(const smg_grid *g, const smg_opts *o)
         return SMG_EINVAL;
     if (o->order != 0 && o->order != 1) return SMG_EINVAL;
     if (o->precision < SMG_PREC_F64 || o->precision > SMG_PREC_BF16) return SMG_EINVAL;
+    if (o->kernel_mode != 0 && o->kernel_mode != 1) return SMG_EINVAL;
     return SMG_OK;
 }
 
 size_t elem_size(int prec) { return prec == SMG_PREC_F64 ? 8 : prec == SMG_PREC_F32 ? 4 : 2; }
 size_t arith_size(int prec) { return prec == SMG_PREC_F64 ? 8 : 4; }
+
+// LDS budgets of the fused kernels (bytes per workgroup)
+constexpr size_t kCoarseLds = 64 * 1024;
+constexpr size_t kStripLds = 48 * 1024;
+
+void choose_fused_schedule(smg_handle *h)
+{
+    const size_t line = static_cast<size_t>(h->nxp) * arith_size(h->o.precision);
+    const int nl = static_cast<int>(h->ny2.size());
+    h->l0 = nl - 1;
+    h->coarse_lds = 0;
+    for (int l = nl - 1; l >= 0; --l) {
+        size_t lines = 0;
+        for (int m = l; m < nl; ++m) lines += h->ny2[m];
+        const size_t bytes = 2 * lines * line;
+        if (bytes > kCoarseLds) break;
+        h->l0 = l;
+        h->coarse_lds = bytes;
+    }
+    int S = static_cast<int>((kStripLds / line - 5) / 2);
+    h->S_down = S < 1 ? 1 : (S > 16 ? 16 : S);
+    S = static_cast<int>((kStripLds / line - 4) / 2);
+    h->S_up = S < 1 ? 1 : (S > 16 ? 16 : S);
+    h->fused = h->o.kernel_mode == 0 && nl <= kMaxLev && h->nz.size() <= static_cast<size_t>(kMaxLev3) &&
+               h->coarse_lds > 0;
+}
 
 // Table sizes need the dedup counts, which depend only on the grid; the
 // host part of the setup is cheap, so sizing runs it too.
@@ -245,6 +279,7 @@ Layout make_layout(const smg_grid &g, const smg_opts &o, int max_nrhs, const Tab
         const size_t sz = static_cast<size_t>(max_nrhs) * P2 * g.nx * t.ny2[l] * es;
         L.x2.push_back(take(sz));
         L.b2.push_back(take(sz));
+        L.y2.push_back(take(sz));
     }
     if (o.precision != SMG_PREC_F64) {
         L.rlo = take(static_cast<size_t>(max_nrhs) * N * es);
@@ -294,6 +329,25 @@ struct VCycle {
     long long ps2(int l2) const { return static_cast<long long>(h->g.nx) * h->ny2[l2]; }
     long long rs2(int l2) const { return static_cast<long long>(h->P2) * ps2(l2); }
 
+    // Events for this launch when its family is being profiled; `values` is the
+    // launch's algorithmic traffic in stored values (each read or written once).
+    LaunchEv ev_for(int family, double values)
+    {
+        if (!h->prof || family != h->prof_family || h->ev_used + 2 > static_cast<int>(h->ev.size()))
+            return LaunchEv{};
+        LaunchEv e{h->ev[h->ev_used], h->ev[h->ev_used + 1]};
+        h->ev_used += 2;
+        h->prof_bytes += values * sizeof(T);
+        return e;
+    }
+
+    // colour residual: b and the result on the colour's planes, the other
+    // colour's planes once, and the own planes unless they are still zero
+    double resid3_values(int nz, int np, bool self_zero) const
+    {
+        return (2.0 * np + (nz - np) + (self_zero ? 0.0 : np)) * pl() * nrhs;
+    }
+
     void line_relax(const Batch &bt, int l2, T *x, long long xps, long long xrs, const T *b, long long bps,
                     long long brs, int colour, int nbr_zero)
     {
@@ -311,18 +365,8 @@ struct VCycle {
         a.fac = h->at<Fac<A>>(h->L.fac);
         a.nxp = h->nxp;
         a.nbr_zero = nbr_zero || a.ny == 1;
-        int slot = -1;
-        if (h->prof && h->ev_used + 2 <= static_cast<int>(h->ev.size())) {
-            slot = h->ev_used;
-            h->ev_used += 2;
-            (void)hipEventRecord(h->ev[slot], st);
-        }
-        launch_line_relax<T, A>(a, st);
-        if (slot >= 0) {
-            (void)hipEventRecord(h->ev[slot + 1], st);
-            const double lines = a.nbr_zero ? 2.0 * a.nq : static_cast<double>(a.nq + a.ny);
-            h->prof_bytes += lines * a.nx * sizeof(T) * a.np * a.nrhs;
-        }
+        const double lines = a.nbr_zero ? 2.0 * a.nq : static_cast<double>(a.nq + a.ny);
+        launch_line_relax<T, A>(a, st, ev_for(SMG_KERNEL_LINE_RELAX, lines * a.nx * a.np * a.nrhs));
     }
 
     void v2(const Batch &bt, int l2)
@@ -350,23 +394,114 @@ struct VCycle {
         ra.np = bt.np; ra.nrhs = nrhs; ra.kmul = bt.kmul; ra.koff = bt.koff;
         ra.pc = bt.pc; ra.lc = LC(l2); ra.lines_total = h->lines_total;
         ra.x_zero = x_zero;
-        launch_restrict2<T, A>(ra, st);
+        launch_restrict2<T, A>(ra, st, ev_for(SMG_KERNEL_RESTRICT2,
+                                             (x_zero ? 1.0 : 2.0) * ny * h->g.nx * bt.np * nrhs +
+                                                 1.0 * ra.nyc * h->g.nx * bt.np * nrhs));
         v2(bt, l2 + 1);
         Prolong2Args<T, A> pa{};
         pa.x = x; pa.xc = h->at<T>(h->L.x2[l2 + 1]);
         pa.xps = xps; pa.xrs = xrs; pa.cps = ps2(l2 + 1); pa.crs = rs2(l2 + 1);
         pa.nx = h->g.nx; pa.ny = ny; pa.nyc = h->ny2[l2 + 1];
         pa.np = bt.np; pa.nrhs = nrhs; pa.x_zero = x_zero;
-        launch_prolong2<T, A>(pa, st);
+        launch_prolong2<T, A>(pa, st, ev_for(SMG_KERNEL_PROLONG2,
+                                            ((x_zero ? 1.0 : 2.0) * ny + pa.nyc) * h->g.nx * bt.np * nrhs));
         for (int s = 0; s < h->ipost; ++s) {
             line_relax(bt, l2, x, xps, xrs, b, bps, brs, second, 0);
             line_relax(bt, l2, x, xps, xrs, b, bps, brs, first, 0);
         }
     }
 
+    bool fused2() const { return h->fused && h->o.order == 0 && h->ipre == 1 && h->ipost <= 1; }
+    bool chain3() const { return h->fused && h->o.post == 0 && h->o.pre >= 1; }
+
+    // One batched 2D cycle on the fused schedule; the result is written to
+    // out (plane stride ops, rhs stride ors), assigned or accumulated.
+    void v2_fused(const Batch &bt, T *out, long long ops, long long ors, bool accumulate)
+    {
+        const int l0 = h->l0, nl = static_cast<int>(h->ny2.size());
+        const int nx = h->g.nx;
+        // where x_0 after pre-smoothing goes: in place in out when nothing is
+        // accumulated and no post-smoothing reads it back across strips
+        const bool in_place = h->ipost == 0 && !accumulate;
+        T *x0pre = in_place ? out : h->at<T>(h->L.x2[0]);
+        const long long x0ps = in_place ? ops : ps2(0), x0rs = in_place ? ors : rs2(0);
+        auto Bp = [&](int l) { return l == 0 ? bt.b : h->at<T>(h->L.b2[l]); };
+        auto Bps = [&](int l) { return l == 0 ? bt.bps : ps2(l); };
+        auto Brs = [&](int l) { return l == 0 ? bt.brs : rs2(l); };
+        for (int l = 0; l < l0; ++l) {
+            Down2Args<T, A> d{};
+            d.b = Bp(l); d.bps = Bps(l); d.brs = Brs(l);
+            d.x = l == 0 ? x0pre : h->at<T>(h->L.x2[l]);
+            d.xps = l == 0 ? x0ps : ps2(l); d.xrs = l == 0 ? x0rs : rs2(l);
+            d.bc = h->at<T>(h->L.b2[l + 1]); d.cps = ps2(l + 1); d.crs = rs2(l + 1);
+            d.nx = nx; d.nxp = h->nxp; d.ny = h->ny2[l]; d.nyc = h->ny2[l + 1]; d.S = h->S_down;
+            d.np = bt.np; d.nrhs = nrhs; d.kmul = bt.kmul; d.koff = bt.koff;
+            d.pc = bt.pc; d.lc = LC(l); d.lines_total = h->lines_total; d.fac = h->at<Fac<A>>(h->L.fac);
+            launch_down2<T, A>(d, st, ev_for(SMG_KERNEL_DOWN2,
+                                             (2.0 * d.ny + d.nyc) * nx * bt.np * static_cast<double>(nrhs)));
+        }
+        Coarse2Args<T, A> c{};
+        c.b = Bp(l0); c.bps = Bps(l0); c.brs = Brs(l0);
+        if (l0 == 0) {
+            c.out = out; c.ops = ops; c.ors = ors; c.accumulate = accumulate;
+        } else {
+            c.out = h->at<T>(h->L.x2[l0]); c.ops = ps2(l0); c.ors = rs2(l0); c.accumulate = 0;
+        }
+        c.nx = nx; c.nxp = h->nxp; c.np = bt.np; c.nrhs = nrhs; c.kmul = bt.kmul; c.koff = bt.koff;
+        c.l0 = l0; c.nlev = nl;
+        for (int l = 0; l < nl; ++l) {
+            c.ny2[l] = h->ny2[l];
+            c.lev_off[l] = h->lev2_off[l];
+        }
+        c.ipre = h->ipre; c.ipost = h->ipost;
+        c.pc = bt.pc; c.lc = LC(0); c.lines_total = h->lines_total; c.fac = h->at<Fac<A>>(h->L.fac);
+        launch_coarse2<T, A>(c, h->coarse_lds, st,
+                             ev_for(SMG_KERNEL_COARSE2, (2.0 + c.accumulate) * h->ny2[l0] * nx * bt.np *
+                                                            static_cast<double>(nrhs)));
+        if (l0 == 0) return;
+        if (h->ipost == 0) {
+            Chain2Args<T, A> ch{};
+            ch.x0 = x0pre; ch.x0ps = x0ps; ch.x0rs = x0rs;
+            ch.out = out; ch.ops = ops; ch.ors = ors; ch.accumulate = accumulate;
+            for (int l = 1; l <= l0; ++l) {
+                ch.xc[l] = h->at<T>(h->L.x2[l]);
+                ch.cps[l] = ps2(l);
+                ch.crs[l] = rs2(l);
+            }
+            for (int l = 0; l <= l0; ++l) ch.ny2[l] = h->ny2[l];
+            ch.nx = nx; ch.np = bt.np; ch.nrhs = nrhs; ch.lc = l0;
+            double lines = (2.0 + accumulate) * h->ny2[0];
+            for (int l = 1; l <= l0; ++l) lines += h->ny2[l];
+            launch_chain2<T, A>(ch, st, ev_for(SMG_KERNEL_CHAIN2, lines * nx * bt.np * static_cast<double>(nrhs)));
+            return;
+        }
+        for (int l = l0 - 1; l >= 0; --l) {
+            Up2Args<T, A> u{};
+            u.xpre = l == 0 ? x0pre : h->at<T>(h->L.x2[l]);
+            u.xps = l == 0 ? x0ps : ps2(l); u.xrs = l == 0 ? x0rs : rs2(l);
+            u.xc = l + 1 == l0 ? h->at<T>(h->L.x2[l0]) : h->at<T>(h->L.y2[l + 1]);
+            u.cps = ps2(l + 1); u.crs = rs2(l + 1);
+            u.b = Bp(l); u.bps = Bps(l); u.brs = Brs(l);
+            if (l == 0) {
+                u.out = out; u.ops = ops; u.ors = ors; u.accumulate = accumulate;
+            } else {
+                u.out = h->at<T>(h->L.y2[l]); u.ops = ps2(l); u.ors = rs2(l); u.accumulate = 0;
+            }
+            u.nx = nx; u.nxp = h->nxp; u.ny = h->ny2[l]; u.nyc = h->ny2[l + 1]; u.S = h->S_up;
+            u.np = bt.np; u.nrhs = nrhs; u.kmul = bt.kmul; u.koff = bt.koff;
+            u.pc = bt.pc; u.lc = LC(l); u.lines_total = h->lines_total; u.fac = h->at<Fac<A>>(h->L.fac);
+            launch_up2<T, A>(u, st, ev_for(SMG_KERNEL_UP2, ((3.0 + u.accumulate) * u.ny + u.nyc) * nx * bt.np *
+                                                                static_cast<double>(nrhs)));
+        }
+    }
+
     // one zebra half-sweep over the planes of one colour at 3D level l
     void sweep3(int l, int colour, bool all_zero, bool self_zero)
     {
+        if (fused2()) {
+            sweep3_fused(l, colour, all_zero, self_zero);
+            return;
+        }
         const int nz = h->nz[l];
         const int np = colour == 0 ? (nz + 1) / 2 : nz / 2;
         if (np == 0) return;
@@ -388,7 +523,7 @@ struct VCycle {
         ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
         ra.pc = PC(l);
         ra.self_zero = self_zero;
-        launch_resid3<T, A>(ra, st);
+        launch_resid3<T, A>(ra, st, ev_for(SMG_KERNEL_RESID3, resid3_values(nz, np, self_zero)));
         bt.b = ra.r; bt.bps = p; bt.brs = rs2(0);
         if (self_zero) {           // own planes still zero: write the solve in place
             bt.x = X0 + colour * p; bt.xps = 2 * p; bt.xrs = ld;
@@ -400,7 +535,47 @@ struct VCycle {
         Correct3Args<T, A> ca{};
         ca.x = X0; ca.y = bt.x; ca.xrs = ld; ca.yps = p; ca.yrs = rs2(0);
         ca.nx = h->g.nx; ca.ny = h->g.ny; ca.np = np; ca.nrhs = nrhs; ca.kmul = 2; ca.koff = colour;
-        launch_correct3<T, A>(ca, st);
+        launch_correct3<T, A>(ca, st, ev_for(SMG_KERNEL_CORRECT3, 3.0 * np * p * nrhs));
+    }
+
+    void sweep3_fused(int l, int colour, bool all_zero, bool self_zero)
+    {
+        const int nz = h->nz[l];
+        const int np = colour == 0 ? (nz + 1) / 2 : nz / 2;
+        if (np == 0) return;
+        T *X0 = X(l);
+        const long long p = pl(), ld = LD(l);
+        Batch bt{np, 2, colour, PC(l), nullptr, 0, 0, nullptr, 0, 0};
+        if (all_zero) {
+            bt.b = B(l) + colour * p; bt.bps = 2 * p; bt.brs = ld;
+        } else {
+            Resid3Args<T, A> ra{};
+            ra.x = X0; ra.b = B(l); ra.r = h->at<T>(h->L.b2[0]);
+            ra.xrs = ld; ra.brs = ld; ra.rps = p; ra.rrs = rs2(0);
+            ra.nx = h->g.nx; ra.ny = h->g.ny; ra.nz = nz; ra.np = np; ra.nrhs = nrhs;
+            ra.kmul = 2; ra.koff = colour;
+            ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
+            ra.pc = PC(l);
+            ra.self_zero = self_zero;
+            launch_resid3<T, A>(ra, st, ev_for(SMG_KERNEL_RESID3, resid3_values(nz, np, self_zero)));
+            bt.b = ra.r; bt.bps = p; bt.brs = rs2(0);
+        }
+        v2_fused(bt, X0 + colour * p, 2 * p, ld, !self_zero);
+    }
+
+    void chain3_all()
+    {
+        Chain3Args<T, A> a{};
+        const int L = static_cast<int>(h->nz.size()) - 1;
+        for (int l = 0; l <= L; ++l) {
+            a.x[l] = X(l);
+            a.rs[l] = LD(l);
+            a.nz[l] = h->nz[l];
+        }
+        a.L = L; a.nx = h->g.nx; a.ny = h->g.ny;
+        double planes = h->nz[0];
+        for (int l = 0; l <= L; ++l) planes += h->nz[l];
+        launch_chain3<T, A>(a, nrhs, st, ev_for(SMG_KERNEL_CHAIN3, planes * pl() * nrhs));
     }
 
     void v3(int l)
@@ -408,7 +583,10 @@ struct VCycle {
         const int nz = h->nz[l];
         if (nz == 1) {
             Batch bt{1, 1, 0, PC(l), X(l), pl(), LD(l), B(l), pl(), LD(l)};
-            v2(bt, 0);
+            if (fused2())
+                v2_fused(bt, X(l), pl(), LD(l), false);
+            else
+                v2(bt, 0);
             return;
         }
         const int first = h->o.order == 0 ? 0 : 1, second = 1 - first;
@@ -424,13 +602,19 @@ struct VCycle {
         ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
         ra.pc = PC(l);
         ra.x_zero = x_zero;
-        launch_restrict3<T, A>(ra, st);
+        launch_restrict3<T, A>(ra, st, ev_for(SMG_KERNEL_RESTRICT3,
+                                             ((x_zero ? 1.0 : 2.0) * nz + h->nz[l + 1]) * pl() * nrhs));
         v3(l + 1);
+        if (chain3()) {          // no post-smoothing: all prolongations in one pass
+            if (l == 0) chain3_all();
+            return;
+        }
         Prolong3Args<T, A> pa{};
         pa.x = X(l); pa.xc = X(l + 1); pa.xrs = LD(l); pa.crs = nl(l + 1);
         pa.nx = h->g.nx; pa.ny = h->g.ny; pa.nz = nz; pa.nzc = h->nz[l + 1]; pa.nrhs = nrhs;
         pa.x_zero = x_zero;
-        launch_prolong3<T, A>(pa, st);
+        launch_prolong3<T, A>(pa, st, ev_for(SMG_KERNEL_PROLONG3,
+                                            ((x_zero ? 1.0 : 2.0) * nz + h->nz[l + 1]) * pl() * nrhs));
         for (int s = 0; s < h->o.post; ++s) {
             sweep3(l, second, false, false);
             sweep3(l, first, false, false);
@@ -593,6 +777,20 @@ int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_o
 
 }  // namespace
 
+int smg_handle_size(const smg_handle *h, size_t *n)
+{
+    if (!h || !n) return SMG_EINVAL;
+    *n = h->N;
+    return SMG_OK;
+}
+
+int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs)
+{
+    if (!h || !max_nrhs) return SMG_EINVAL;
+    *max_nrhs = h->max_nrhs;
+    return SMG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -642,6 +840,7 @@ int smg_setup(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, void *ws, 
         h->nfac = static_cast<int>(t.uniq.size());
         h->P2 = (g->nz + 1) / 2;
         h->elem = elem_size(o->precision);
+        choose_fused_schedule(h);
         h->L = make_layout(*g, *o, max_nrhs, t, h->nxp);
         if (ws_bytes < h->L.total) {
             delete h;
@@ -723,20 +922,19 @@ const char *smg_strerror(int status)
     }
 }
 
-int smg_profile_line_relax(smg_handle *h, const double *r, double *s, int32_t reps, void *stream,
-                           int32_t *launches, double *kernel_ms, double *bytes)
+int smg_profile_kernel(smg_handle *h, int32_t family, const double *r, double *s, int32_t reps, void *stream,
+                       int32_t *launches, double *kernel_ms, double *bytes)
 {
     if (!h || !r || !s || reps < 1 || !launches || !kernel_ms || !bytes) return SMG_EINVAL;
+    if (family < 0 || family >= SMG_KERNEL_COUNT) return SMG_EINVAL;
     hipStream_t st = as_stream(stream);
-    // count launches of one V-cycle first
-    h->prof = true;
-    h->ev_used = 0;
-    h->prof_bytes = 0;
     if (h->ev.empty()) {
         h->ev.resize(2 * 4096);
         for (auto &e : h->ev)
             if (hipEventCreate(&e) != hipSuccess) return SMG_EHIP;
     }
+    h->prof = true;
+    h->prof_family = family;
     double ms_total = 0.0, bytes_total = 0.0;
     int per_cycle = 0;
     for (int rep = 0; rep < reps; ++rep) {

@@ -1,6 +1,7 @@
 // Internal declarations of the SMG library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -10,6 +11,21 @@
 #include "../../include/smg.h"
 
 namespace smg {
+
+// Optional dispatch-stamped start/stop events of one launch (hipExtLaunchKernel):
+// the profiler times individual kernels with them; null events = plain launch.
+struct LaunchEv {
+    hipEvent_t e0 = nullptr;
+    hipEvent_t e1 = nullptr;
+};
+
+#define SMG_LAUNCH(EV, K, G, B, L, S, ...)                                          \
+    do {                                                                            \
+        if ((EV).e0)                                                                \
+            hipExtLaunchKernelGGL(K, G, B, L, S, (EV).e0, (EV).e1, 0, __VA_ARGS__); \
+        else                                                                        \
+            hipLaunchKernelGGL(K, G, B, L, S, __VA_ARGS__);                         \
+    } while (0)
 
 // bfloat16 storage: the upper half of an IEEE binary32, rounded to nearest even.
 struct bf16 {
@@ -153,21 +169,92 @@ struct Prolong3Args {
     int x_zero;             // x is known to be zero: x = P xc
 };
 
+// Fused-schedule argument blocks (smg_fused.hip) ---------------------------
+constexpr int kMaxLev = 16;     // 2D levels (ny <= 2^15) and 3D chain arrays
+constexpr int kMaxLev3 = 24;
+
+template <typename T, typename A>
+struct Down2Args {
+    const T *b; T *x; T *bc;
+    long long bps, brs, xps, xrs, cps, crs;
+    int nx, nxp, ny, nyc, S, np, nrhs, kmul, koff;
+    const PlaneCoef<A> *pc;
+    const LineCoef<A> *lc;      // rows of this 2D level, plane type 0
+    int lines_total;
+    const Fac<A> *fac;
+};
+
+template <typename T, typename A>
+struct Coarse2Args {
+    const T *b; T *out;
+    long long bps, brs, ops, ors;
+    int nx, nxp, np, nrhs, kmul, koff;
+    int l0, nlev;
+    int ny2[kMaxLev], lev_off[kMaxLev];
+    int ipre, ipost, accumulate;
+    const PlaneCoef<A> *pc;
+    const LineCoef<A> *lc;      // rows of 2D level 0, plane type 0
+    int lines_total;
+    const Fac<A> *fac;
+};
+
+template <typename T, typename A>
+struct Chain2Args {
+    const T *x0; T *out;
+    long long x0ps, x0rs, ops, ors;
+    const T *xc[kMaxLev];
+    long long cps[kMaxLev], crs[kMaxLev];
+    int nx, np, nrhs, lc;
+    int ny2[kMaxLev];
+    int accumulate;
+};
+
+template <typename T, typename A>
+struct Up2Args {
+    const T *xpre; const T *xc; const T *b; T *out;
+    long long xps, xrs, cps, crs, bps, brs, ops, ors;
+    int nx, nxp, ny, nyc, S, np, nrhs, kmul, koff;
+    const PlaneCoef<A> *pc;
+    const LineCoef<A> *lc;      // rows of this 2D level, plane type 0
+    int lines_total;
+    const Fac<A> *fac;
+    int accumulate;
+};
+
+template <typename T, typename A>
+struct Chain3Args {
+    T *x[kMaxLev3];
+    long long rs[kMaxLev3];
+    int nz[kMaxLev3];
+    int L, nx, ny;
+};
+
+template <typename T, typename A>
+void launch_down2(const Down2Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
+template <typename T, typename A>
+void launch_coarse2(const Coarse2Args<T, A> &a, size_t lds_bytes, hipStream_t st, const LaunchEv &ev = LaunchEv{});
+template <typename T, typename A>
+void launch_chain2(const Chain2Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
+template <typename T, typename A>
+void launch_up2(const Up2Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
+template <typename T, typename A>
+void launch_chain3(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const LaunchEv &ev = LaunchEv{});
+
 // Launchers (smg_kernels.hip) ---------------------------------------------
 template <typename T, typename A>
-void launch_line_relax(const LineRelaxArgs<T, A> &a, hipStream_t st);
+void launch_line_relax(const LineRelaxArgs<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
-void launch_restrict2(const Restrict2Args<T, A> &a, hipStream_t st);
+void launch_restrict2(const Restrict2Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
-void launch_prolong2(const Prolong2Args<T, A> &a, hipStream_t st);
+void launch_prolong2(const Prolong2Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
-void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st);
+void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
-void launch_correct3(const Correct3Args<T, A> &a, hipStream_t st);
+void launch_correct3(const Correct3Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
-void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st);
+void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
-void launch_prolong3(const Prolong3Args<T, A> &a, hipStream_t st);
+void launch_prolong3(const Prolong3Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename A>
 void launch_thomas_tables(const LineCoef<double> *uniq_ab, int nfac, int nx, int nxp, Fac<A> *out, hipStream_t st);
 template <typename T>
@@ -204,3 +291,7 @@ void launch_true_resid(const double *b, const double *x, double *tmp, int nx, in
                        double cy, double cz, double *partials, hipStream_t st);
 
 }  // namespace smg
+
+// Handle queries shared by the library's translation units.
+int smg_handle_size(const smg_handle *h, size_t *n);
+int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs);

@@ -366,70 +366,76 @@ inline unsigned blocks_for(long long n, int bs) { return static_cast<unsigned>((
 
 }  // namespace
 
+template <typename T, typename A, int E>
+static void line_relax_e(const LineRelaxArgs<T, A> &a, dim3 grid, hipStream_t st, const LaunchEv &ev)
+{
+    SMG_LAUNCH(ev, (k_line_relax<T, A, E>), grid, dim3(kBlock), 0, st, a);
+}
+
 template <typename T, typename A>
-void launch_line_relax(const LineRelaxArgs<T, A> &a, hipStream_t st)
+void launch_line_relax(const LineRelaxArgs<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     const long long waves = static_cast<long long>(a.nq) * a.np * a.nrhs;
     if (waves == 0) return;
     const dim3 grid(blocks_for(waves, kWavesPerBlock));
     const int E = (a.nx + 63) / 64;
     switch (E) {
-    case 1: hipLaunchKernelGGL((k_line_relax<T, A, 1>), grid, dim3(kBlock), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_line_relax<T, A, 2>), grid, dim3(kBlock), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_line_relax<T, A, 3>), grid, dim3(kBlock), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_line_relax<T, A, 4>), grid, dim3(kBlock), 0, st, a); break;
-    case 5: hipLaunchKernelGGL((k_line_relax<T, A, 5>), grid, dim3(kBlock), 0, st, a); break;
-    case 6: hipLaunchKernelGGL((k_line_relax<T, A, 6>), grid, dim3(kBlock), 0, st, a); break;
-    case 7: hipLaunchKernelGGL((k_line_relax<T, A, 7>), grid, dim3(kBlock), 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_line_relax<T, A, 8>), grid, dim3(kBlock), 0, st, a); break;
+    case 1: line_relax_e<T, A, 1>(a, grid, st, ev); break;
+    case 2: line_relax_e<T, A, 2>(a, grid, st, ev); break;
+    case 3: line_relax_e<T, A, 3>(a, grid, st, ev); break;
+    case 4: line_relax_e<T, A, 4>(a, grid, st, ev); break;
+    case 5: line_relax_e<T, A, 5>(a, grid, st, ev); break;
+    case 6: line_relax_e<T, A, 6>(a, grid, st, ev); break;
+    case 7: line_relax_e<T, A, 7>(a, grid, st, ev); break;
+    case 8: line_relax_e<T, A, 8>(a, grid, st, ev); break;
     default: break;   // nx > 512 is rejected at setup
     }
 }
 
 template <typename T, typename A>
-void launch_restrict2(const Restrict2Args<T, A> &a, hipStream_t st)
+void launch_restrict2(const Restrict2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     const long long n = static_cast<long long>(a.nx) * a.nyc * a.np * a.nrhs;
     if (n == 0) return;
-    hipLaunchKernelGGL((k_restrict2<T, A>), dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
+    SMG_LAUNCH(ev, (k_restrict2<T, A>), dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
-void launch_prolong2(const Prolong2Args<T, A> &a, hipStream_t st)
+void launch_prolong2(const Prolong2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     const long long n = static_cast<long long>(a.nx) * a.ny * a.np * a.nrhs;
     if (n == 0) return;
-    hipLaunchKernelGGL((k_prolong2<T, A>), dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
+    SMG_LAUNCH(ev, (k_prolong2<T, A>), dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
-void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st)
+void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     if (a.np == 0) return;
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.np, a.nrhs);
-    hipLaunchKernelGGL((k_resid3<T, A>), grid, dim3(256), 0, st, a);
+    SMG_LAUNCH(ev, (k_resid3<T, A>), grid, dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
-void launch_correct3(const Correct3Args<T, A> &a, hipStream_t st)
+void launch_correct3(const Correct3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     if (a.np == 0) return;
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.np, a.nrhs);
-    hipLaunchKernelGGL((k_correct3<T, A>), grid, dim3(256), 0, st, a);
+    SMG_LAUNCH(ev, (k_correct3<T, A>), grid, dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
-void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st)
+void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.nzc, a.nrhs);
-    hipLaunchKernelGGL((k_restrict3<T, A>), grid, dim3(256), 0, st, a);
+    SMG_LAUNCH(ev, (k_restrict3<T, A>), grid, dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
-void launch_prolong3(const Prolong3Args<T, A> &a, hipStream_t st)
+void launch_prolong3(const Prolong3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.nz, a.nrhs);
-    hipLaunchKernelGGL((k_prolong3<T, A>), grid, dim3(256), 0, st, a);
+    SMG_LAUNCH(ev, (k_prolong3<T, A>), grid, dim3(256), 0, st, a);
 }
 
 template <typename A>
@@ -454,13 +460,13 @@ void launch_convert_out(const T *src, long long lds, double *dst, long long ldd,
 }
 
 #define SMG_INSTANTIATE(T, A)                                                          \
-    template void launch_line_relax<T, A>(const LineRelaxArgs<T, A> &, hipStream_t);   \
-    template void launch_restrict2<T, A>(const Restrict2Args<T, A> &, hipStream_t);     \
-    template void launch_prolong2<T, A>(const Prolong2Args<T, A> &, hipStream_t);       \
-    template void launch_resid3<T, A>(const Resid3Args<T, A> &, hipStream_t);           \
-    template void launch_correct3<T, A>(const Correct3Args<T, A> &, hipStream_t);       \
-    template void launch_restrict3<T, A>(const Restrict3Args<T, A> &, hipStream_t);     \
-    template void launch_prolong3<T, A>(const Prolong3Args<T, A> &, hipStream_t);
+    template void launch_line_relax<T, A>(const LineRelaxArgs<T, A> &, hipStream_t, const LaunchEv &); \
+    template void launch_restrict2<T, A>(const Restrict2Args<T, A> &, hipStream_t, const LaunchEv &);     \
+    template void launch_prolong2<T, A>(const Prolong2Args<T, A> &, hipStream_t, const LaunchEv &);       \
+    template void launch_resid3<T, A>(const Resid3Args<T, A> &, hipStream_t, const LaunchEv &);           \
+    template void launch_correct3<T, A>(const Correct3Args<T, A> &, hipStream_t, const LaunchEv &);       \
+    template void launch_restrict3<T, A>(const Restrict3Args<T, A> &, hipStream_t, const LaunchEv &);     \
+    template void launch_prolong3<T, A>(const Prolong3Args<T, A> &, hipStream_t, const LaunchEv &);
 
 SMG_INSTANTIATE(double, double)
 SMG_INSTANTIATE(float, float)

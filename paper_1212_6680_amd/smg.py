@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libsmg.so")
 SMG_OK, SMG_NOT_CONVERGED = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 PRECOND = {"smg": 0, "none": 1}
+KERNELS = {"line_relax": 0, "restrict2": 1, "prolong2": 2, "resid3": 3, "correct3": 4, "restrict3": 5,
+           "prolong3": 6, "down2": 7, "coarse2": 8, "chain2": 9, "up2": 10, "chain3": 11}
 
 
 class SMGError(RuntimeError):
@@ -32,7 +34,8 @@ class smg_grid(C.Structure):
 
 class smg_opts(C.Structure):
     _fields_ = [("pre", C.c_int32), ("post", C.c_int32), ("inner_pre", C.c_int32),
-                ("inner_post", C.c_int32), ("order", C.c_int32), ("precision", C.c_int32)]
+                ("inner_post", C.c_int32), ("order", C.c_int32), ("precision", C.c_int32),
+                ("kernel_mode", C.c_int32)]
 
 
 class krylov_opts(C.Structure):
@@ -47,7 +50,8 @@ class krylov_info(C.Structure):
 
 
 class lobpcg_opts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32)]
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32),
+                ("guard", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lobpcg_info(C.Structure):
@@ -76,10 +80,10 @@ def lib():
         L.smg_destroy.argtypes = [p]
         L.smg_strerror.argtypes = [C.c_int]
         L.smg_strerror.restype = C.c_char_p
-        L.smg_profile_line_relax.argtypes = [p, p, p, i32, p, C.POINTER(i32), C.POINTER(d), C.POINTER(d)]
+        L.smg_profile_kernel.argtypes = [p, i32, p, p, i32, p, C.POINTER(i32), C.POINTER(d), C.POINTER(d)]
         if hasattr(L, "lobpcg_solve"):
             L.lobpcg_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
-            L.lobpcg_solve.argtypes = [p, i32, p, C.POINTER(d), C.POINTER(d), p, C.c_size_t,
+            L.lobpcg_solve.argtypes = [p, i32, p, p, p, p, C.c_size_t,
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
         _lib = L
     return _lib
@@ -115,12 +119,12 @@ class SMG:
     """One SMG hierarchy on the GPU for an (nx, ny, nz) brick with coefficients c."""
 
     def __init__(self, shape, c=(1.0, 1.0, 1.0), pre=1, post=1, inner_pre=-1, inner_post=-1, order=0,
-                 precision="f64", max_nrhs=1, device="cuda"):
+                 precision="f64", max_nrhs=1, device="cuda", kernel_mode=0):
         L = lib()
         self.shape = tuple(int(v) for v in shape)
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
         self.grid = smg_grid(*self.shape, *[float(v) for v in c])
-        self.opts = smg_opts(pre, post, inner_pre, inner_post, order, PREC[precision])
+        self.opts = smg_opts(pre, post, inner_pre, inner_post, order, PREC[precision], kernel_mode)
         self.max_nrhs = int(max_nrhs)
         nbytes = C.c_size_t(0)
         _check(L.smg_workspace_bytes(C.byref(self.grid), C.byref(self.opts), self.max_nrhs,
@@ -157,12 +161,12 @@ class SMG:
         _check(lib().smg_matvec(self.h, _dptr(x), _dptr(y), nrhs, self._ld(x), _stream()), "smg_matvec")
         return y
 
-    def _solve(self, fn, b, x, rtol, max_iter, precond, history):
+    def _solve(self, fn, b, x, rtol, max_iter, precond, history, zero_x0):
         if x is None:
-            x = torch.zeros_like(b)
+            x = torch.empty_like(b)
             x0_zero = 1
         else:
-            x0_zero = 0
+            x0_zero = 1 if zero_x0 else 0
         hist = (C.c_double * (max_iter + 1))() if history else None
         histc = (C.c_double * max(max_iter, 1))() if history else None
         o = krylov_opts(rtol, max_iter, PRECOND[precond], x0_zero, 0,
@@ -178,22 +182,45 @@ class SMG:
             out["history_c"] = list(histc[:info.iters])
         return x, out
 
-    def pcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False):
+    def pcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False):
         """Algorithm 1 with beta from equation (1)."""
-        return self._solve(lib().pcg_solve, b, x, rtol, max_iter, precond, history)
+        return self._solve(lib().pcg_solve, b, x, rtol, max_iter, precond, history, zero_x0)
 
-    def fpcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False):
+    def fpcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False):
         """Algorithm 1 with beta from equation (2)."""
-        return self._solve(lib().fpcg_solve, b, x, rtol, max_iter, precond, history)
+        return self._solve(lib().fpcg_solve, b, x, rtol, max_iter, precond, history, zero_x0)
 
-    def psd(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False):
+    def psd(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False):
         """Algorithm 1 with beta = 0."""
-        return self._solve(lib().psd_solve, b, x, rtol, max_iter, precond, history)
+        return self._solve(lib().psd_solve, b, x, rtol, max_iter, precond, history, zero_x0)
 
-    def profile_line_relax(self, r: torch.Tensor, reps: int = 3):
-        """(launches per V-cycle, kernel ms per V-cycle, algorithmic bytes per V-cycle)."""
+    def lobpcg(self, X0: torch.Tensor, rtol=1e-8, max_iter=500, precond="smg", guard=0):
+        """LOBPCG for the m smallest eigenpairs; X0 is (m + guard, n), one initial vector per row.
+
+        Returns (Ritz values (m + guard,) as a NumPy array, Ritz vectors (m + guard, n), info);
+        convergence is required of the first m."""
+        mb = X0.shape[0]
+        m = mb - guard
+        nbytes = C.c_size_t(0)
+        _check(lib().lobpcg_workspace_bytes(self.h, mb, C.byref(nbytes)), "lobpcg_workspace_bytes")
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=X0.device)
+        X = X0.clone().contiguous()
+        lam = (C.c_double * mb)()
+        res = (C.c_double * mb)()
+        o = lobpcg_opts(rtol, max_iter, PRECOND[precond], guard, 0)
+        info = lobpcg_info()
+        code = lib().lobpcg_solve(self.h, m, _dptr(X), C.cast(lam, C.c_void_p), C.cast(res, C.c_void_p),
+                                  C.c_void_p(ws.data_ptr()), nbytes.value, C.byref(o), C.byref(info), _stream())
+        _check(code, "lobpcg_solve", ok=(SMG_OK, SMG_NOT_CONVERGED))
+        import numpy as np
+        out = Info(iters=info.iters, nconv=info.nconv, status=info.status, seconds=info.seconds,
+                   resnorms=np.array(res[:]))
+        return np.array(lam[:]), X, out
+
+    def profile_kernel(self, family: str, r: torch.Tensor, reps: int = 3):
+        """(launches per V-cycle, kernel ms per V-cycle, algorithmic bytes per V-cycle) of one kernel family."""
         s = torch.empty_like(r)
         nl, ms, by = C.c_int32(0), C.c_double(0), C.c_double(0)
-        _check(lib().smg_profile_line_relax(self.h, _dptr(r), _dptr(s), reps, _stream(),
-                                            C.byref(nl), C.byref(ms), C.byref(by)), "smg_profile_line_relax")
+        _check(lib().smg_profile_kernel(self.h, KERNELS[family], _dptr(r), _dptr(s), reps, _stream(),
+                                        C.byref(nl), C.byref(ms), C.byref(by)), "smg_profile_kernel")
         return nl.value, ms.value, by.value

@@ -37,28 +37,28 @@ def _ws(grid, opts, nrhs=1):
 
 def test_workspace_query_and_invalid_arguments():
     g = S.smg_grid(32, 32, 32, 1.0, 1.0, 1.0)
-    o = S.smg_opts(1, 0, -1, -1, 0, 0)
+    o = S.smg_opts(1, 0, -1, -1, 0, 0, 0)
     rc, n = _ws(g, o)
     assert rc == 0 and n > 5 * 32 ** 3 * 8
     rc2, n2 = _ws(g, o, 4)
     assert rc2 == 0 and n2 > n
     # FP32 and BF16 hierarchies need less than FP64 for a big batch
-    rc3, n3 = _ws(g, S.smg_opts(1, 0, -1, -1, 0, 1), 16)
-    rc4, n4 = _ws(g, S.smg_opts(1, 0, -1, -1, 0, 2), 16)
+    rc3, n3 = _ws(g, S.smg_opts(1, 0, -1, -1, 0, 1, 0), 16)
+    rc4, n4 = _ws(g, S.smg_opts(1, 0, -1, -1, 0, 2, 0), 16)
     rc5, n5 = _ws(g, o, 16)
     assert rc3 == rc4 == rc5 == 0 and n4 < n3 < n5
     for bad in [S.smg_grid(0, 4, 4, 1, 1, 1), S.smg_grid(4, -1, 4, 1, 1, 1), S.smg_grid(513, 4, 4, 1, 1, 1),
                 S.smg_grid(4, 4, 4, 0.0, 1, 1), S.smg_grid(4, 4, 4, 1, float("nan"), 1)]:
         assert _ws(bad, o)[0] == -1
-    for bado in [S.smg_opts(-1, 0, -1, -1, 0, 0), S.smg_opts(1, 9, -1, -1, 0, 0),
-                 S.smg_opts(1, 0, -2, -1, 0, 0), S.smg_opts(1, 0, -1, -1, 2, 0), S.smg_opts(1, 0, -1, -1, 0, 3)]:
+    for bado in [S.smg_opts(-1, 0, -1, -1, 0, 0, 0), S.smg_opts(1, 9, -1, -1, 0, 0, 0),
+                 S.smg_opts(1, 0, -2, -1, 0, 0, 0), S.smg_opts(1, 0, -1, -1, 2, 0, 0), S.smg_opts(1, 0, -1, -1, 0, 3, 0), S.smg_opts(1, 0, -1, -1, 0, 0, 2)]:
         assert _ws(g, bado)[0] == -1
     assert _ws(g, o, 0)[0] == -1
 
 
 def test_setup_rejects_small_workspace_before_touching_the_device():
     g = S.smg_grid(16, 16, 16, 1.0, 1.0, 1.0)
-    o = S.smg_opts(1, 1, -1, -1, 0, 0)
+    o = S.smg_opts(1, 1, -1, -1, 0, 0, 0)
     rc, n = _ws(g, o)
     h = C.c_void_p()
     fake = C.c_void_p(0x1000)   # never dereferenced: the size check comes first

@@ -129,3 +129,33 @@ def test_vcycle_parity_full_size(n):
         ref = O.SMG(shape, c, *pp).apply(r)
         s = _smg(shape, c, *pp).apply(_dev(r)).cpu().numpy()
         assert _relerr(s, ref) <= TOL
+
+
+FUSED_SHAPES = [(1, 1, 1), (9, 1, 1), (5, 4, 3), (16, 16, 16), (33, 17, 9), (64, 64, 2), (130, 6, 7),
+                (17, 40, 33), (100, 70, 45), (256, 256, 4), (300, 11, 3), (64, 200, 5), (512, 3, 4)]
+
+
+@pytest.mark.parametrize("shape", FUSED_SHAPES)
+@pytest.mark.parametrize("pp", [(1, 0), (1, 1), (2, 0), (0, 1)])
+def test_fused_schedule_equals_stage_schedule_and_oracle(shape, pp):
+    """The fused kernels (strip relax+restrict, LDS-resident coarse levels,
+    prolongation chains) compute the same cycle as one launch per stage."""
+    c = tuple((v + 1.0) ** 2 for v in shape)
+    r = _dev(synth.rhs(*shape, seed=17))
+    a = _smg(shape, c, *pp, kernel_mode=0).apply(r).cpu().numpy()
+    b = _smg(shape, c, *pp, kernel_mode=1).apply(r).cpu().numpy()
+    assert _relerr(a, b) <= TOL
+    if np.prod(shape) <= 200000:
+        ref = O.SMG(shape, c, *pp).apply(synth.rhs(*shape, seed=17))
+        assert _relerr(a, ref) <= TOL
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_fused_schedule_low_precision(prec):
+    shape = (96, 80, 40)
+    c = tuple((v + 1.0) ** 2 for v in shape)
+    r = _dev(synth.rhs(*shape, seed=18))
+    for pp in [(1, 0), (1, 1)]:
+        a = _smg(shape, c, *pp, precision=prec, kernel_mode=0).apply(r).cpu().numpy()
+        b = _smg(shape, c, *pp, precision=prec, kernel_mode=1).apply(r).cpu().numpy()
+        assert _relerr(a, b) <= (1e-5 if prec == "f32" else 3e-2)
