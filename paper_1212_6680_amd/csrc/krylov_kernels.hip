@@ -146,6 +146,75 @@ __global__ __launch_bounds__(kRB) void k_update_p_q(const double *s, const doubl
     if (threadIdx.x == 0) partials[blockIdx.x] = pq;
 }
 
+// The same pass as a z-marching stencil: a block owns a 64 x 8 (i, j) tile and
+// a run of planes; p at k-1, k, k+1 stays in registers, the in-plane
+// neighbours of plane k come from an LDS tile with a one-point halo (halo
+// values are formed from s and p_{k-1} by the block itself).  s and p_{k-1}
+// are read about once, p_k and q written once.
+constexpr int kTX = 64, kTY = 8, kTileThreads = kTX * kTY;
+
+__global__ __launch_bounds__(kTileThreads) void k_update_p_q_tiled(const double *s, const double *p_old,
+                                                                   double *p_new, double *q, const KScalars *sc,
+                                                                   int nx, int ny, int nz, double cx, double cy,
+                                                                   double cz, int kchunk, double *partials)
+{
+    __shared__ double tile[(kTY + 2) * (kTX + 2)];
+    __shared__ double lds[kTileThreads / 64];
+    const double beta = sc->beta;
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+    const int i = blockIdx.x * kTX + tx, j = blockIdx.y * kTY + ty;
+    const bool in = i < nx && j < ny;
+    const long long pl = static_cast<long long>(nx) * ny;
+    const long long c2 = static_cast<long long>(j) * nx + i;
+    const int k0 = blockIdx.z * kchunk, k1 = min(nz, k0 + kchunk);
+    auto pv = [&](long long c) { return beta == 0.0 ? s[c] : s[c] + beta * p_old[c]; };
+    // halo point of this thread (threads 0..143), tile coordinates (hy, hx)
+    int hy = -1, hx = -1, hi = -1, hj = -1;
+    const int t = threadIdx.x;
+    if (t < kTX) {
+        hy = 0; hx = t + 1;
+    } else if (t < 2 * kTX) {
+        hy = kTY + 1; hx = t - kTX + 1;
+    } else if (t < 2 * kTX + kTY) {
+        hy = t - 2 * kTX + 1; hx = 0;
+    } else if (t < 2 * kTX + 2 * kTY) {
+        hy = t - 2 * kTX - kTY + 1; hx = kTX + 1;
+    }
+    if (hy >= 0) {
+        hi = blockIdx.x * kTX + hx - 1;
+        hj = blockIdx.y * kTY + hy - 1;
+    }
+    const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const long long hc2 = static_cast<long long>(hj) * nx + hi;
+    const double diag = 2.0 * (cx + cy + cz);
+    double pm = (in && k0 > 0 && k0 < nz) ? pv((k0 - 1) * pl + c2) : 0.0;
+    double pc = (in && k0 < nz) ? pv(k0 * pl + c2) : 0.0;
+    double pq = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const double pn = (in && k + 1 < nz) ? pv((k + 1) * pl + c2) : 0.0;
+        tile[(ty + 1) * (kTX + 2) + tx + 1] = pc;
+        if (hy >= 0) tile[hy * (kTX + 2) + hx] = hin ? pv(k * pl + hc2) : 0.0;
+        __syncthreads();
+        if (in) {
+            const int cc = (ty + 1) * (kTX + 2) + tx + 1;
+            const double qv = diag * pc - cx * (tile[cc - 1] + tile[cc + 1]) -
+                              cy * (tile[cc - (kTX + 2)] + tile[cc + (kTX + 2)]) - cz * (pm + pn);
+            p_new[k * pl + c2] = pc;
+            q[k * pl + c2] = qv;
+            pq += pc * qv;
+        }
+        __syncthreads();
+        pm = pc;
+        pc = pn;
+    }
+    pq = block_sum(pq, lds);
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0) partials[bid] = pq;
+    if (bid == 0)
+        for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) partials[e] = 0.0;
+}
+
 __global__ __launch_bounds__(kRB) void k_update_xr(double *x, double *r, const double *p, const double *q,
                                                    const KScalars *sc, long long n, double *partials)
 {
@@ -249,6 +318,16 @@ void launch_dots_sr_sq(const double *s, const double *r, const double *q, int wa
 void launch_update_p_q(const double *s, const double *p_old, double *p_new, double *q, const KScalars *sc, int nx,
                        int ny, int nz, double cx, double cy, double cz, double *partials, hipStream_t st)
 {
+    const int gx = (nx + kTX - 1) / kTX, gy = (ny + kTY - 1) / kTY;
+    if (gx * gy <= kRedBlocks) {
+        int gz = kRedBlocks / (gx * gy);
+        gz = gz < 1 ? 1 : (gz > nz ? nz : gz);
+        const int kchunk = (nz + gz - 1) / gz;
+        gz = (nz + kchunk - 1) / kchunk;
+        hipLaunchKernelGGL(k_update_p_q_tiled, dim3(gx, gy, gz), dim3(kTileThreads), 0, st, s, p_old, p_new, q, sc,
+                           nx, ny, nz, cx, cy, cz, kchunk, partials);
+        return;
+    }
     hipLaunchKernelGGL(k_update_p_q, dim3(kRedBlocks), dim3(kRB), 0, st, s, p_old, p_new, q, sc, nx, ny, nz, cx, cy,
                        cz, partials);
 }

@@ -2,8 +2,8 @@
 //
 // The stage-by-stage schedule of smg_kernels.hip launches four kernels per 2D
 // level (F relax, C relax, residual+restriction, prolongation+correction),
-// i.e. ~600 mostly tiny launches per 256^3 V-cycle.  These kernels cover the
-// same arithmetic with far fewer launches:
+// ~600 mostly tiny launches per 256^3 V-cycle.  These kernels cover the same
+// arithmetic with far fewer launches:
 //   k2_down   one launch per fine 2D level: for a strip of S coarse lines a
 //             workgroup solves the F lines it needs (zero initial guess), then
 //             the C lines, keeps both in LDS, writes its own lines of x, and
@@ -11,136 +11,28 @@
 //   k2_coarse one workgroup per plane runs the whole remaining 2D sub-cycle on
 //             the small levels with every line in LDS;
 //   k2_chain  without post-smoothing the upward half of the 2D cycle is a
-//             chain of prolongations, x_0 + P(x_1 + P(x_2 + ...)), evaluated
-//             per fine point in one pass and added straight into the 3D
-//             iterate (the 3D correction step);
+//             chain of prolongations, x_0 + P(x_1 + P(x_2 + ...)); a workgroup
+//             stages the coarse windows of a run of fine lines in LDS once and
+//             adds the result straight into the 3D iterate;
 //   k2_up     with one post-smoothing step: prolongation, C-line and F-line
 //             relaxation of a strip (with a two-line halo) in one launch;
-//   k3_chain  the same prolongation chain over the 3D levels.
-// Lines are held in registers by one wave (E = ceil(nx/64) points per lane)
-// and stored in LDS lane-interleaved (element e of lane l at [e*64 + l]), so
-// LDS accesses are conflict-free.
-#include "smg_internal.h"
+//   k3_chain  the prolongation chain over the 3D levels, tiled the same way.
+// Workgroups have W = 16 waves so that each wave handles one line per phase;
+// every global load a workgroup needs is issued before its first barrier.
+// Lines are held in registers (E = ceil(nx/64) points per lane) and stored in
+// LDS lane-interleaved (point e of lane l at [e*64 + l]): conflict-free.
+#include "line_ops.hpp"
 
 namespace smg {
 
 namespace {
 
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
+using namespace lineops;
+
+constexpr int kW = 16;                 // waves per workgroup
+constexpr int kThreads = 64 * kW;
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-template <typename T, typename A, int E>
-__device__ inline void gload(A (&v)[E], const T *row, int nx, int lane)
-{
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        v[e] = i < nx ? static_cast<A>(ldv(row + i)) : A(0);
-    }
-}
-
-template <typename T, typename A, int E>
-__device__ inline void gstore(T *row, const A (&v)[E], int nx, int lane)
-{
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        if (i < nx) stv(row + i, v[e]);
-    }
-}
-
-template <typename A, int E>
-__device__ inline void sload(A (&v)[E], const A *s, int lane)
-{
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = s[e * 64 + lane];
-}
-
-template <typename A, int E>
-__device__ inline void sstore(A *s, const A (&v)[E], int lane)
-{
-#pragma unroll
-    for (int e = 0; e < E; ++e) s[e * 64 + lane] = v[e];
-}
-
-// f -= (a*Tx + b*I) w   (w zero beyond nx)
-template <typename A, int E>
-__device__ inline void sub_op(A (&f)[E], const A (&w)[E], A a, A b, int lane)
-{
-    if (a != A(0)) {
-        A left = __shfl_up(w[E - 1], 1, 64);
-        A right = __shfl_down(w[0], 1, 64);
-        if (lane == 0) left = A(0);
-        if (lane == 63) right = A(0);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const A wl = e > 0 ? w[e - 1] : left;
-            const A wr = e < E - 1 ? w[e + 1] : right;
-            f[e] -= a * (A(2) * w[e] - wl - wr) + b * w[e];
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) f[e] -= b * w[e];
-    }
-}
-
-// Exact solve of one line in place: Thomas recurrences as two lane scans.
-template <typename A, int E>
-__device__ inline void thomas(A (&f)[E], const Fac<A> *fac, int lane)
-{
-    const int i0 = lane * E;
-    A h[E], pr[E];
-    A acc = A(0), prod = A(1);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const Fac<A> fe = fac[i0 + e];
-        h[e] = fe.h;
-        acc = fe.g * f[e] + fe.h * acc;
-        prod *= fe.h;
-        f[e] = acc;
-        pr[e] = prod;
-    }
-    A sa = pr[E - 1], sb = f[E - 1];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const A pa = __shfl_up(sa, off, 64);
-        const A pb = __shfl_up(sb, off, 64);
-        if (lane >= off) {
-            sb = sa * pb + sb;
-            sa = sa * pa;
-        }
-    }
-    A carry = __shfl_up(sb, 1, 64);
-    if (lane == 0) carry = A(0);
-#pragma unroll
-    for (int e = 0; e < E; ++e) f[e] += pr[e] * carry;
-    acc = A(0);
-    prod = A(1);
-#pragma unroll
-    for (int e = E - 1; e >= 0; --e) {
-        acc = f[e] + h[e] * acc;
-        prod *= h[e];
-        f[e] = acc;
-        pr[e] = prod;
-    }
-    sa = pr[0];
-    sb = f[0];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const A pa = __shfl_down(sa, off, 64);
-        const A pb = __shfl_down(sb, off, 64);
-        if (lane + off < 64) {
-            sb = sa * pb + sb;
-            sa = sa * pa;
-        }
-    }
-    carry = __shfl_down(sb, 1, 64);
-    if (lane == 63) carry = A(0);
-#pragma unroll
-    for (int e = 0; e < E; ++e) f[e] += pr[e] * carry;
-}
 
 template <typename A>
 __device__ inline const LineCoef<A> *plane_lines(const PlaneCoef<A> *pc, int k, const LineCoef<A> *lc0, int lines_total)
@@ -150,9 +42,10 @@ __device__ inline const LineCoef<A> *plane_lines(const PlaneCoef<A> *pc, int k, 
 
 // ---------------------------------------------------------------------------
 // k2_down: one pre-smoothing zebra sweep (F then C, zero initial guess) of a
-// strip of coarse lines [J0, J0+S), the own lines of x, and the restricted
-// residual b_c[J] = 1/2 r_{2J} + r_{2J+1} + 1/2 r_{2J+2}.
-// LDS slot s holds fine line j = 2*J0 - 2 + s, s in [0, 2S+5).
+// strip of coarse lines [J0, J1), the strip's own lines of x, and the
+// restricted residual b_c[J] = 1/2 r_{2J} + r_{2J+1} + 1/2 r_{2J+2}.
+// LDS slot s holds fine line j = 2*J0 - 2 + s, s in [0, 2S+5).  The host
+// keeps S <= W - 3 so that every phase is one line per wave.
 // ---------------------------------------------------------------------------
 template <typename T, typename A, int E>
 __global__ __launch_bounds__(kThreads) void k2_down(Down2Args<T, A> a)
@@ -173,79 +66,191 @@ __global__ __launch_bounds__(kThreads) void k2_down(Down2Args<T, A> a)
     const T *bpl = a.b + r * a.brs + p * a.bps;
     T *xpl = a.x + r * a.xrs + p * a.xps;
 
+    const int f0 = jlo + (jlo & 1), c0 = jlo | 1;
+    const int nf = f0 <= jhi ? (jhi - f0) / 2 + 1 : 0;
+    const int nc = c0 <= jhi ? (jhi - c0) / 2 + 1 : 0;
+    const int jf = f0 + 2 * w, jc = c0 + 2 * w, J = J0 + w;
+    const bool hf = w < nf, hc = w < nc, hr = J < J1;
+
+    // every global read of the workgroup, issued up front
+    A fb[E], cb[E], rb0[E], rb1[E], rb2[E];
+    if (hf) gload<T, A, E>(fb, bpl + static_cast<long long>(jf) * nx, nx, lane);
+    if (hc) gload<T, A, E>(cb, bpl + static_cast<long long>(jc) * nx, nx, lane);
+    if (hr) {
+        gload<T, A, E>(rb0, bpl + static_cast<long long>(2 * J) * nx, nx, lane);
+        gload<T, A, E>(rb1, bpl + static_cast<long long>(2 * J + 1) * nx, nx, lane);
+        if (2 * J + 2 < ny) gload<T, A, E>(rb2, bpl + static_cast<long long>(2 * J + 2) * nx, nx, lane);
+    }
     // F lines: x_j = L_j^{-1} b_j
-    {
-        const int f0 = jlo + (jlo & 1);
-        const int nf = f0 <= jhi ? (jhi - f0) / 2 + 1 : 0;
-        for (int t = w; t < nf; t += kWaves) {
-            const int j = f0 + 2 * t;
-            A f[E];
-            gload<T, A, E>(f, bpl + static_cast<long long>(j) * nx, nx, lane);
-            thomas<A, E>(f, a.fac + static_cast<size_t>(lc[j].fac) * nxp, lane);
-            sstore<A, E>(xs + (j - base) * nxp, f, lane);
-        }
+    if (hf) {
+        thomas<A, E>(fb, a.fac + static_cast<size_t>(lc[jf].fac) * nxp, lane);
+        sstore<A, E>(xs + (jf - base) * nxp, fb, lane);
     }
     __syncthreads();
     // C lines: x_j = L_j^{-1} (b_j - V_{j-1} x_{j-1} - V_j x_{j+1})
-    {
-        const int c0 = jlo | 1;
-        const int nc = c0 <= jhi ? (jhi - c0) / 2 + 1 : 0;
-        for (int t = w; t < nc; t += kWaves) {
-            const int j = c0 + 2 * t;
-            A f[E], v[E];
-            gload<T, A, E>(f, bpl + static_cast<long long>(j) * nx, nx, lane);
-            const LineCoef<A> cm = lc[j - 1];
-            sload<A, E>(v, xs + (j - 1 - base) * nxp, lane);
-            sub_op<A, E>(f, v, cm.va, cm.vb, lane);
-            if (j + 1 < ny) {
-                const LineCoef<A> cj = lc[j];
-                sload<A, E>(v, xs + (j + 1 - base) * nxp, lane);
-                sub_op<A, E>(f, v, cj.va, cj.vb, lane);
-            }
-            thomas<A, E>(f, a.fac + static_cast<size_t>(lc[j].fac) * nxp, lane);
-            sstore<A, E>(xs + (j - base) * nxp, f, lane);
+    if (hc) {
+        A v[E];
+        const LineCoef<A> cm = lc[jc - 1];
+        sload<A, E>(v, xs + (jc - 1 - base) * nxp, lane);
+        sub_op<A, E>(cb, v, cm.va, cm.vb);
+        if (jc + 1 < ny) {
+            const LineCoef<A> cj = lc[jc];
+            sload<A, E>(v, xs + (jc + 1 - base) * nxp, lane);
+            sub_op<A, E>(cb, v, cj.va, cj.vb);
         }
+        thomas<A, E>(cb, a.fac + static_cast<size_t>(lc[jc].fac) * nxp, lane);
+        sstore<A, E>(xs + (jc - base) * nxp, cb, lane);
     }
     __syncthreads();
     // own lines of x: [2 J0, 2 J1), plus the last fine line for the last strip
     {
         const int o0 = 2 * J0;
         const int o1 = (J1 == a.nyc) ? ny : 2 * J1;
-        for (int j = o0 + w; j < o1; j += kWaves) {
+        for (int j = o0 + w; j < o1; j += kW) {
             A v[E];
             sload<A, E>(v, xs + (j - base) * nxp, lane);
             gstore<T, A, E>(xpl + static_cast<long long>(j) * nx, v, nx, lane);
         }
     }
-    // restricted residual of the strip's coarse lines
-    T *bcpl = a.bc + r * a.crs + p * a.cps;
-    for (int J = J0 + w; J < J1; J += kWaves) {
+    // restricted residual of coarse line J
+    if (hr) {
         A acc[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = A(0);
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int j = 2 * J + d;
             if (j >= ny) break;
             A f[E], v[E];
-            gload<T, A, E>(f, bpl + static_cast<long long>(j) * nx, nx, lane);
+#pragma unroll
+            for (int e = 0; e < E; ++e) f[e] = d == 0 ? rb0[e] : d == 1 ? rb1[e] : rb2[e];
             const LineCoef<A> cj = lc[j];
             sload<A, E>(v, xs + (j - base) * nxp, lane);
-            sub_op<A, E>(f, v, cj.la, cj.lb, lane);
+            sub_op<A, E>(f, v, cj.la, cj.lb);
             if (j > 0) {
                 const LineCoef<A> cm = lc[j - 1];
                 sload<A, E>(v, xs + (j - 1 - base) * nxp, lane);
-                sub_op<A, E>(f, v, cm.va, cm.vb, lane);
+                sub_op<A, E>(f, v, cm.va, cm.vb);
             }
             if (j + 1 < ny) {
                 sload<A, E>(v, xs + (j + 1 - base) * nxp, lane);
-                sub_op<A, E>(f, v, cj.va, cj.vb, lane);
+                sub_op<A, E>(f, v, cj.va, cj.vb);
             }
             const A wgt = d == 1 ? A(1) : A(0.5);
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] += wgt * f[e];
         }
-        gstore<T, A, E>(bcpl + static_cast<long long>(J) * nx, acc, nx, lane);
+        gstore<T, A, E>(a.bc + r * a.crs + p * a.cps + static_cast<long long>(J) * nx, acc, nx, lane);
     }
+}
+
+// ---------------------------------------------------------------------------
+// k2_down_reg: the same stage with one wave per coarse line J and nothing but
+// registers: the wave solves the F lines 2J-2, 2J, 2J+2, 2J+4 and the C lines
+// 2J-1, 2J+1, 2J+3 it needs (its neighbours solve some of them again), forms
+// b_c[J], and writes its own lines 2J and 2J+1 (and the last line of an odd
+// level).  No barrier and no LDS: a wave never waits for another.  Used when a
+// line fits in 4 points per lane (nx <= 256).
+// ---------------------------------------------------------------------------
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(256) void k2_down_reg(Down2Args<T, A> a)
+{
+    const int lane = threadIdx.x & 63;
+    const long long wv = static_cast<long long>(blockIdx.x) * 4 + wave_id();
+    const long long total = static_cast<long long>(a.nyc) * a.np * a.nrhs;
+    if (wv >= total) return;   // whole waves
+    const int J = static_cast<int>(wv % a.nyc);
+    const long long t = wv / a.nyc;
+    const int p = static_cast<int>(t % a.np), r = static_cast<int>(t / a.np);
+    const int ny = a.ny, nx = a.nx, nxp = a.nxp;
+    const int k = p * a.kmul + a.koff;
+    const LineCoef<A> *lc = plane_lines(a.pc, k, a.lc, a.lines_total);
+    const T *bpl = a.b + r * a.brs + p * a.bps;
+    T *xpl = a.x + r * a.xrs + p * a.xps;
+    const int j0 = 2 * J;   // lines j0-2 .. j0+4 around the coarse line
+    const bool has_m2 = j0 >= 2, has_p2 = j0 + 2 < ny, has_p3 = j0 + 3 < ny, has_p4 = j0 + 4 < ny;
+
+    // all right-hand sides first (F: j0-2, j0, j0+2, j0+4; C: j0-1, j0+1, j0+3)
+    A fm2[E], f0[E], fp2[E], fp4[E], cm1[E], cp1[E], cp3[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) fm2[e] = fp2[e] = fp4[e] = cm1[e] = cp3[e] = A(0);
+    if (has_m2) {
+        gload<T, A, E>(fm2, bpl + static_cast<long long>(j0 - 2) * nx, nx, lane);
+        gload<T, A, E>(cm1, bpl + static_cast<long long>(j0 - 1) * nx, nx, lane);
+    }
+    gload<T, A, E>(f0, bpl + static_cast<long long>(j0) * nx, nx, lane);
+    gload<T, A, E>(cp1, bpl + static_cast<long long>(j0 + 1) * nx, nx, lane);
+    if (has_p2) gload<T, A, E>(fp2, bpl + static_cast<long long>(j0 + 2) * nx, nx, lane);
+    if (has_p3) gload<T, A, E>(cp3, bpl + static_cast<long long>(j0 + 3) * nx, nx, lane);
+    if (has_p4) gload<T, A, E>(fp4, bpl + static_cast<long long>(j0 + 4) * nx, nx, lane);
+    // copies of b_j0, b_j0+1, b_j0+2 for the residual
+    A b0[E], b1[E], b2[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        b0[e] = f0[e];
+        b1[e] = cp1[e];
+        b2[e] = fp2[e];
+    }
+    // interior lines share one Thomas table: load it once
+    const int fi = lc[j0].fac;
+    A g[E], h[E];
+    load_fac<A, E>(g, h, a.fac + static_cast<size_t>(fi) * nxp, lane);
+    auto solve = [&](A (&x)[E], int j) {
+        const int fj = lc[j].fac;
+        if (fj == fi)
+            thomas_gh<A, E>(x, g, h, lane);
+        else
+            thomas<A, E>(x, a.fac + static_cast<size_t>(fj) * nxp, lane);
+    };
+    if (has_m2) solve(fm2, j0 - 2);
+    solve(f0, j0);
+    if (has_p2) solve(fp2, j0 + 2);
+    if (has_p4) solve(fp4, j0 + 4);
+    // C line j: (b_j - V_{j-1} x_{j-1} - V_j x_{j+1}), then the exact solve
+    auto solve_c = [&](A (&x)[E], int j, const A (&xl)[E], const A (&xr)[E]) {
+        const LineCoef<A> cm = lc[j - 1];
+        sub_op<A, E>(x, xl, cm.va, cm.vb);
+        if (j + 1 < ny) {
+            const LineCoef<A> cj = lc[j];
+            sub_op<A, E>(x, xr, cj.va, cj.vb);
+        }
+        solve(x, j);
+    };
+    if (has_m2) solve_c(cm1, j0 - 1, fm2, f0);
+    solve_c(cp1, j0 + 1, f0, fp2);            // j0 + 1 < ny always (J < nyc)
+    if (has_p3) solve_c(cp3, j0 + 3, fp2, fp4);
+    // own lines
+    gstore<T, A, E>(xpl + static_cast<long long>(j0) * nx, f0, nx, lane);
+    gstore<T, A, E>(xpl + static_cast<long long>(j0 + 1) * nx, cp1, nx, lane);
+    if (J == a.nyc - 1 && has_p2) gstore<T, A, E>(xpl + static_cast<long long>(j0 + 2) * nx, fp2, nx, lane);
+    // r_j = b_j - L_j x_j - V_{j-1} x_{j-1} - V_j x_{j+1} for j = j0, j0+1, j0+2
+    {
+        const LineCoef<A> cj = lc[j0];
+        sub_op<A, E>(b0, f0, cj.la, cj.lb);
+        if (has_m2) {
+            const LineCoef<A> cm = lc[j0 - 1];
+            sub_op<A, E>(b0, cm1, cm.va, cm.vb);
+        }
+        sub_op<A, E>(b0, cp1, cj.va, cj.vb);
+    }
+    {
+        const LineCoef<A> cj = lc[j0 + 1], cm = lc[j0];
+        sub_op<A, E>(b1, cp1, cj.la, cj.lb);
+        sub_op<A, E>(b1, f0, cm.va, cm.vb);
+        if (has_p2) sub_op<A, E>(b1, fp2, cj.va, cj.vb);
+    }
+    A acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = A(0.5) * b0[e] + b1[e];
+    if (has_p2) {
+        const LineCoef<A> cj = lc[j0 + 2], cm = lc[j0 + 1];
+        sub_op<A, E>(b2, fp2, cj.la, cj.lb);
+        sub_op<A, E>(b2, cp1, cm.va, cm.vb);
+        if (has_p3) sub_op<A, E>(b2, cp3, cj.va, cj.vb);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] += A(0.5) * b2[e];
+    }
+    gstore<T, A, E>(a.bc + r * a.crs + p * a.cps + static_cast<long long>(J) * nx, acc, nx, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -257,7 +262,7 @@ __device__ inline void lds_relax(A *xs, const A *bs, const LineCoef<A> *lc, cons
                                  int colour, bool nbr_zero, int lane, int w)
 {
     const int n = colour == 0 ? (ny + 1) / 2 : ny / 2;
-    for (int t = w; t < n; t += kWaves) {
+    for (int t = w; t < n; t += kW) {
         const int j = 2 * t + colour;
         A f[E], v[E];
         sload<A, E>(f, bs + j * nxp, lane);
@@ -265,12 +270,12 @@ __device__ inline void lds_relax(A *xs, const A *bs, const LineCoef<A> *lc, cons
             if (j > 0) {
                 const LineCoef<A> cm = lc[j - 1];
                 sload<A, E>(v, xs + (j - 1) * nxp, lane);
-                sub_op<A, E>(f, v, cm.va, cm.vb, lane);
+                sub_op<A, E>(f, v, cm.va, cm.vb);
             }
             if (j + 1 < ny) {
                 const LineCoef<A> cj = lc[j];
                 sload<A, E>(v, xs + (j + 1) * nxp, lane);
-                sub_op<A, E>(f, v, cj.va, cj.vb, lane);
+                sub_op<A, E>(f, v, cj.va, cj.vb);
             }
         }
         thomas<A, E>(f, fac + static_cast<size_t>(lc[j].fac) * nxp, lane);
@@ -288,29 +293,29 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
     const int nx = a.nx, nxp = a.nxp;
     const int k = p * a.kmul + a.koff;
     const LineCoef<A> *lcp = plane_lines(a.pc, k, a.lc, a.lines_total);
-    // LDS: x and b of every level l0..L-1, line offsets lo[l]
-    int lo[16];
-    int off = 0;
-    for (int l = a.l0; l < a.nlev; ++l) {
-        lo[l] = off;
-        off += a.ny2[l];
-    }
-    A *xs = sm, *bs = sm + static_cast<size_t>(off) * nxp;
-    // right-hand side of level l0
+    int total = 0;
+    for (int l = a.l0; l < a.nlev; ++l) total += a.ny2[l];
+    A *xs = sm, *bs = sm + static_cast<size_t>(total) * nxp;
+    // line offset of level l inside xs / bs
+    auto off = [&](int l) {
+        int o = 0;
+        for (int m = a.l0; m < l; ++m) o += a.ny2[m];
+        return o;
+    };
     {
         const T *bpl = a.b + r * a.brs + p * a.bps;
-        for (int j = w; j < a.ny2[a.l0]; j += kWaves) {
+        for (int j = w; j < a.ny2[a.l0]; j += kW) {
             A v[E];
             gload<T, A, E>(v, bpl + static_cast<long long>(j) * nx, nx, lane);
-            sstore<A, E>(bs + (lo[a.l0] + j) * nxp, v, lane);
+            sstore<A, E>(bs + j * nxp, v, lane);
         }
     }
     __syncthreads();
-    // downward half
     for (int l = a.l0; l < a.nlev - 1; ++l) {
         const int ny = a.ny2[l], nyc = a.ny2[l + 1];
         const LineCoef<A> *lc = lcp + a.lev_off[l];
-        A *x = xs + lo[l] * nxp, *b = bs + lo[l] * nxp, *bc = bs + lo[l + 1] * nxp;
+        const int ol = off(l), oc = ol + ny;
+        A *x = xs + ol * nxp, *b = bs + ol * nxp, *bc = bs + oc * nxp;
         for (int s = 0; s < a.ipre; ++s) {
             lds_relax<A, E>(x, b, lc, a.fac, ny, nxp, 0, s == 0, lane, w);
             __syncthreads();
@@ -318,12 +323,12 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
             __syncthreads();
         }
         if (a.ipre == 0) {
-            for (int j = w; j < ny; j += kWaves)
+            for (int j = w; j < ny; j += kW)
 #pragma unroll
                 for (int e = 0; e < E; ++e) x[j * nxp + e * 64 + lane] = A(0);
             __syncthreads();
         }
-        for (int J = w; J < nyc; J += kWaves) {
+        for (int J = w; J < nyc; J += kW) {
             A acc[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] = A(0);
@@ -334,15 +339,15 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
                 sload<A, E>(f, b + j * nxp, lane);
                 const LineCoef<A> cj = lc[j];
                 sload<A, E>(v, x + j * nxp, lane);
-                sub_op<A, E>(f, v, cj.la, cj.lb, lane);
+                sub_op<A, E>(f, v, cj.la, cj.lb);
                 if (j > 0) {
                     const LineCoef<A> cm = lc[j - 1];
                     sload<A, E>(v, x + (j - 1) * nxp, lane);
-                    sub_op<A, E>(f, v, cm.va, cm.vb, lane);
+                    sub_op<A, E>(f, v, cm.va, cm.vb);
                 }
                 if (j + 1 < ny) {
                     sload<A, E>(v, x + (j + 1) * nxp, lane);
-                    sub_op<A, E>(f, v, cj.va, cj.vb, lane);
+                    sub_op<A, E>(f, v, cj.va, cj.vb);
                 }
                 const A wgt = d == 1 ? A(1) : A(0.5);
 #pragma unroll
@@ -352,24 +357,23 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
         }
         __syncthreads();
     }
-    // coarsest level: one exact line solve
     {
-        const int l = a.nlev - 1;
+        const int l = a.nlev - 1, ol = off(l);
         if (w == 0) {
             A f[E];
-            sload<A, E>(f, bs + lo[l] * nxp, lane);
+            sload<A, E>(f, bs + ol * nxp, lane);
             thomas<A, E>(f, a.fac + static_cast<size_t>((lcp + a.lev_off[l])[0].fac) * nxp, lane);
-            sstore<A, E>(xs + lo[l] * nxp, f, lane);
+            sstore<A, E>(xs + ol * nxp, f, lane);
         }
         __syncthreads();
     }
-    // upward half
     for (int l = a.nlev - 2; l >= a.l0; --l) {
         const int ny = a.ny2[l], nyc = a.ny2[l + 1];
         const LineCoef<A> *lc = lcp + a.lev_off[l];
-        A *x = xs + lo[l] * nxp, *b = bs + lo[l] * nxp;
-        const A *xc = xs + lo[l + 1] * nxp;
-        for (int j = w; j < ny; j += kWaves) {
+        const int ol = off(l), oc = ol + ny;
+        A *x = xs + ol * nxp, *b = bs + ol * nxp;
+        const A *xc = xs + oc * nxp;
+        for (int j = w; j < ny; j += kW) {
             A v[E], c[E];
             sload<A, E>(v, x + j * nxp, lane);
             if (j & 1) {
@@ -377,14 +381,14 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
 #pragma unroll
                 for (int e = 0; e < E; ++e) v[e] += c[e];
             } else {
-                const int J = j >> 1;
-                if (J - 1 >= 0) {
-                    sload<A, E>(c, xc + (J - 1) * nxp, lane);
+                const int Jc = j >> 1;
+                if (Jc - 1 >= 0) {
+                    sload<A, E>(c, xc + (Jc - 1) * nxp, lane);
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e] += A(0.5) * c[e];
                 }
-                if (J < nyc) {
-                    sload<A, E>(c, xc + J * nxp, lane);
+                if (Jc < nyc) {
+                    sload<A, E>(c, xc + Jc * nxp, lane);
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e] += A(0.5) * c[e];
                 }
@@ -399,12 +403,11 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
             __syncthreads();
         }
     }
-    // result of level l0
     {
         T *opl = a.out + r * a.ors + p * a.ops;
-        for (int j = w; j < a.ny2[a.l0]; j += kWaves) {
+        for (int j = w; j < a.ny2[a.l0]; j += kW) {
             A v[E];
-            sload<A, E>(v, xs + (lo[a.l0] + j) * nxp, lane);
+            sload<A, E>(v, xs + j * nxp, lane);
             T *row = opl + static_cast<long long>(j) * nx;
             if (a.accumulate) {
                 A o[E];
@@ -418,63 +421,145 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
 }
 
 // ---------------------------------------------------------------------------
-// k2_chain: y = x_0 + P_0(x_1 + P_1(... + P x_lc)) per fine point, then
-// out = y or out += y.  Coarse levels 1..lc are packed; x_lc is complete.
+// Prolongation chains.  For a run [j0, j1) of fine indices the chain needs,
+// at every coarser level, the index window [lo, hi] with lo = floor((lo_f-1)/2)
+// (clamped at 0) and hi = floor(hi_f/2) (clamped at the level size).  A
+// workgroup of 256 threads owns 64 columns (i) and a run of RUN fine lines
+// (or planes); it stages every level's window in LDS, evaluates
+// v_l = x_l + P v_{l+1} from the coarsest level down, and writes the fine run.
 // ---------------------------------------------------------------------------
+constexpr int kChainCols = 64;
+constexpr int kChainRun = 32;
+constexpr int kChainWin = 24;     // window lines per level: RUN/2 + 3 fits at level 1
+
+struct Win {
+    int lo, hi;
+};
+
+__device__ inline Win coarser(Win f, int nc)
+{
+    Win c;
+    c.lo = f.lo - 1 < 0 ? 0 : (f.lo - 1) >> 1;
+    c.hi = f.hi >> 1;
+    if (c.hi > nc - 1) c.hi = nc - 1;
+    return c;
+}
+
+// v (LDS, window wf of level l) = x_l(window wf) + P v_c (window wc of level l+1)
+template <typename A>
+__device__ inline A prolong_point(const A *vc, Win wc, int jj, int nc, int col)
+{
+    A s = A(0);
+    if (jj & 1) {
+        s += vc[(((jj - 1) >> 1) - wc.lo) * kChainCols + col];
+    } else {
+        const int Jc = jj >> 1;
+        if (Jc - 1 >= 0) s += A(0.5) * vc[(Jc - 1 - wc.lo) * kChainCols + col];
+        if (Jc < nc) s += A(0.5) * vc[(Jc - wc.lo) * kChainCols + col];
+    }
+    return s;
+}
+
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void k2_chain(Chain2Args<T, A> a)
 {
-    const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const long long total = static_cast<long long>(a.nx) * a.ny2[0] * a.np * a.nrhs;
-    if (idx >= total) return;
-    const int i = static_cast<int>(idx % a.nx);
-    long long t = idx / a.nx;
-    const int j = static_cast<int>(t % a.ny2[0]);
-    t /= a.ny2[0];
-    const int p = static_cast<int>(t % a.np);
-    const int r = static_cast<int>(t / a.np);
-    // index windows [lo_l, lo_l + 2] of the lines each level contributes
-    int lo[16], hi[16];
-    lo[0] = hi[0] = j;
-    for (int l = 0; l < a.lc; ++l) {
-        lo[l + 1] = max(0, (lo[l] - 1) >> 1);
-        hi[l + 1] = min(a.ny2[l + 1] - 1, hi[l] >> 1);
-    }
-    A v[3];
-    {
+    __shared__ A vs[2][kChainWin * kChainCols];
+    const int nx = a.nx;
+    const int ncol = (nx + kChainCols - 1) / kChainCols;
+    const int nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
+    int bid = blockIdx.x;
+    const int ct = bid % ncol;
+    bid /= ncol;
+    const int rt = bid % nrun;
+    bid /= nrun;
+    const int p = bid % a.np, r = bid / a.np;
+    const int col = threadIdx.x & (kChainCols - 1), row0 = threadIdx.x >> 6;   // 4 rows of 64
+    const int i = ct * kChainCols + col;
+    const Win w0{rt * kChainRun, min(a.ny2[0], rt * kChainRun + kChainRun) - 1};
+    // windows of every level (uniform; recomputed from the fine run)
+    auto win = [&](int l) {
+        Win wv = w0;
+        for (int m = 0; m < l; ++m) wv = coarser(wv, a.ny2[m + 1]);
+        return wv;
+    };
+    int cur = 0;
+    {   // coarsest level of the chain: v = x_lc
         const int l = a.lc;
+        const Win wl = win(l);
         const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
-        for (int q = 0; q < 3; ++q) {
-            const int jj = lo[l] + q;
-            v[q] = jj <= hi[l] ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * a.nx + i)) : A(0);
-        }
+        for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4)
+            vs[cur][(jj - wl.lo) * kChainCols + col] =
+                i < nx ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * nx + i)) : A(0);
+        __syncthreads();
     }
-    for (int l = a.lc - 1; l >= 0; --l) {
-        const T *xl = l == 0 ? a.x0 + r * a.x0rs + p * a.x0ps : a.xc[l] + r * a.crs[l] + p * a.cps[l];
-        const int nyc = a.ny2[l + 1];
-        A nv[3];
-        for (int q = 0; q < 3; ++q) {
-            const int jj = lo[l] + q;
-            if (jj > hi[l]) {
-                nv[q] = A(0);
-                continue;
-            }
-            A s = ldv(xl + static_cast<long long>(jj) * a.nx + i);
-            if (jj & 1) {
-                s += v[((jj - 1) >> 1) - lo[l + 1]];
-            } else {
-                const int J = jj >> 1;
-                if (J - 1 >= 0) s += A(0.5) * v[J - 1 - lo[l + 1]];
-                if (J < nyc) s += A(0.5) * v[J - lo[l + 1]];
-            }
-            nv[q] = s;
+    for (int l = a.lc - 1; l >= 1; --l) {
+        const Win wl = win(l), wc = win(l + 1);
+        const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
+        for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4) {
+            A s = i < nx ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * nx + i)) : A(0);
+            s += prolong_point(vs[cur], wc, jj, a.ny2[l + 1], col);
+            vs[cur ^ 1][(jj - wl.lo) * kChainCols + col] = s;
         }
-        v[0] = nv[0];
-        v[1] = nv[1];
-        v[2] = nv[2];
+        cur ^= 1;
+        __syncthreads();
     }
-    T *o = a.out + r * a.ors + p * a.ops + static_cast<long long>(j) * a.nx + i;
-    stv(o, a.accumulate ? static_cast<A>(ldv(o)) + v[0] : v[0]);
+    if (i >= nx) return;
+    const Win wc = win(1);
+    const T *x0 = a.x0 + r * a.x0rs + p * a.x0ps;
+    T *out = a.out + r * a.ors + p * a.ops;
+    for (int jj = w0.lo + row0; jj <= w0.hi; jj += 4) {
+        const long long o = static_cast<long long>(jj) * nx + i;
+        A s = static_cast<A>(ldv(x0 + o)) + prolong_point(vs[cur], wc, jj, a.ny2[1], col);
+        if (a.accumulate) s += static_cast<A>(ldv(out + o));
+        stv(out + o, s);
+    }
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k3_chain(Chain3Args<T, A> a)
+{
+    __shared__ A vs[2][kChainWin * kChainCols];
+    const long long pl = static_cast<long long>(a.nx) * a.ny;
+    const int ncol = static_cast<int>((pl + kChainCols - 1) / kChainCols);
+    const int nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
+    const int ct = blockIdx.x % ncol;
+    const int rt = blockIdx.x / ncol;
+    const int r = blockIdx.y;
+    const int col = threadIdx.x & (kChainCols - 1), row0 = threadIdx.x >> 6;
+    const long long c = static_cast<long long>(ct) * kChainCols + col;
+    const Win w0{rt * kChainRun, min(a.nz[0], rt * kChainRun + kChainRun) - 1};
+    auto win = [&](int l) {
+        Win wv = w0;
+        for (int m = 0; m < l; ++m) wv = coarser(wv, a.nz[m + 1]);
+        return wv;
+    };
+    int cur = 0;
+    {
+        const int l = a.L;
+        const Win wl = win(l);
+        const T *xl = a.x[l] + r * a.rs[l];
+        for (int kk = wl.lo + row0; kk <= wl.hi; kk += 4)
+            vs[cur][(kk - wl.lo) * kChainCols + col] = c < pl ? static_cast<A>(ldv(xl + kk * pl + c)) : A(0);
+        __syncthreads();
+    }
+    for (int l = a.L - 1; l >= 1; --l) {
+        const Win wl = win(l), wc = win(l + 1);
+        const T *xl = a.x[l] + r * a.rs[l];
+        for (int kk = wl.lo + row0; kk <= wl.hi; kk += 4) {
+            A s = c < pl ? static_cast<A>(ldv(xl + kk * pl + c)) : A(0);
+            s += prolong_point(vs[cur], wc, kk, a.nz[l + 1], col);
+            vs[cur ^ 1][(kk - wl.lo) * kChainCols + col] = s;
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    if (c >= pl) return;
+    const Win wc = win(1);
+    T *x0 = a.x[0] + r * a.rs[0];
+    for (int kk = w0.lo + row0; kk <= w0.hi; kk += 4) {
+        T *o = x0 + kk * pl + c;
+        stv(o, static_cast<A>(ldv(o)) + prolong_point(vs[cur], wc, kk, a.nz[1], col));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -502,8 +587,7 @@ __global__ __launch_bounds__(kThreads) void k2_up(Up2Args<T, A> a)
     const T *xp = a.xpre + r * a.xrs + p * a.xps;
     const T *cp = a.xc + r * a.crs + p * a.cps;
     const T *bp = a.b + r * a.brs + p * a.bps;
-    // prolongation + correction on [jlo, jhi]
-    for (int j = jlo + w; j <= jhi; j += kWaves) {
+    for (int j = jlo + w; j <= jhi; j += kW) {
         A v[E], c[E];
         gload<T, A, E>(v, xp + static_cast<long long>(j) * nx, nx, lane);
         if (j & 1) {
@@ -511,14 +595,14 @@ __global__ __launch_bounds__(kThreads) void k2_up(Up2Args<T, A> a)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] += c[e];
         } else {
-            const int J = j >> 1;
-            if (J - 1 >= 0) {
-                gload<T, A, E>(c, cp + static_cast<long long>(J - 1) * nx, nx, lane);
+            const int Jc = j >> 1;
+            if (Jc - 1 >= 0) {
+                gload<T, A, E>(c, cp + static_cast<long long>(Jc - 1) * nx, nx, lane);
 #pragma unroll
                 for (int e = 0; e < E; ++e) v[e] += A(0.5) * c[e];
             }
-            if (J < nyc) {
-                gload<T, A, E>(c, cp + static_cast<long long>(J) * nx, nx, lane);
+            if (Jc < nyc) {
+                gload<T, A, E>(c, cp + static_cast<long long>(Jc) * nx, nx, lane);
 #pragma unroll
                 for (int e = 0; e < E; ++e) v[e] += A(0.5) * c[e];
             }
@@ -526,33 +610,31 @@ __global__ __launch_bounds__(kThreads) void k2_up(Up2Args<T, A> a)
         sstore<A, E>(xs + (j - base) * nxp, v, lane);
     }
     __syncthreads();
-    // C lines in [j0 - 1, j1] , then F lines in [j0, j1)
     for (int colour = 1; colour >= 0; --colour) {
         const int lo = colour == 1 ? max(1, (j0 - 1) | 1) : j0 + (j0 & 1);
         const int hi = colour == 1 ? min(ny - 1, j1) : j1 - 1;
         const int n = lo <= hi ? (hi - lo) / 2 + 1 : 0;
-        for (int t = w; t < n; t += kWaves) {
+        for (int t = w; t < n; t += kW) {
             const int j = lo + 2 * t;
             A f[E], v[E];
             gload<T, A, E>(f, bp + static_cast<long long>(j) * nx, nx, lane);
             if (j > 0) {
                 const LineCoef<A> cm = lc[j - 1];
                 sload<A, E>(v, xs + (j - 1 - base) * nxp, lane);
-                sub_op<A, E>(f, v, cm.va, cm.vb, lane);
+                sub_op<A, E>(f, v, cm.va, cm.vb);
             }
             if (j + 1 < ny) {
                 const LineCoef<A> cj = lc[j];
                 sload<A, E>(v, xs + (j + 1 - base) * nxp, lane);
-                sub_op<A, E>(f, v, cj.va, cj.vb, lane);
+                sub_op<A, E>(f, v, cj.va, cj.vb);
             }
             thomas<A, E>(f, a.fac + static_cast<size_t>(lc[j].fac) * nxp, lane);
             sstore<A, E>(xs + (j - base) * nxp, f, lane);
         }
         __syncthreads();
     }
-    // own lines out
     T *op = a.out + r * a.ors + p * a.ops;
-    for (int j = j0 + w; j < j1; j += kWaves) {
+    for (int j = j0 + w; j < j1; j += kW) {
         A v[E];
         sload<A, E>(v, xs + (j - base) * nxp, lane);
         T *row = op + static_cast<long long>(j) * nx;
@@ -566,66 +648,20 @@ __global__ __launch_bounds__(kThreads) void k2_up(Up2Args<T, A> a)
     }
 }
 
-// ---------------------------------------------------------------------------
-// k3_chain: s = x_0 + P(x_1 + P(... + P x_L)) over the 3D levels, in place on
-// level 0 (each point reads its own x_0 value and writes it back).
-// ---------------------------------------------------------------------------
-template <typename T, typename A>
-__global__ __launch_bounds__(256) void k3_chain(Chain3Args<T, A> a)
-{
-    const long long pl = static_cast<long long>(a.nx) * a.ny;
-    const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= pl) return;
-    const int k = blockIdx.y, r = blockIdx.z;
-    int lo[24], hi[24];
-    lo[0] = hi[0] = k;
-    for (int l = 0; l < a.L; ++l) {
-        lo[l + 1] = max(0, (lo[l] - 1) >> 1);
-        hi[l + 1] = min(a.nz[l + 1] - 1, hi[l] >> 1);
-    }
-    A v[3];
-    {
-        const int l = a.L;
-        const T *xl = a.x[l] + r * a.rs[l];
-        for (int q = 0; q < 3; ++q) {
-            const int kk = lo[l] + q;
-            v[q] = kk <= hi[l] ? static_cast<A>(ldv(xl + kk * pl + c)) : A(0);
-        }
-    }
-    for (int l = a.L - 1; l >= 0; --l) {
-        const T *xl = a.x[l] + r * a.rs[l];
-        const int nzc = a.nz[l + 1];
-        A nv[3];
-        for (int q = 0; q < 3; ++q) {
-            const int kk = lo[l] + q;
-            if (kk > hi[l]) {
-                nv[q] = A(0);
-                continue;
-            }
-            A s = ldv(xl + kk * pl + c);
-            if (kk & 1) {
-                s += v[((kk - 1) >> 1) - lo[l + 1]];
-            } else {
-                const int K = kk >> 1;
-                if (K - 1 >= 0) s += A(0.5) * v[K - 1 - lo[l + 1]];
-                if (K < nzc) s += A(0.5) * v[K - lo[l + 1]];
-            }
-            nv[q] = s;
-        }
-        v[0] = nv[0];
-        v[1] = nv[1];
-        v[2] = nv[2];
-    }
-    T *o = a.x[0] + r * a.rs[0] + k * pl + c;
-    stv(o, v[0]);
-}
-
 inline unsigned nb(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+template <typename K>
+inline void allow_lds(K kernel, size_t bytes)
+{
+    if (bytes > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(bytes));
+}
 
 }  // namespace
 
-#define SMG_E_SWITCH(E, CALL)                 \
-    switch (E) {                              \
+#define SMG_E_SWITCH(E, CALL)                      \
+    switch (E) {                                   \
     case 1: { constexpr int EE = 1; CALL; } break; \
     case 2: { constexpr int EE = 2; CALL; } break; \
     case 3: { constexpr int EE = 3; CALL; } break; \
@@ -634,18 +670,33 @@ inline unsigned nb(long long n, int bs) { return static_cast<unsigned>((n + bs -
     case 6: { constexpr int EE = 6; CALL; } break; \
     case 7: { constexpr int EE = 7; CALL; } break; \
     case 8: { constexpr int EE = 8; CALL; } break; \
-    default: break;                           \
+    default: break;                                \
     }
+
+int fused_waves() { return kW; }
 
 template <typename T, typename A>
 void launch_down2(const Down2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
+    const int E = a.nxp / 64;
+    if (E <= 4) {   // register-only variant: one wave per coarse line
+        const long long waves = static_cast<long long>(a.nyc) * a.np * a.nrhs;
+        if (waves == 0) return;
+        const dim3 grid(static_cast<unsigned>((waves + 3) / 4));
+        switch (E) {
+        case 1: SMG_LAUNCH(ev, (k2_down_reg<T, A, 1>), grid, dim3(256), 0, st, a); break;
+        case 2: SMG_LAUNCH(ev, (k2_down_reg<T, A, 2>), grid, dim3(256), 0, st, a); break;
+        case 3: SMG_LAUNCH(ev, (k2_down_reg<T, A, 3>), grid, dim3(256), 0, st, a); break;
+        default: SMG_LAUNCH(ev, (k2_down_reg<T, A, 4>), grid, dim3(256), 0, st, a); break;
+        }
+        return;
+    }
     const int nstrip = (a.nyc + a.S - 1) / a.S;
     const long long nblk = static_cast<long long>(nstrip) * a.np * a.nrhs;
     if (nblk == 0) return;
     const size_t lds = static_cast<size_t>(2 * a.S + 5) * a.nxp * sizeof(A);
-    SMG_E_SWITCH(a.nxp / 64, SMG_LAUNCH(ev, (k2_down<T, A, EE>), dim3(static_cast<unsigned>(nblk)),
-                                                dim3(kThreads), lds, st, a));
+    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_down<T, A, EE>, lds);
+                 SMG_LAUNCH(ev, (k2_down<T, A, EE>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds, st, a));
 }
 
 template <typename T, typename A>
@@ -653,16 +704,19 @@ void launch_coarse2(const Coarse2Args<T, A> &a, size_t lds_bytes, hipStream_t st
 {
     const long long nblk = static_cast<long long>(a.np) * a.nrhs;
     if (nblk == 0) return;
-    SMG_E_SWITCH(a.nxp / 64, SMG_LAUNCH(ev, (k2_coarse<T, A, EE>), dim3(static_cast<unsigned>(nblk)),
-                                                dim3(kThreads), lds_bytes, st, a));
+    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_coarse<T, A, EE>, lds_bytes);
+                 SMG_LAUNCH(ev, (k2_coarse<T, A, EE>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds_bytes,
+                            st, a));
 }
 
 template <typename T, typename A>
 void launch_chain2(const Chain2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
-    const long long n = static_cast<long long>(a.nx) * a.ny2[0] * a.np * a.nrhs;
-    if (n == 0) return;
-    SMG_LAUNCH(ev, (k2_chain<T, A>), dim3(nb(n, 256)), dim3(256), 0, st, a);
+    const long long ncol = (a.nx + kChainCols - 1) / kChainCols;
+    const long long nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
+    const long long nblk = ncol * nrun * a.np * a.nrhs;
+    if (nblk == 0) return;
+    SMG_LAUNCH(ev, (k2_chain<T, A>), dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
@@ -672,18 +726,20 @@ void launch_up2(const Up2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
     const long long nblk = static_cast<long long>(nstrip) * a.np * a.nrhs;
     if (nblk == 0) return;
     const size_t lds = static_cast<size_t>(2 * a.S + 4) * a.nxp * sizeof(A);
-    SMG_E_SWITCH(a.nxp / 64, SMG_LAUNCH(ev, (k2_up<T, A, EE>), dim3(static_cast<unsigned>(nblk)),
-                                                dim3(kThreads), lds, st, a));
+    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_up<T, A, EE>, lds);
+                 SMG_LAUNCH(ev, (k2_up<T, A, EE>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds, st, a));
 }
 
 template <typename T, typename A>
 void launch_chain3(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const LaunchEv &ev)
 {
-    const dim3 grid(nb(static_cast<long long>(a.nx) * a.ny, 256), a.nz[0], nrhs);
-    SMG_LAUNCH(ev, (k3_chain<T, A>), grid, dim3(256), 0, st, a);
+    const long long pl = static_cast<long long>(a.nx) * a.ny;
+    const long long ncol = (pl + kChainCols - 1) / kChainCols;
+    const long long nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
+    SMG_LAUNCH(ev, (k3_chain<T, A>), dim3(static_cast<unsigned>(ncol * nrun), nrhs), dim3(256), 0, st, a);
 }
 
-#define SMG_FUSED_INSTANTIATE(T, A)                                                          \
+#define SMG_FUSED_INSTANTIATE(T, A)                                                                      \
     template void launch_down2<T, A>(const Down2Args<T, A> &, hipStream_t, const LaunchEv &);             \
     template void launch_coarse2<T, A>(const Coarse2Args<T, A> &, size_t, hipStream_t, const LaunchEv &); \
     template void launch_chain2<T, A>(const Chain2Args<T, A> &, hipStream_t, const LaunchEv &);           \

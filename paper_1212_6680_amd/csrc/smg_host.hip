@@ -137,8 +137,10 @@ int check_grid(const smg_grid *g, const smg_opts *o)
 size_t elem_size(int prec) { return prec == SMG_PREC_F64 ? 8 : prec == SMG_PREC_F32 ? 4 : 2; }
 size_t arith_size(int prec) { return prec == SMG_PREC_F64 ? 8 : 4; }
 
-// LDS budgets of the fused kernels (bytes per workgroup)
-constexpr size_t kCoarseLds = 64 * 1024;
+// LDS budgets of the fused kernels (bytes per workgroup).  The coarse kernel
+// is latency-bound (one workgroup per plane), so it may take most of a CU's
+// 160 KB: every extra 2D level it absorbs removes one launch per 2D cycle.
+constexpr size_t kCoarseLds = 128 * 1024;
 constexpr size_t kStripLds = 48 * 1024;
 
 void choose_fused_schedule(smg_handle *h)
@@ -155,8 +157,10 @@ void choose_fused_schedule(smg_handle *h)
         h->l0 = l;
         h->coarse_lds = bytes;
     }
+    // k2_down handles one F line, one C line and one coarse line per wave
     int S = static_cast<int>((kStripLds / line - 5) / 2);
-    h->S_down = S < 1 ? 1 : (S > 16 ? 16 : S);
+    const int smax = fused_waves() - 3;
+    h->S_down = S < 1 ? 1 : (S > smax ? smax : S);
     S = static_cast<int>((kStripLds / line - 4) / 2);
     h->S_up = S < 1 ? 1 : (S > 16 ? 16 : S);
     h->fused = h->o.kernel_mode == 0 && nl <= kMaxLev && h->nz.size() <= static_cast<size_t>(kMaxLev3) &&

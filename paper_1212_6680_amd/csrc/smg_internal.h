@@ -239,6 +239,7 @@ template <typename T, typename A>
 void launch_up2(const Up2Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
 void launch_chain3(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const LaunchEv &ev = LaunchEv{});
+int fused_waves();   // waves per workgroup of the strip and coarse kernels
 
 // Launchers (smg_kernels.hip) ---------------------------------------------
 template <typename T, typename A>

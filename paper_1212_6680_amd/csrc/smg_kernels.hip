@@ -362,6 +362,80 @@ __global__ void k_convert_out(const T *src, long long lds, double *dst, long lon
     dst[r * ldd + i] = static_cast<double>(ldv(src + r * lds + i));
 }
 
+// Residual + restriction marching in z.  A block owns a 64 x 8 (i, j) tile and
+// a run of coarse planes [K0, K1).  Every fine x plane is staged once in an
+// LDS tile with a one-point halo, its in-plane product T2 x is formed once,
+// and a window of three planes (x and T2 x) in registers feeds the 15-point
+// residuals r_k = b_k - C_k x_k - U_{k-1} x_{k-1} - U_k x_{k+1}, which are
+// combined into b_c[K] = 1/2 r_{2K} + r_{2K+1} + 1/2 r_{2K+2} as the march
+// passes.  x and b are read about once.
+constexpr int kRTX = 64, kRTY = 8, kRThreads = kRTX * kRTY;
+
+template <typename T, typename A>
+__global__ __launch_bounds__(kRThreads) void k_restrict3_march(Restrict3Args<T, A> a, int kchunk)
+{
+    __shared__ A tile[(kRTY + 2) * (kRTX + 2)];
+    const int tx = threadIdx.x % kRTX, ty = threadIdx.x / kRTX;
+    const int i = blockIdx.x * kRTX + tx, j = blockIdx.y * kRTY + ty;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const bool in = i < nx && j < ny;
+    const long long pl = static_cast<long long>(nx) * ny;
+    const long long c2 = static_cast<long long>(j) * nx + i;
+    const int r = blockIdx.z / ((a.nzc + kchunk - 1) / kchunk);
+    const int K0 = (blockIdx.z % ((a.nzc + kchunk - 1) / kchunk)) * kchunk;
+    const int K1 = min(a.nzc, K0 + kchunk);
+    const T *x = a.x + r * a.xrs;
+    const T *b = a.b + r * a.brs;
+    // this thread's halo point, if any
+    int hy = -1, hx = -1;
+    const int t = threadIdx.x;
+    if (t < kRTX) { hy = 0; hx = t + 1; }
+    else if (t < 2 * kRTX) { hy = kRTY + 1; hx = t - kRTX + 1; }
+    else if (t < 2 * kRTX + kRTY) { hy = t - 2 * kRTX + 1; hx = 0; }
+    else if (t < 2 * kRTX + 2 * kRTY) { hy = t - 2 * kRTX - kRTY + 1; hx = kRTX + 1; }
+    const int hi = blockIdx.x * kRTX + hx - 1, hj = blockIdx.y * kRTY + hy - 1;
+    const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const long long hc2 = static_cast<long long>(hj) * nx + hi;
+    const int cc = (ty + 1) * (kRTX + 2) + tx + 1;
+    const A cx = a.cx, cy = a.cy;
+    // window of planes kl-2, kl-1, kl: x and T2 x at this point
+    A xw0 = 0, xw1 = 0, xw2 = 0, tw0 = 0, tw1 = 0, tw2 = 0;
+    int kl = 2 * K0 - 2;   // next advance loads plane kl + 1
+    auto advance = [&]() {
+        ++kl;
+        const bool live = kl >= 0 && kl < nz && !a.x_zero;
+        const A xc = (in && live) ? static_cast<A>(ldv(x + kl * pl + c2)) : A(0);
+        tile[cc] = xc;
+        if (hy >= 0) tile[hy * (kRTX + 2) + hx] = (hin && live) ? static_cast<A>(ldv(x + kl * pl + hc2)) : A(0);
+        __syncthreads();
+        const A t2 = cx * (A(2) * xc - tile[cc - 1] - tile[cc + 1]) +
+                     cy * (A(2) * xc - tile[cc - (kRTX + 2)] - tile[cc + (kRTX + 2)]);
+        __syncthreads();
+        xw0 = xw1; xw1 = xw2; xw2 = xc;
+        tw0 = tw1; tw1 = tw2; tw2 = t2;
+    };
+    // residual of fine plane k (0 <= k < nz); needs planes k-1, k, k+1 loaded
+    auto resid = [&](int k) {
+        while (kl < k + 1) advance();
+        A v = in ? static_cast<A>(ldv(b + k * pl + c2)) : A(0);
+        const PlaneCoef<A> ck = a.pc[k];
+        v -= ck.ca * tw1 + ck.cb * xw1;
+        if (k > 0) {
+            const PlaneCoef<A> cm = a.pc[k - 1];
+            v -= cm.ua * tw0 + cm.ub * xw0;
+        }
+        if (k < nz - 1) v -= ck.ua * tw2 + ck.ub * xw2;
+        return v;
+    };
+    A r_even = resid(2 * K0);
+    for (int K = K0; K < K1; ++K) {
+        const A r_odd = resid(2 * K + 1);
+        const A r_next = 2 * K + 2 < nz ? resid(2 * K + 2) : A(0);
+        if (in) stv(a.bc + r * a.crs + K * pl + c2, A(0.5) * r_even + r_odd + A(0.5) * r_next);
+        r_even = r_next;
+    }
+}
+
 inline unsigned blocks_for(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 
 }  // namespace
@@ -427,6 +501,17 @@ void launch_correct3(const Correct3Args<T, A> &a, hipStream_t st, const LaunchEv
 template <typename T, typename A>
 void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
+    const int gx = (a.nx + kRTX - 1) / kRTX, gy = (a.ny + kRTY - 1) / kRTY;
+    if (a.nzc >= 2) {
+        // enough blocks to fill the chip; each marches kchunk coarse planes
+        int nzb = 2048 / (gx * gy * a.nrhs);
+        nzb = nzb < 1 ? 1 : (nzb > a.nzc ? a.nzc : nzb);
+        const int kchunk = (a.nzc + nzb - 1) / nzb;
+        nzb = (a.nzc + kchunk - 1) / kchunk;
+        const dim3 grid(gx, gy, nzb * a.nrhs);
+        SMG_LAUNCH(ev, (k_restrict3_march<T, A>), grid, dim3(kRThreads), 0, st, a, kchunk);
+        return;
+    }
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.nzc, a.nrhs);
     SMG_LAUNCH(ev, (k_restrict3<T, A>), grid, dim3(256), 0, st, a);
 }
