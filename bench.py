@@ -70,6 +70,61 @@ def read_traffic(family):
         return None
 
 
+def other_configs(torch, dev):
+    """The other workloads of the hot path, each timed once after a warm-up:
+    LOBPCG (m = 16 and m = 64 smallest eigenpairs of the 128^3 Laplacian,
+    SMG(1,0) applied to the active block in one batched V-cycle) and FPCG at
+    384^3 with the SMG preconditioner in FP64, FP32 and BF16 storage."""
+    import synth
+    from paper_1212_6680_amd.smg import SMG
+
+    def smallest_eigs(nn, cc, m):
+        # Dirichlet Laplacian spectrum: sums of 4 c sin^2(k pi / (2 (n+1))) over the three axes
+        k = np.arange(1, min(nn, m) + 1)
+        l1 = 4.0 * cc * np.sin(k * np.pi / (2 * (nn + 1))) ** 2
+        return np.sort((l1[:, None, None] + l1[None, :, None] + l1[None, None, :]).ravel())[:m]
+
+    res = {}
+    n = 128
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    for m, guard in ((16, 0), (64, 3)):
+        G = SMG(shape, c, 1, 0, max_nrhs=m + guard)
+        X0 = torch.from_numpy(synth.block(n ** 3, m + guard, 3)).to(dev)
+        G.lobpcg(X0, rtol=1e-8, max_iter=2, guard=guard)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, X, info = G.lobpcg(X0, rtol=1e-8, max_iter=400, guard=guard)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ex = smallest_eigs(n, c[0], m)
+        res[f"lobpcg_128_m{m}"] = {
+            "s": dt, "iters": info.iters, "nconv": info.nconv, "guard": guard, "status": info.status,
+            "max_rel_eig_err_vs_closed_form": float(np.max(np.abs(lam[:m] - ex) / ex)),
+            "max_resnorm": float(info.resnorms[:m].max())}
+        del G, X
+        torch.cuda.empty_cache()
+    n = 384
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    b = torch.from_numpy(synth.rhs(n, n, n, 5)).to(dev)
+    x64 = None
+    for prec in ("f64", "f32", "bf16"):
+        G = SMG(shape, c, 1, 0, precision=prec)
+        x = torch.empty_like(b)
+        G.fpcg(b, x, rtol=1e-8, max_iter=3, zero_x0=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = G.fpcg(b, x, rtol=1e-8, max_iter=500, zero_x0=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if prec == "f64":
+            x64 = x.clone()
+        err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+        res[f"fpcg_384_smg_{prec}"] = {"s": dt, "iters": info.iters, "status": info.status,
+                                       "true_rel_res": info.true_rel_res, "rel_err_vs_f64_solution": err}
+        del G
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +133,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the LOBPCG and mixed-precision workloads reported beside the headline")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for counter collection: a 512 MiB device copy, then one V-cycle")
     args = ap.parse_args()
@@ -215,6 +272,9 @@ def main():
                 del Gv
         var["fpcg_10"] = {"s": sec_per_solve, "iters": iters, "status": 0, "rel_res": infos[-1].rel_res}
         out["variants"] = var
+
+    if not args.no_configs:
+        out["configs"] = other_configs(torch, dev)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

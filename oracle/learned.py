@@ -1,0 +1,137 @@
+"""FP64 oracle of the learned post-smoother network.  TEST INFRASTRUCTURE ONLY.
+
+The network (a form added beside the paper's method, not in the paper) maps a
+residual to a correction: four 3x3x3 convolutions with zero padding,
+1 -> 16 -> 16 -> 16 -> 1 channels, ReLU after the first three, a bias per
+output channel.  Written from the definition of a cross-correlation
+    out[z,y,x,o] = b[o] + sum_{dz,dy,dx,i} W[dz,dy,dx,i,o] in[z+dz-1, y+dy-1, x+dx-1, i]
+(inputs outside the grid are zero), with the backward pass derived by hand:
+    d in[z,y,x,i] = sum_{dz,dy,dx,o} W[dz,dy,dx,i,o] g[z-dz+1, y-dy+1, x-dx+1, o]
+    d W[dz,dy,dx,i,o] = sum_{z,y,x} in[z+dz-1, y+dy-1, x+dx-1, i] g[z,y,x,o]
+    d b[o] = sum_{z,y,x} g[z,y,x,o]
+where g is the gradient at the layer's output after the ReLU mask.
+Arrays are channels-last: (nz, ny, nx, C).  Weights: (3, 3, 3, Cin, Cout).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CHANNELS = (1, 16, 16, 16, 1)
+
+
+def init_params(seed: int = 0):
+    """He-style initial weights from a seeded NumPy generator (tests only)."""
+    g = np.random.default_rng(seed)
+    params = []
+    for ci, co in zip(CHANNELS[:-1], CHANNELS[1:]):
+        W = g.standard_normal((3, 3, 3, ci, co)) * np.sqrt(2.0 / (27 * ci))
+        b = 0.01 * g.standard_normal(co)
+        params.append((W, b))
+    return params
+
+
+def _pad(a):
+    return np.pad(a, ((1, 1), (1, 1), (1, 1), (0, 0)))
+
+
+def conv(inp, W, b):
+    nz, ny, nx, _ = inp.shape
+    p = _pad(inp)
+    out = np.broadcast_to(b, (nz, ny, nx, W.shape[-1])).astype(np.float64).copy()
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                out += p[dz:dz + nz, dy:dy + ny, dx:dx + nx, :] @ W[dz, dy, dx]
+    return out
+
+
+def conv_backward(inp, W, g):
+    """(d inp, d W, d b) for out = conv(inp, W, b) and output gradient g."""
+    nz, ny, nx, _ = inp.shape
+    p = _pad(inp)
+    gp = _pad(g)
+    din = np.zeros_like(inp)
+    dW = np.zeros_like(W)
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                # input point (z,y,x) feeds output (z-dz+1, y-dy+1, x-dx+1)
+                din += gp[2 - dz:2 - dz + nz, 2 - dy:2 - dy + ny, 2 - dx:2 - dx + nx, :] @ W[dz, dy, dx].T
+                dW[dz, dy, dx] = np.einsum("zyxi,zyxo->io", p[dz:dz + nz, dy:dy + ny, dx:dx + nx, :], g)
+    db = g.sum(axis=(0, 1, 2))
+    return din, dW, db
+
+
+def forward(params, x, keep=False):
+    """x: (nz, ny, nx) -> (nz, ny, nx); with keep=True also the layer outputs."""
+    a = x[..., None].astype(np.float64)
+    acts = [a]
+    for li, (W, b) in enumerate(params):
+        a = conv(a, W, b)
+        if li < len(params) - 1:
+            a = np.maximum(a, 0.0)
+        acts.append(a)
+    return (a[..., 0], acts) if keep else a[..., 0]
+
+
+def loss_and_grads(params, x, target):
+    """MSE loss mean((N(x) - target)^2) and its gradients."""
+    y, acts = forward(params, x, keep=True)
+    n = y.size
+    diff = y - target
+    loss = float(np.sum(diff * diff) / n)
+    g = (2.0 / n) * diff[..., None]
+    grads = [None] * len(params)
+    for li in range(len(params) - 1, -1, -1):
+        W, _ = params[li]
+        if li < len(params) - 1:
+            g = g * (acts[li + 1] > 0)           # ReLU mask from the layer's output
+        din, dW, db = conv_backward(acts[li], W, g)
+        grads[li] = (dW, db)
+        g = din
+    return loss, grads
+
+
+def adam_step(params, grads, state, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba 2015) with bias correction; state holds (m, v) pairs."""
+    new = []
+    for k, ((W, b), (dW, db)) in enumerate(zip(params, grads)):
+        outs = []
+        for j, (p, gr) in enumerate(((W, dW), (b, db))):
+            m, v = state[2 * k + j]
+            m = beta1 * m + (1 - beta1) * gr
+            v = beta2 * v + (1 - beta2) * gr * gr
+            state[2 * k + j] = (m, v)
+            mh = m / (1 - beta1 ** t)
+            vh = v / (1 - beta2 ** t)
+            outs.append(p - lr * mh / (np.sqrt(vh) + eps))
+        new.append(tuple(outs))
+    return new
+
+
+def zero_state(params):
+    st = []
+    for W, b in params:
+        st.append((np.zeros_like(W), np.zeros_like(W)))
+        st.append((np.zeros_like(b), np.zeros_like(b)))
+    return st
+
+
+def flatten(params) -> np.ndarray:
+    """Parameters in the library's flat order: per layer W (3,3,3,Cin,Cout) then b."""
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params])
+
+
+def unflatten(flat: np.ndarray):
+    out, off = [], 0
+    for ci, co in zip(CHANNELS[:-1], CHANNELS[1:]):
+        nw = 27 * ci * co
+        W = flat[off:off + nw].reshape(3, 3, 3, ci, co)
+        off += nw
+        b = flat[off:off + co]
+        off += co
+        out.append((W.copy(), b.copy()))
+    return out
+
+
+NPARAMS = sum(27 * ci * co + co for ci, co in zip(CHANNELS[:-1], CHANNELS[1:]))

@@ -1,0 +1,88 @@
+"""Pins of the learned-smoother network oracle (FP64 NumPy):
+the convolution against torch's CPU conv3d (an independent implementation),
+the hand-derived backward pass against central finite differences, and the
+Adam step against torch.optim.Adam."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import learned as L
+
+
+def test_parameter_count():
+    assert L.NPARAMS == 14737
+    p = L.init_params(0)
+    assert L.flatten(p).size == L.NPARAMS
+    q = L.unflatten(L.flatten(p))
+    for (W, b), (W2, b2) in zip(p, q):
+        assert np.array_equal(W, W2) and np.array_equal(b, b2)
+
+
+@pytest.mark.parametrize("ci,co,shape", [(1, 16, (5, 6, 7)), (16, 16, (4, 5, 3)), (16, 1, (6, 4, 5))])
+def test_conv_equals_torch_conv3d(ci, co, shape):
+    g = np.random.default_rng(ci * 100 + co)
+    x = g.standard_normal(shape + (ci,))
+    W = g.standard_normal((3, 3, 3, ci, co))
+    b = g.standard_normal(co)
+    ours = L.conv(x, W, b)
+    xt = torch.from_numpy(x).permute(3, 0, 1, 2)[None]              # N C D H W
+    Wt = torch.from_numpy(W).permute(4, 3, 0, 1, 2).contiguous()     # Cout Cin kD kH kW
+    ref = torch.nn.functional.conv3d(xt, Wt, torch.from_numpy(b), padding=1)[0].permute(1, 2, 3, 0).numpy()
+    assert np.allclose(ours, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_conv_backward_finite_differences():
+    g = np.random.default_rng(3)
+    x = g.standard_normal((4, 3, 5, 2))
+    W = g.standard_normal((3, 3, 3, 2, 3))
+    b = g.standard_normal(3)
+    proj = g.standard_normal((4, 3, 5, 3))
+    f = lambda x_, W_, b_: float(np.sum(L.conv(x_, W_, b_) * proj))
+    din, dW, db = L.conv_backward(x, W, proj)
+    h = 1e-6
+    for idx in [(0, 0, 0, 0), (2, 1, 4, 1), (3, 2, 2, 0)]:
+        e = np.zeros_like(x)
+        e[idx] = h
+        assert abs((f(x + e, W, b) - f(x - e, W, b)) / (2 * h) - din[idx]) < 1e-7
+    for idx in [(0, 0, 0, 0, 0), (1, 2, 0, 1, 2), (2, 2, 2, 1, 1)]:
+        e = np.zeros_like(W)
+        e[idx] = h
+        assert abs((f(x, W + e, b) - f(x, W - e, b)) / (2 * h) - dW[idx]) < 1e-7
+    e = np.zeros_like(b)
+    e[1] = h
+    assert abs((f(x, W, b + e) - f(x, W, b - e)) / (2 * h) - db[1]) < 1e-7
+
+
+def test_loss_gradients_finite_differences():
+    g = np.random.default_rng(5)
+    params = L.init_params(1)
+    x = g.standard_normal((5, 5, 5))
+    t = g.standard_normal((5, 5, 5))
+    loss, grads = L.loss_and_grads(params, x, t)
+    h = 1e-6
+    flat = L.flatten(params)
+    gflat = L.flatten(grads)
+    for k in [0, 17, 431, 440, 5000, 14000, 14300, L.NPARAMS - 1]:
+        e = np.zeros_like(flat)
+        e[k] = h
+        lp = L.loss_and_grads(L.unflatten(flat + e), x, t)[0]
+        lm = L.loss_and_grads(L.unflatten(flat - e), x, t)[0]
+        assert abs((lp - lm) / (2 * h) - gflat[k]) <= 1e-6 * max(1.0, abs(gflat[k]))
+
+
+def test_adam_matches_torch():
+    params = L.init_params(2)
+    g = np.random.default_rng(7)
+    grads_seq = [[(g.standard_normal(W.shape), g.standard_normal(b.shape)) for W, b in params] for _ in range(3)]
+    tp = [torch.nn.Parameter(torch.from_numpy(a.copy())) for W, b in params for a in (W, b)]
+    opt = torch.optim.Adam(tp, lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    state = L.zero_state(params)
+    cur = params
+    for t, gs in enumerate(grads_seq, start=1):
+        cur = L.adam_step(cur, gs, state, 1e-3, t)
+        for p_, gr in zip(tp, [a for pair in gs for a in pair]):
+            p_.grad = torch.from_numpy(gr.copy())
+        opt.step()
+    ours = L.flatten(cur)
+    ref = np.concatenate([p_.detach().numpy().ravel() for p_ in tp])
+    assert np.allclose(ours, ref, rtol=1e-12, atol=1e-14)
