@@ -39,7 +39,7 @@ def kernel_source_hash() -> str:
 
 
 KERNEL_NAMES = {
-    "down2": "k2_down (fused pre-smoothing + residual + restriction of a 2D level)",
+    "down2": "k2_down_reg / k2_down (fused pre-smoothing + residual + restriction of a 2D level)",
     "coarse2": "k2_coarse (LDS-resident 2D sub-cycle)",
     "chain2": "k2_chain (2D prolongation chain + 3D correction)",
     "up2": "k2_up (fused prolongation + post-smoothing)",
