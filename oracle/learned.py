@@ -62,34 +62,80 @@ def conv_backward(inp, W, g):
     return din, dW, db
 
 
-def forward(params, x, keep=False):
-    """x: (nz, ny, nx) -> (nz, ny, nx); with keep=True also the layer outputs."""
-    a = x[..., None].astype(np.float64)
+def forward(params, x, keep=False, quantize=None):
+    """x: (nz, ny, nx) -> (nz, ny, nx); with keep=True also the layer outputs.
+    quantize: optional rounding of the input, the weights and every activation
+    after its ReLU (where a reduced-precision implementation stores them)."""
+    q = quantize if quantize is not None else (lambda v: v)
+    a = q(x[..., None].astype(np.float64))
     acts = [a]
     for li, (W, b) in enumerate(params):
-        a = conv(a, W, b)
+        a = conv(a, q(W), b)
         if li < len(params) - 1:
-            a = np.maximum(a, 0.0)
+            a = q(np.maximum(a, 0.0))
         acts.append(a)
     return (a[..., 0], acts) if keep else a[..., 0]
 
 
-def loss_and_grads(params, x, target):
-    """MSE loss mean((N(x) - target)^2) and its gradients."""
-    y, acts = forward(params, x, keep=True)
+def unit_laplacian(d):
+    """The 7-point stencil 6 d - (sum of the six neighbours), zero outside the grid."""
+    p = np.pad(d, 1)
+    nz, ny, nx = d.shape
+    nb = (p[:-2, 1:-1, 1:-1] + p[2:, 1:-1, 1:-1] + p[1:-1, :-2, 1:-1] + p[1:-1, 2:, 1:-1]
+          + p[1:-1, 1:-1, :-2] + p[1:-1, 1:-1, 2:])
+    return 6.0 * d - nb
+
+
+def loss_and_grads(params, x, target, loss="mse", quantize=None):
+    """Loss and its parameter gradients.
+
+    loss="mse":    mean((N(x) - target)^2)
+    loss="energy": mean(d * L d), d = N(x) - target, L the unit 7-point stencil
+                   (the error in the energy norm of the unit-stencil operator)
+    quantize: optional rounding applied where a reduced-precision implementation
+    stores values: the input, the weights, every activation after its ReLU, and
+    the gradient at each layer output after the ReLU mask (biases, the final
+    output and the accumulated weight gradients stay exact).
+    """
+    q = quantize if quantize is not None else (lambda a: a)
+    qp = [(q(W), b) for W, b in params]
+    a = q(x[..., None].astype(np.float64))
+    acts = [a]
+    for li, (W, b) in enumerate(qp):
+        a = conv(a, W, b)
+        if li < len(qp) - 1:
+            a = q(np.maximum(a, 0.0))
+        acts.append(a)
+    y = a[..., 0]
     n = y.size
     diff = y - target
-    loss = float(np.sum(diff * diff) / n)
-    g = (2.0 / n) * diff[..., None]
-    grads = [None] * len(params)
-    for li in range(len(params) - 1, -1, -1):
-        W, _ = params[li]
-        if li < len(params) - 1:
-            g = g * (acts[li + 1] > 0)           # ReLU mask from the layer's output
+    if loss == "mse":
+        val = float(np.sum(diff * diff) / n)
+        g = (2.0 / n) * diff
+    elif loss == "energy":
+        Ld = unit_laplacian(diff)
+        val = float(np.sum(diff * Ld) / n)
+        g = (2.0 / n) * Ld
+    else:
+        raise ValueError(loss)
+    g = q(g[..., None])
+    grads = [None] * len(qp)
+    for li in range(len(qp) - 1, -1, -1):
+        W, _ = qp[li]
+        if li < len(qp) - 1:
+            g = q(g * (acts[li + 1] > 0))        # ReLU mask from the layer's output
         din, dW, db = conv_backward(acts[li], W, g)
         grads[li] = (dW, db)
         g = din
-    return loss, grads
+    return val, grads
+
+
+def round_bf16(a):
+    """Round to bfloat16 (nearest even) through binary32, returned as float64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(a))
 
 
 def adam_step(params, grads, state, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):

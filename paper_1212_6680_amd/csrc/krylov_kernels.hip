@@ -215,6 +215,75 @@ __global__ __launch_bounds__(kTileThreads) void k_update_p_q_tiled(const double 
         for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) partials[e] = 0.0;
 }
 
+// r = b - A x with partial sums of r^2 and b^2 (x tiled through LDS, marching
+// in z like k_update_p_q_tiled); block 0 zeroes the unused partial slots.
+__global__ __launch_bounds__(kTileThreads) void k_resid_tiled(const double *b, const double *x, double *r, int nx,
+                                                              int ny, int nz, double cx, double cy, double cz,
+                                                              int kchunk, double *partials)
+{
+    __shared__ double tile[(kTY + 2) * (kTX + 2)];
+    __shared__ double lds[kTileThreads / 64];
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+    const int i = blockIdx.x * kTX + tx, j = blockIdx.y * kTY + ty;
+    const bool in = i < nx && j < ny;
+    const long long pl = static_cast<long long>(nx) * ny;
+    const long long c2 = static_cast<long long>(j) * nx + i;
+    const int k0 = blockIdx.z * kchunk, k1 = min(nz, k0 + kchunk);
+    int hy = -1, hx = -1, hi = -1, hj = -1;
+    const int t = threadIdx.x;
+    if (t < kTX) {
+        hy = 0; hx = t + 1;
+    } else if (t < 2 * kTX) {
+        hy = kTY + 1; hx = t - kTX + 1;
+    } else if (t < 2 * kTX + kTY) {
+        hy = t - 2 * kTX + 1; hx = 0;
+    } else if (t < 2 * kTX + 2 * kTY) {
+        hy = t - 2 * kTX - kTY + 1; hx = kTX + 1;
+    }
+    if (hy >= 0) {
+        hi = blockIdx.x * kTX + hx - 1;
+        hj = blockIdx.y * kTY + hy - 1;
+    }
+    const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const long long hc2 = static_cast<long long>(hj) * nx + hi;
+    const double diag = 2.0 * (cx + cy + cz);
+    double xm = (in && k0 > 0 && k0 < nz) ? x[(k0 - 1) * pl + c2] : 0.0;
+    double xc = (in && k0 < nz) ? x[k0 * pl + c2] : 0.0;
+    double rr = 0.0, bb = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const double xn = (in && k + 1 < nz) ? x[(k + 1) * pl + c2] : 0.0;
+        tile[(ty + 1) * (kTX + 2) + tx + 1] = xc;
+        if (hy >= 0) tile[hy * (kTX + 2) + hx] = hin ? x[k * pl + hc2] : 0.0;
+        __syncthreads();
+        if (in) {
+            const int cc = (ty + 1) * (kTX + 2) + tx + 1;
+            const double ax = diag * xc - cx * (tile[cc - 1] + tile[cc + 1]) -
+                              cy * (tile[cc - (kTX + 2)] + tile[cc + (kTX + 2)]) - cz * (xm + xn);
+            const double bv = b[k * pl + c2];
+            const double rv = bv - ax;
+            r[k * pl + c2] = rv;
+            rr += rv * rv;
+            bb += bv * bv;
+        }
+        __syncthreads();
+        xm = xc;
+        xc = xn;
+    }
+    rr = block_sum(rr, lds);
+    bb = block_sum(bb, lds);
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0) {
+        partials[bid] = rr;
+        partials[kRedBlocks + bid] = bb;
+    }
+    if (bid == 0)
+        for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) {
+            partials[e] = 0.0;
+            partials[kRedBlocks + e] = 0.0;
+        }
+}
+
 __global__ __launch_bounds__(kRB) void k_update_xr(double *x, double *r, const double *p, const double *q,
                                                    const KScalars *sc, long long n, double *partials)
 {
@@ -259,7 +328,8 @@ __global__ __launch_bounds__(kRB) void k_finalize(int which, int method, int k, 
         double beta = 0.0;
         if (k > 0 && method == 0) beta = v0 / sc->sr_prev;
         if (k > 0 && method == 1) beta = -sc->alpha_prev * v1 / sc->sr_prev;
-        if (!isfinite(beta) || !isfinite(v0)) sc->breakdown = 1;
+        // first check of an iteration: a re-evaluation with another s_k replaces it
+        sc->breakdown = (!isfinite(beta) || !isfinite(v0)) ? 1 : 0;
         sc->beta = beta;
     } else if (which == 2) {
         sc->pq = v0;
@@ -304,6 +374,16 @@ void launch_matvec7(const double *x, double *y, long long ld, int nrhs, int nx, 
 void launch_init_resid(const double *b, const double *x, double *r, int x_zero, int nx, int ny, int nz, double cx,
                        double cy, double cz, double *partials, hipStream_t st)
 {
+    const int gx = (nx + kTX - 1) / kTX, gy = (ny + kTY - 1) / kTY;
+    if (!x_zero && gx * gy <= kRedBlocks) {
+        int gz = kRedBlocks / (gx * gy);
+        gz = gz < 1 ? 1 : (gz > nz ? nz : gz);
+        const int kchunk = (nz + gz - 1) / gz;
+        gz = (nz + kchunk - 1) / kchunk;
+        hipLaunchKernelGGL(k_resid_tiled, dim3(gx, gy, gz), dim3(kTileThreads), 0, st, b, x, r, nx, ny, nz, cx, cy,
+                           cz, kchunk, partials);
+        return;
+    }
     hipLaunchKernelGGL(k_init_resid, dim3(kRedBlocks), dim3(kRB), 0, st, b, x, r, x_zero, nx, ny, nz, cx, cy, cz,
                        partials);
 }

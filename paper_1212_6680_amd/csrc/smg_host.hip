@@ -15,6 +15,7 @@
 #include <new>
 #include <utility>
 
+#include "net_internal.h"
 #include "smg_internal.h"
 
 using namespace smg;
@@ -699,11 +700,13 @@ int upload_tables(smg_handle *h, const Tables &t, hipStream_t st)
     return SMG_OK;
 }
 
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // Krylov (Algorithm 1)
 // ---------------------------------------------------------------------------
-int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_opts *o, krylov_info *info,
-           void *stream)
+int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const krylov_opts *o,
+                    krylov_info *info, void *stream, PrecondHook *hook)
 {
     if (!h || !b || !x || !o) return SMG_EINVAL;
     if (o->max_iter < 0 || !(o->rtol >= 0.0)) return SMG_EINVAL;
@@ -725,6 +728,11 @@ int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_o
         return status;
     };
     auto sync = [&]() { return hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess; };
+    auto fall_back = [&](int k, int reason) {
+        hook->active = 0;
+        hook->fallback_iter = k;
+        hook->fallback_reason = reason;
+    };
 
     if (o->x0_zero) launch_fill(x, 0.0, n, st);
     launch_init_resid(b, x, r, o->x0_zero ? 1 : 0, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
@@ -734,6 +742,7 @@ int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_o
     const double bnorm = std::sqrt(hs->bb);
     const double bden = bnorm > 0.0 ? bnorm : 1.0;
     double rel = std::sqrt(hs->rr) / bden;
+    std::vector<double> rels{rel};
     if (o->history) o->history[0] = rel;
     double c0 = 0.0;
     int k = 0, status = SMG_NOT_CONVERGED;
@@ -742,9 +751,29 @@ int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_o
             vcycle(h, r, s, 1, static_cast<long long>(n), st);
         else
             launch_copy(r, s, n, st);
-        launch_dots_sr_sq(s, r, q, method == 1 && k > 0, n, part, st);
-        launch_finalize(1, method, k, part, sc, nullptr, st);
-        launch_update_p_q(s, pa, pb, q, sc, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+        const double *su = s;
+        bool dots_done = false;
+        if (hook && hook->active) {
+            // learned correction of s_k; the policy falls back to plain s_k
+            const double *sl = hook->apply(hook->ctx, r, s, st);
+            if (!sl) return finish(SMG_EHIP);
+            launch_dots_sr_sq(sl, r, q, method == 1 && k > 0, n, part, st);
+            launch_finalize(1, method, k, part, sc, hs, st);
+            if (!sync()) return finish(SMG_EHIP);
+            if (!std::isfinite(hs->sr) || !std::isfinite(hs->sq))
+                fall_back(k, NET_FALLBACK_NONFINITE);
+            else if (!(hs->sr > 0.0))
+                fall_back(k, NET_FALLBACK_SR);
+            else {
+                su = sl;
+                dots_done = true;
+            }
+        }
+        if (!dots_done) {
+            launch_dots_sr_sq(s, r, q, method == 1 && k > 0, n, part, st);
+            launch_finalize(1, method, k, part, sc, nullptr, st);
+        }
+        launch_update_p_q(su, pa, pb, q, sc, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
         launch_finalize(2, method, k, part, sc, nullptr, st);
         launch_update_xr(x, r, pb, q, sc, n, part, st);
         launch_finalize(3, method, k, part, sc, hs, st);
@@ -758,12 +787,14 @@ int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_o
         if (k == 0) c0 = std::sqrt(std::fabs(hs->sr));
         if (o->history_c) o->history_c[k] = c0 > 0.0 ? std::sqrt(std::fabs(hs->sr)) / c0 : 0.0;
         rel = std::sqrt(hs->rr) / bden;
+        rels.push_back(rel);
         if (o->history) o->history[k + 1] = rel;
         if (!std::isfinite(rel)) {
             status = SMG_EBREAKDOWN;
             ++k;
             break;
         }
+        if (hook && hook->active && k >= 1 && rel > 0.9 * rels[k - 1]) fall_back(k + 1, NET_FALLBACK_STAGNATION);
     }
     if (status != SMG_EBREAKDOWN) {
         inf.iters = k;
@@ -779,14 +810,14 @@ int krylov(smg_handle *h, int method, const double *b, double *x, const krylov_o
     return finish(status);
 }
 
-}  // namespace
-
 int smg_handle_size(const smg_handle *h, size_t *n)
 {
     if (!h || !n) return SMG_EINVAL;
     *n = h->N;
     return SMG_OK;
 }
+
+const smg_grid *smg_handle_grid(const smg_handle *h) { return h ? &h->g : nullptr; }
 
 int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs)
 {
@@ -890,17 +921,17 @@ int smg_matvec(smg_handle *h, const double *x, double *y, int32_t nrhs, int64_t 
 
 int pcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream)
 {
-    return krylov(h, 0, b, x, o, info, stream);
+    return krylov_run(h, 0, b, x, o, info, stream, nullptr);
 }
 
 int fpcg_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream)
 {
-    return krylov(h, 1, b, x, o, info, stream);
+    return krylov_run(h, 1, b, x, o, info, stream, nullptr);
 }
 
 int psd_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, krylov_info *info, void *stream)
 {
-    return krylov(h, 2, b, x, o, info, stream);
+    return krylov_run(h, 2, b, x, o, info, stream, nullptr);
 }
 
 int smg_destroy(smg_handle *h)

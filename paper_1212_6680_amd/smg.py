@@ -59,6 +59,15 @@ class lobpcg_info(C.Structure):
                 ("reserved", C.c_int32), ("seconds", C.c_double)]
 
 
+class net_solve_info(C.Structure):
+    _fields_ = [("fallback_iter", C.c_int32), ("fallback_reason", C.c_int32)]
+
+
+NET_PREC = {"bf16": 0, "f64": 1}
+NET_LOSS = {"mse": 0, "energy": 1}
+NET_NPARAMS = 14737
+FALLBACK = {0: "none", 1: "sr", 2: "nonfinite", 3: "stagnation"}
+
 _lib = None
 
 
@@ -85,6 +94,19 @@ def lib():
             L.lobpcg_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
             L.lobpcg_solve.argtypes = [p, i32, p, p, p, p, C.c_size_t,
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
+        L.net_workspace_bytes.argtypes = [i64, i32, i32, C.POINTER(C.c_size_t)]
+        L.net_setup.argtypes = [i64, i32, i32, p, C.c_size_t, p, C.POINTER(p)]
+        L.net_destroy.argtypes = [p]
+        L.net_set_params.argtypes = [p, p, p]
+        L.net_get_params.argtypes = [p, p, p]
+        L.net_layer_forward.argtypes = [p, i32, i32, i32, i32, p, p, p]
+        L.net_loss_grad.argtypes = [p, i32, i32, i32, p, p, i32, p, p, p]
+        L.net_adam_step.argtypes = [p, d, p]
+        L.net_train.argtypes = [p, i32, i32, i32, p, p, i32, i32, p, p, i32, p, p]
+        L.net_correct.argtypes = [p, p, p, p, p, p, p]
+        L.net_make_pairs.argtypes = [p, p, p, i32, C.c_uint64, d, i32, p, p, p, p]
+        L.fpcg_learned_solve.argtypes = [p, p, p, p, C.POINTER(krylov_opts), C.POINTER(krylov_info),
+                                         C.POINTER(net_solve_info), p]
         _lib = L
     return _lib
 
@@ -161,7 +183,7 @@ class SMG:
         _check(lib().smg_matvec(self.h, _dptr(x), _dptr(y), nrhs, self._ld(x), _stream()), "smg_matvec")
         return y
 
-    def _solve(self, fn, b, x, rtol, max_iter, precond, history, zero_x0):
+    def _solve(self, fn, b, x, rtol, max_iter, precond, history, zero_x0, net=None):
         if x is None:
             x = torch.empty_like(b)
             x0_zero = 1
@@ -173,10 +195,18 @@ class SMG:
                         C.cast(hist, C.POINTER(C.c_double)) if history else None,
                         C.cast(histc, C.POINTER(C.c_double)) if history else None)
         info = krylov_info()
-        code = fn(self.h, _dptr(b, self.n), _dptr(x, self.n), C.byref(o), C.byref(info), _stream())
+        if net is None:
+            code = fn(self.h, _dptr(b, self.n), _dptr(x, self.n), C.byref(o), C.byref(info), _stream())
+        else:
+            ninfo = net_solve_info()
+            code = fn(self.h, net.h, _dptr(b, self.n), _dptr(x, self.n), C.byref(o), C.byref(info),
+                      C.byref(ninfo), _stream())
         _check(code, fn.__name__, ok=(SMG_OK, SMG_NOT_CONVERGED))
         out = Info(iters=info.iters, status=info.status, rel_res=info.rel_res,
                    true_rel_res=info.true_rel_res, seconds=info.solve_seconds)
+        if net is not None:
+            out["fallback_iter"] = ninfo.fallback_iter
+            out["fallback_reason"] = FALLBACK[ninfo.fallback_reason]
         if history:
             out["history"] = list(hist[:info.iters + 1])
             out["history_c"] = list(histc[:info.iters])
@@ -193,6 +223,10 @@ class SMG:
     def psd(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False):
         """Algorithm 1 with beta = 0."""
         return self._solve(lib().psd_solve, b, x, rtol, max_iter, precond, history, zero_x0)
+
+    def fpcg_learned(self, net, b, x=None, rtol=1e-8, max_iter=500, history=False, zero_x0=False):
+        """Flexible PCG with the V-cycle followed by the learned correction of `net` (with fallback)."""
+        return self._solve(lib().fpcg_learned_solve, b, x, rtol, max_iter, "smg", history, zero_x0, net=net)
 
     def lobpcg(self, X0: torch.Tensor, rtol=1e-8, max_iter=500, precond="smg", guard=0):
         """LOBPCG for the m smallest eigenpairs; X0 is (m + guard, n), one initial vector per row.
@@ -224,3 +258,116 @@ class SMG:
         _check(lib().smg_profile_kernel(self.h, KERNELS[family], _dptr(r), _dptr(s), reps, _stream(),
                                         C.byref(nl), C.byref(ms), C.byref(by)), "smg_profile_kernel")
         return nl.value, ms.value, by.value
+
+
+def _tptr(t: torch.Tensor, dtype, n: int | None = None):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise SMGError(f"expected a contiguous {dtype} CUDA tensor")
+    if n is not None and t.numel() < n:
+        raise SMGError("tensor too small")
+    return C.c_void_p(t.data_ptr())
+
+
+class Net:
+    """The learned post-smoother network (include/smg_net.h) in the caller's device workspace."""
+
+    def __init__(self, max_voxels: int, precision="bf16", train=False, device="cuda"):
+        L = lib()
+        self.precision = precision
+        self.storage = torch.bfloat16 if precision == "bf16" else torch.float64
+        self.accum = torch.float32 if precision == "bf16" else torch.float64
+        self.max_voxels = int(max_voxels)
+        self.train_mode = 1 if train else 0
+        nbytes = C.c_size_t(0)
+        _check(L.net_workspace_bytes(self.max_voxels, NET_PREC[precision], self.train_mode, C.byref(nbytes)),
+               "net_workspace_bytes")
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(L.net_setup(self.max_voxels, NET_PREC[precision], self.train_mode, C.c_void_p(self.ws.data_ptr()),
+                           nbytes.value, _stream(), C.byref(h)), "net_setup")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.net_destroy(h)
+            self.h = None
+
+    def set_params(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+        if a.size != NET_NPARAMS:
+            raise SMGError("wrong parameter count")
+        _check(lib().net_set_params(self.h, C.c_void_p(a.ctypes.data), _stream()), "net_set_params")
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(NET_NPARAMS, dtype=np.float64)
+        _check(lib().net_get_params(self.h, C.c_void_p(a.ctypes.data), _stream()), "net_get_params")
+        return a
+
+    def layer_forward(self, layer: int, shape, inp: torch.Tensor) -> torch.Tensor:
+        nx, ny, nz = shape
+        n = nx * ny * nz
+        cin = 1 if layer == 0 else 16
+        if layer == 3:
+            out = torch.empty(n, dtype=self.accum, device=inp.device)
+        else:
+            out = torch.empty(n * 16, dtype=self.storage, device=inp.device)
+        _check(lib().net_layer_forward(self.h, layer, nx, ny, nz, _tptr(inp, self.storage, n * cin),
+                                       C.c_void_p(out.data_ptr()), _stream()), "net_layer_forward")
+        return out
+
+    def loss_grad(self, shape, inp: torch.Tensor, target: torch.Tensor, loss="mse"):
+        import numpy as np
+        nx, ny, nz = shape
+        n = nx * ny * nz
+        val = C.c_double(0)
+        g = np.empty(NET_NPARAMS, dtype=np.float64)
+        _check(lib().net_loss_grad(self.h, nx, ny, nz, _tptr(inp, self.storage, n), _tptr(target, self.accum, n),
+                                   NET_LOSS[loss], C.byref(val), C.c_void_p(g.ctypes.data), _stream()),
+               "net_loss_grad")
+        return val.value, g
+
+    def adam_step(self, lr: float):
+        _check(lib().net_adam_step(self.h, float(lr), _stream()), "net_adam_step")
+
+    def train(self, shape, inputs: torch.Tensor, targets: torch.Tensor, order, lr, loss="mse"):
+        """Adam steps on pairs order[k] with learning rates lr[k]; returns the loss history."""
+        import numpy as np
+        nx, ny, nz = shape
+        n = nx * ny * nz
+        npairs = inputs.numel() // n
+        o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+        r = np.ascontiguousarray(np.asarray(lr, dtype=np.float64))
+        if o.size != r.size:
+            raise SMGError("order and lr must have the same length")
+        hist = np.empty(max(o.size, 1), dtype=np.float64)
+        _check(lib().net_train(self.h, nx, ny, nz, _tptr(inputs, self.storage, npairs * n),
+                               _tptr(targets, self.accum, npairs * n), npairs, o.size, C.c_void_p(o.ctypes.data),
+                               C.c_void_p(r.ctypes.data), NET_LOSS[loss], C.c_void_p(hist.ctypes.data), _stream()),
+               "net_train")
+        return hist[:o.size]
+
+    def correct(self, smg: "SMG", r: torch.Tensor, s: torch.Tensor, out: torch.Tensor | None = None):
+        """out = s + sigma N(r'/(cbar sigma)), r' = r - A s; returns (out, sigma)."""
+        if out is None:
+            out = torch.empty_like(s)
+        sig = C.c_double(0)
+        _check(lib().net_correct(self.h, smg.h, _dptr(r, smg.n), _dptr(s, smg.n), _dptr(out, smg.n),
+                                 C.byref(sig), _stream()), "net_correct")
+        return out, sig.value
+
+    def make_pairs(self, smg_pre: "SMG", smg_exact: "SMG", npairs: int, seed0: int, exact_rtol=1e-13,
+                   exact_max_iter=200):
+        """Training pairs on smg_pre's grid: (inputs, targets, sigmas)."""
+        import numpy as np
+        n = smg_pre.n
+        inputs = torch.empty(npairs * n, dtype=self.storage, device=self.ws.device)
+        targets = torch.empty(npairs * n, dtype=self.accum, device=self.ws.device)
+        sig = np.empty(npairs, dtype=np.float64)
+        _check(lib().net_make_pairs(self.h, smg_pre.h, smg_exact.h, npairs, int(seed0), float(exact_rtol),
+                                    int(exact_max_iter), C.c_void_p(inputs.data_ptr()),
+                                    C.c_void_p(targets.data_ptr()), C.c_void_p(sig.ctypes.data), _stream()),
+               "net_make_pairs")
+        return inputs, targets, sig

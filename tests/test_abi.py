@@ -71,3 +71,20 @@ def test_strerror():
     assert S.strerror(0) == "ok"
     assert "workspace" in S.strerror(-2)
     assert S.strerror(12345) == "unknown status"
+
+
+def test_net_workspace_query_and_invalid_arguments():
+    L = S.lib()
+    n = C.c_size_t(0)
+    assert L.net_workspace_bytes(32 ** 3, 0, 0, C.byref(n)) == 0
+    infer = n.value
+    assert infer >= 32 ** 3 * (8 + 8 + 2 * 16 * 2)
+    assert L.net_workspace_bytes(32 ** 3, 0, 1, C.byref(n)) == 0 and n.value > infer
+    assert L.net_workspace_bytes(32 ** 3, 1, 0, C.byref(n)) == 0 and n.value > infer
+    for args in [(0, 0, 0), (32, 2, 0), (32, 0, 2), (-5, 1, 1)]:
+        assert L.net_workspace_bytes(*args, C.byref(n)) == -1
+    h = C.c_void_p()
+    buf = (C.c_uint8 * 64)()
+    assert L.net_setup(32 ** 3, 0, 0, C.cast(buf, C.c_void_p), 64, None, C.byref(h)) == -2
+    assert not h.value
+    assert L.net_setup(32 ** 3, 0, 0, None, 1 << 30, None, C.byref(h)) == -1

@@ -1,0 +1,292 @@
+"""GPU parity of the learned post-smoother against the FP64 network oracle.
+
+F64 check mode: every kernel (direct convolutions, input and weight
+gradients, loss, Adam, correction, training pairs) is compared with the
+oracle at 1e-10 relative.  BF16 mode (MFMA for the 16 -> 16 layers): the
+oracle rounds to bfloat16 where the kernels store (input, weights,
+activations, gradients), so what remains is FP32 accumulation and the rare
+rounding-boundary flip; the bounds are stated per test.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import definitional as D
+from oracle import learned as L
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _net(nvox, prec, train=True):
+    from paper_1212_6680_amd.smg import Net
+    return Net(nvox, prec, train=train)
+
+
+def _smg(shape, c, pre, post, **kw):
+    from paper_1212_6680_amd.smg import SMG
+    return SMG(shape, c, pre, post, **kw)
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
+
+
+def _bf16_dev(a):
+    """bfloat16 device tensor of a (rounded to nearest even) and the rounded values in FP64."""
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+    return t.to("cuda"), t.to(torch.float64).numpy()
+
+
+def _layer_params(params, l):
+    return params[l]
+
+
+SHAPES = [(13, 11, 9), (70, 9, 6)]   # (nx, ny, nz): ragged against every tile size
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("layer", [0, 1, 2, 3])
+def test_layer_forward_f64(shape, layer):
+    nx, ny, nz = shape
+    params = L.init_params(3)
+    W, b = params[layer]
+    cin = W.shape[3]
+    x = np.random.default_rng(layer).standard_normal((nz, ny, nx, cin))
+    ref = L.conv(x, W, b)
+    if layer < 3:
+        ref = np.maximum(ref, 0.0)
+    net = _net(nx * ny * nz, "f64", train=False)
+    net.set_params(L.flatten(params))
+    out = net.layer_forward(layer, shape, _dev(x.ravel())).cpu().numpy().reshape(ref.shape)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(64, 8, 5), (130, 17, 4)])
+@pytest.mark.parametrize("layer", [0, 1, 2, 3])
+def test_layer_forward_bf16(shape, layer):
+    """bf16 inputs and weights, FP32 accumulation: the error is at most one bf16
+    rounding of the output (2^-8 relative, layers 0..2) plus FP32 accumulation
+    error (<= 1e-4 of the sum of |terms| over 432 products)."""
+    nx, ny, nz = shape
+    params = L.init_params(4)
+    W, b = params[layer]
+    cin = W.shape[3]
+    xd, xq = _bf16_dev(np.random.default_rng(10 + layer).standard_normal((nz, ny, nx, cin)).ravel())
+    xq = xq.reshape(nz, ny, nx, cin)
+    Wq = L.round_bf16(W)
+    b32 = b.astype(np.float32).astype(np.float64)
+    ref = L.conv(xq, Wq, b32)
+    bound = L.conv(np.abs(xq), np.abs(Wq), np.abs(b32))
+    net = _net(nx * ny * nz, "bf16", train=False)
+    net.set_params(L.flatten(params))
+    out = net.layer_forward(layer, shape, xd)
+    out = out.to(torch.float64).cpu().numpy().reshape(ref.shape)
+    if layer < 3:
+        ref = np.maximum(ref, 0.0)
+        tol = 2.0 ** -8 * np.abs(ref) + 1e-4 * bound
+    else:
+        tol = 1e-5 * bound
+    err = np.abs(out - ref)
+    assert np.all(err <= tol), (float(np.max(err / (tol + 1e-300))), float(np.max(err)))
+
+
+@pytest.mark.parametrize("loss", ["mse", "energy"])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (13, 10, 7)])
+def test_loss_and_gradient_f64(shape, loss):
+    nx, ny, nz = shape
+    g = np.random.default_rng(21)
+    params = L.init_params(6)
+    x = g.standard_normal((nz, ny, nx))
+    t = 0.3 * g.standard_normal((nz, ny, nx))
+    ref_loss, ref_grads = L.loss_and_grads(params, x, t, loss=loss)
+    net = _net(nx * ny * nz, "f64")
+    net.set_params(L.flatten(params))
+    val, grad = net.loss_grad(shape, _dev(x.ravel()), _dev(t.ravel()), loss=loss)
+    assert abs(val - ref_loss) <= 1e-12 * abs(ref_loss)
+    ref = L.flatten(ref_grads)
+    for l in range(4):
+        lo, hi = _offsets(l)
+        assert np.linalg.norm(grad[lo:hi] - ref[lo:hi]) <= 1e-10 * np.linalg.norm(ref[lo:hi]), l
+
+
+def _offsets(l):
+    off = 0
+    for i, (ci, co) in enumerate(zip(L.CHANNELS[:-1], L.CHANNELS[1:])):
+        n = 27 * ci * co + co
+        if i == l:
+            return off, off + n
+        off += n
+
+
+@pytest.mark.parametrize("loss", ["mse", "energy"])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (40, 12, 9)])
+def test_loss_and_gradient_bf16(shape, loss):
+    """Against the oracle rounded where the kernels store: layer gradients agree
+    to 2e-3 in norm (FP32 accumulation plus occasional one-ulp flips of a stored
+    bf16 value), the loss to 1e-3."""
+    nx, ny, nz = shape
+    g = np.random.default_rng(22)
+    params = L.init_params(7)
+    xd, xq = _bf16_dev(g.standard_normal(nx * ny * nz))
+    t = (0.3 * g.standard_normal(nx * ny * nz)).astype(np.float32)
+    pq = [(W, b.astype(np.float32).astype(np.float64)) for W, b in params]
+    ref_loss, ref_grads = L.loss_and_grads(pq, xq.reshape(nz, ny, nx), t.astype(np.float64).reshape(nz, ny, nx),
+                                           loss=loss, quantize=L.round_bf16)
+    net = _net(nx * ny * nz, "bf16")
+    net.set_params(L.flatten(params))
+    val, grad = net.loss_grad(shape, xd, _dev(t, torch.float32), loss=loss)
+    assert abs(val - ref_loss) <= 1e-3 * abs(ref_loss)
+    ref = L.flatten(ref_grads)
+    for l in range(4):
+        lo, hi = _offsets(l)
+        rel = np.linalg.norm(grad[lo:hi] - ref[lo:hi]) / np.linalg.norm(ref[lo:hi])
+        assert rel <= 2e-3, (l, rel)
+
+
+def test_adam_step_f64():
+    shape = (9, 8, 7)
+    nx, ny, nz = shape
+    g = np.random.default_rng(23)
+    params = L.init_params(8)
+    x = g.standard_normal((nz, ny, nx))
+    t = 0.3 * g.standard_normal((nz, ny, nx))
+    net = _net(nx * ny * nz, "f64")
+    net.set_params(L.flatten(params))
+    state = L.zero_state(params)
+    cur = params
+    lr = 1e-3
+    for step in range(1, 4):
+        _, ref_grads = L.loss_and_grads(cur, x, t)
+        net.loss_grad(shape, _dev(x.ravel()), _dev(t.ravel()))
+        net.adam_step(lr)
+        cur = L.adam_step(cur, ref_grads, state, lr, step)
+        gflat = np.abs(L.flatten(ref_grads))
+        got, ref = net.get_params(), L.flatten(cur)
+        # Adam divides by |g|: elements whose gradient is at rounding level are excluded
+        big = gflat > 1e-6 * gflat.max()
+        assert np.max(np.abs(got - ref)[big]) <= 1e-8 * lr
+        assert np.max(np.abs(got - ref)) <= 2 * step * lr
+
+
+def test_correction_f64():
+    shape = (20, 18, 16)
+    nx, ny, nz = shape
+    c = (441.0, 441.0, 441.0)
+    params = L.init_params(9)
+    r = synth.rhs(nx, ny, nz, 31)
+    s = 1e-3 * synth.rhs(nx, ny, nz, 32)
+    rp = r - O.matvec(s, shape, c)
+    cbar = sum(c) / 3
+    sigma = np.sqrt(np.mean((rp / cbar) ** 2))
+    ref = s + sigma * L.forward(params, (rp / (cbar * sigma)).reshape(nz, ny, nx)).ravel()
+    G = _smg(shape, c, 1, 0)
+    net = _net(G.n, "f64", train=False)
+    net.set_params(L.flatten(params))
+    out, sig = net.correct(G, _dev(r), _dev(s))
+    out = out.cpu().numpy()
+    assert abs(sig - sigma) <= 1e-13 * sigma
+    assert np.linalg.norm(out - ref) <= 1e-10 * np.linalg.norm(ref - s)
+
+
+def test_correction_bf16():
+    """bf16 network input and activations, as in the oracle with the same roundings:
+    the correction agrees to 2e-3 relative in norm."""
+    shape = (70, 24, 20)
+    nx, ny, nz = shape
+    c = (1.0, 1.0, 1.0)
+    params = L.init_params(10)
+    r = synth.rhs(nx, ny, nz, 33)
+    s = 0.1 * synth.rhs(nx, ny, nz, 34)
+    rp = r - O.matvec(s, shape, c)
+    sigma = np.sqrt(np.mean(rp ** 2))
+    pq = [(W, b.astype(np.float32).astype(np.float64)) for W, b in params]
+    y = L.forward(pq, (rp / sigma).reshape(nz, ny, nx), quantize=L.round_bf16).ravel()
+    G = _smg(shape, c, 1, 0)
+    net = _net(G.n, "bf16", train=False)
+    net.set_params(L.flatten(params))
+    out, sig = net.correct(G, _dev(r), _dev(s))
+    corr = (out.cpu().numpy() - s) / sig
+    assert abs(sig - sigma) <= 1e-13 * sigma
+    assert np.linalg.norm(corr - y) <= 2e-3 * np.linalg.norm(y)
+
+
+def test_pairs_match_oracle_f64():
+    shape = (20, 18, 16)
+    nx, ny, nz = shape
+    c = (441.0, 441.0, 441.0)
+    Gp, Ge = _smg(shape, c, 1, 0), _smg(shape, c, 1, 1)
+    net = _net(Gp.n, "f64")
+    inputs, targets, sig = net.make_pairs(Gp, Ge, 2, 500, exact_rtol=1e-13, exact_max_iter=100)
+    inputs = inputs.cpu().numpy().reshape(2, -1)
+    targets = targets.cpu().numpy().reshape(2, -1)
+    S = O.SMG(shape, c, 1, 0)
+    cbar = sum(c) / 3
+    for i in range(2):
+        b = synth.rhs(nx, ny, nz, 500 + i)
+        xp = S.apply(b)
+        rp = b - O.matvec(xp, shape, c)
+        sigma = np.sqrt(np.mean((rp / cbar) ** 2))
+        xs = D.dst_solve(b, shape, c)
+        assert abs(sig[i] - sigma) <= 1e-11 * sigma
+        assert np.linalg.norm(inputs[i] - rp / (cbar * sigma)) <= 1e-10 * np.linalg.norm(rp / (cbar * sigma))
+        e = (xs - xp) / sigma
+        assert np.linalg.norm(targets[i] - e) <= 1e-8 * np.linalg.norm(e)
+
+
+def test_training_reduces_loss_bf16():
+    shape = (24, 24, 24)
+    n = 24 ** 3
+    c = ((25.0) ** 2,) * 3
+    Gp, Ge = _smg(shape, c, 1, 0), _smg(shape, c, 1, 1)
+    net = _net(n, "bf16")
+    inputs, targets, _ = net.make_pairs(Gp, Ge, 8, 900, exact_rtol=1e-10)
+    net.set_params(L.flatten(L.init_params(0)))
+    order = np.random.default_rng(0).integers(0, 8, 150)
+    hist = net.train(shape, inputs, targets, order, np.full(150, 2e-3))
+    assert np.all(np.isfinite(hist))
+    assert hist[-20:].mean() < 0.8 * hist[:5].mean(), (hist[:5], hist[-20:])
+
+
+def _corrupt(kind, prec):
+    p = L.flatten(L.init_params(0))
+    if kind == "huge":
+        # overflows the storage format within the four layers
+        return np.full_like(p, 1e30 if prec == "bf16" else 1e150)
+    q = np.zeros_like(p)
+    q[-1] = 1e4                 # output bias: a constant correction
+    return q
+
+
+@pytest.mark.parametrize("kind", ["huge", "constant"])
+@pytest.mark.parametrize("prec", ["bf16", "f64"])
+def test_fallback_on_corrupted_network(kind, prec):
+    n = 32
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    G = _smg(shape, c, 1, 0)
+    b = _dev(synth.rhs(n, n, n, 1))
+    _, plain = G.fpcg(b)
+    net = _net(G.n, prec, train=False)
+    net.set_params(_corrupt(kind, prec))
+    x, info = G.fpcg_learned(net, b)
+    assert info.status == 0 and info.rel_res <= 1e-8 and info.true_rel_res <= 1.5e-8
+    assert info.fallback_reason != "none"
+    if kind == "huge":
+        assert info.fallback_reason == "nonfinite" and info.fallback_iter == 0
+    assert info.fallback_iter <= 3
+    assert info.iters <= plain.iters + info.fallback_iter + 2
+
+
+def test_zero_network_is_plain_fpcg():
+    """All-zero parameters give a zero correction: the solve is plain FPCG-SMG(1,0)."""
+    n = 32
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    G = _smg(shape, c, 1, 0)
+    b = _dev(synth.rhs(n, n, n, 1))
+    x0, plain = G.fpcg(b, history=True)
+    net = _net(G.n, "bf16", train=False)
+    net.set_params(np.zeros(L.NPARAMS))
+    x1, info = G.fpcg_learned(net, b, history=True)
+    assert info.fallback_reason == "none" and info.iters == plain.iters
+    assert np.allclose(info.history, plain.history, rtol=1e-12, atol=0)

@@ -86,3 +86,50 @@ def test_adam_matches_torch():
     ours = L.flatten(cur)
     ref = np.concatenate([p_.detach().numpy().ravel() for p_ in tp])
     assert np.allclose(ours, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_energy_loss_gradients_finite_differences():
+    g = np.random.default_rng(11)
+    params = L.init_params(4)
+    x = g.standard_normal((4, 5, 6))
+    t = g.standard_normal((4, 5, 6))
+    loss, grads = L.loss_and_grads(params, x, t, loss="energy")
+    # energy norm of the unit stencil is a positive quadratic form
+    d = L.forward(params, x) - t
+    assert loss > 0 and np.isclose(loss, float(np.sum(d * L.unit_laplacian(d))) / d.size, rtol=1e-13)
+    flat, gflat = L.flatten(params), L.flatten(grads)
+    h = 1e-6
+    for k in [3, 440, 7000, 14300, L.NPARAMS - 2]:
+        e = np.zeros_like(flat)
+        e[k] = h
+        lp = L.loss_and_grads(L.unflatten(flat + e), x, t, loss="energy")[0]
+        lm = L.loss_and_grads(L.unflatten(flat - e), x, t, loss="energy")[0]
+        assert abs((lp - lm) / (2 * h) - gflat[k]) <= 1e-6 * max(1.0, abs(gflat[k]))
+
+
+def test_unit_laplacian_is_the_dirichlet_stencil():
+    # on a 1-voxel-thick slab the stencil is 6*d minus in-plane neighbours only
+    d = np.zeros((3, 3, 3))
+    d[1, 1, 1] = 1.0
+    Ld = L.unit_laplacian(d)
+    assert Ld[1, 1, 1] == 6.0 and Ld[0, 1, 1] == -1.0 and Ld[1, 1, 2] == -1.0 and Ld[0, 0, 0] == 0.0
+    assert np.isclose(np.sum(Ld), 0.0)
+
+
+def test_round_bf16_matches_torch():
+    g = np.random.default_rng(12)
+    a = np.concatenate([g.standard_normal(1000) * 10.0 ** g.integers(-20, 20, 1000), [0.0, -0.0, 1.0, 3.0]])
+    ours = L.round_bf16(a)
+    ref = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_quantized_loss_without_rounding_equals_plain():
+    g = np.random.default_rng(13)
+    params = L.init_params(5)
+    x = g.standard_normal((4, 4, 5))
+    t = g.standard_normal((4, 4, 5))
+    a = L.loss_and_grads(params, x, t)
+    b = L.loss_and_grads(params, x, t, quantize=lambda v: v)
+    assert a[0] == b[0]
+    assert np.array_equal(L.flatten(a[1]), L.flatten(b[1]))
