@@ -70,7 +70,7 @@ def read_traffic(family):
         return None
 
 
-def other_configs(torch, dev):
+def other_configs(torch, dev, learned=True):
     """The other workloads of the hot path, each timed once after a warm-up:
     LOBPCG (m = 16 and m = 64 smallest eigenpairs of the 128^3 Laplacian,
     SMG(1,0) applied to the active block in one batched V-cycle) and FPCG at
@@ -122,7 +122,98 @@ def other_configs(torch, dev):
         res[f"fpcg_384_smg_{prec}"] = {"s": dt, "iters": info.iters, "status": info.status,
                                        "true_rel_res": info.true_rel_res, "rel_err_vs_f64_solution": err}
         del G
+    del b, x, x64
+    torch.cuda.empty_cache()
+    res["batch_48_uneven"] = batch_config(torch, dev)
+    if learned:
+        res["learned_256"] = learned_config(torch, dev)
     return res
+
+
+def batch_config(torch, dev):
+    """48 independent FPCG-SMG(1,0) solves on boxes with nx, ny, nz drawn from
+    32..96 (unit grid size, b ~ U[-1,1) seeds 1000 + box): one batched solve
+    (grouped launches, graph-replayed iteration) against the 48 solves one
+    after another, with every box checked bitwise against its own solve."""
+    import synth
+    from paper_1212_6680_amd.smg import SMG, SMGBatch
+    dims = synth.box_dims(48, 32, 96, 4)
+    Gs = [SMG(d, (1.0, 1.0, 1.0), 1, 0) for d in dims]
+    bs = [torch.from_numpy(synth.rhs(*d, 1000 + i)).to(dev) for i, d in enumerate(dims)]
+    for G, b in zip(Gs, bs):
+        G.fpcg(b, max_iter=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    singles = [G.fpcg(b) for G, b in zip(Gs, bs)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    xs = [torch.empty_like(b) for b in bs]
+    t0 = time.perf_counter()
+    B = SMGBatch(Gs, bs, xs, use_graph=True)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    B.fpcg(max_iter=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = B.fpcg()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    steps, launches = B.stats()
+    same = all(torch.equal(x, xr) and i.iters == ir.iters for x, i, (xr, ir) in zip(xs, infos, singles))
+    return {"boxes": 48, "dof": int(sum(G.n for G in Gs)), "s": t_batch, "sequential_s": t_seq,
+            "speedup": t_seq / t_batch, "create_s": t_create,
+            "grouped_launches_per_iteration": steps, "box_launches_per_iteration": launches,
+            "iters_min": min(i.iters for i in infos), "iters_max": max(i.iters for i in infos),
+            "all_converged": all(i.status == 0 for i in infos), "bitwise_equal_to_single_solves": bool(same)}
+
+
+def learned_config(torch, dev):
+    """Learned post-smoother: trained at 128^3 on 2000 (r', e') pairs from
+    SMG(1,0) (b seeds 10000 + i, energy-norm loss, one Adam step per pair),
+    then used inside FPCG at 256^3 (b seed 6) beside SMG (1,0) and (1,1)."""
+    import synth
+    from paper_1212_6680_amd.smg import SMG, Net
+    n = 128
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    Gp, Ge = SMG(shape, c, 1, 0), SMG(shape, c, 1, 1)
+    net = Net(n ** 3, "bf16", train=True)
+    npairs, steps = 2000, 2000
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inputs, targets, _ = net.make_pairs(Gp, Ge, npairs, 10000, exact_rtol=1e-10)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    net.set_params(synth.he_init(0))
+    order = np.random.default_rng(0).permutation(npairs)[:steps]
+    lr = 2e-3 * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * np.arange(steps) / steps)))
+    t0 = time.perf_counter()
+    hist = net.train(shape, inputs, targets, order, lr, loss="energy")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    params = net.get_params()
+    del inputs, targets, net, Gp, Ge
+    torch.cuda.empty_cache()
+    n = 256
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    b = torch.from_numpy(synth.rhs(n, n, n, 6)).to(dev)
+    G10, G11 = SMG(shape, c, 1, 0), SMG(shape, c, 1, 1)
+    ev = Net(n ** 3, "bf16", train=False)
+    ev.set_params(params)
+    out = {"train_grid": 128, "pairs": npairs, "adam_steps": steps, "pairs_s": t_pairs, "train_s": t_train,
+           "loss_first": float(hist[:10].mean()), "loss_last": float(hist[-100:].mean())}
+    for name, fn in (("smg10", lambda: G10.fpcg(b)), ("smg11", lambda: G11.fpcg(b)),
+                     ("learned", lambda: G10.fpcg_learned(ev, b))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = fn()
+        torch.cuda.synchronize()
+        out[name] = {"s": time.perf_counter() - t0, "iters": info.iters, "status": info.status,
+                     "true_rel_res": info.true_rel_res}
+        if name == "learned":
+            out[name]["fallback_iter"] = info.fallback_iter
+            out[name]["fallback_reason"] = info.fallback_reason
+    return out
 
 
 def main():
@@ -133,6 +224,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned post-smoother workload")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the LOBPCG and mixed-precision workloads reported beside the headline")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -274,7 +366,7 @@ def main():
         out["variants"] = var
 
     if not args.no_configs:
-        out["configs"] = other_configs(torch, dev)
+        out["configs"] = other_configs(torch, dev, learned=not args.no_learned)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

@@ -171,6 +171,31 @@ int lobpcg_workspace_bytes(smg_handle *h, int32_t mb, size_t *bytes);
 int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *resnorms, void *ws,
                  size_t ws_bytes, const lobpcg_opts *o, lobpcg_info *info, void *stream);
 
+/* Batched flexible PCG over nbox independent bricks (each with its own handle,
+ * grid and right-hand side), all advanced together: every stage of the
+ * V-cycle and of the recurrence is one grouped launch over all boxes, the
+ * stopping test (||r_k||/||b|| <= rtol or max_iter) runs on the device, and
+ * one iteration is captured as a HIP graph and replayed (use_graph = 1).
+ * Per box, the kernels, their arguments and their order are those of
+ * fpcg_solve, so each box's result equals its single-box fpcg_solve bitwise.
+ * Handles must be FP64 (SMG_PREC_F64), distinct, and not used elsewhere while
+ * the batch exists.  b[i], x[i]: device vectors of box i (host arrays of nbox
+ * device pointers, bound at creation).  ws: caller-owned device workspace of
+ * ws_bytes >= smg_batch_workspace_bytes (launch tables).  The batch runs on a
+ * private stream ordered after and before the caller's `stream`. */
+typedef struct smg_batch smg_batch;
+int smg_batch_workspace_bytes(smg_handle *const *hs, int32_t nbox, size_t *bytes);
+int smg_batch_create(smg_handle *const *hs, int32_t nbox, const double *const *b, double *const *x, void *ws,
+                     size_t ws_bytes, int32_t use_graph, void *stream, smg_batch **out);
+/* One batched solve with options o (history pointers must be NULL, precond
+ * SMG_PRECOND_SMG); infos: host, nbox entries.  Returns SMG_OK when every box
+ * converged, else the most severe status among the boxes. */
+int smg_batch_fpcg(smg_batch *bt, const krylov_opts *o, krylov_info *infos, void *stream);
+/* Grouped launches per iteration (steps) and the per-box launches they
+ * replace (the sum over boxes of each box's launches per iteration). */
+int smg_batch_stats(const smg_batch *bt, int32_t *steps_per_iteration, int32_t *launches_per_iteration);
+int smg_batch_destroy(smg_batch *bt);
+
 /* Releases the host-side handle (the caller's workspace is not freed). */
 int smg_destroy(smg_handle *h);
 

@@ -10,6 +10,7 @@
 // partial per block (wave shuffles, then LDS across the block's waves), and
 // a one-block finalize kernel sums the partials in a fixed order and advances
 // the scalar recurrence on the device.
+#include "group.h"
 #include "smg_internal.h"
 
 namespace smg {
@@ -66,65 +67,78 @@ __global__ __launch_bounds__(256) void k_matvec7(const double *x, double *y, lon
     y[r * ld + c] = a7(x + r * ld, c, i, j, k, nx, ny, nz, cx, cy, cz);
 }
 
-__global__ __launch_bounds__(kRB) void k_init_resid(const double *b, const double *x, double *r, int x_zero, int nx,
-                                                    int ny, int nz, double cx, double cy, double cz,
-                                                    double *partials)
+
+#define SMG_GROUPED_KERNEL(NAME, BOUNDS, ARGS)                                                 \
+    __global__ __launch_bounds__(BOUNDS) void NAME(ARGS a) { NAME##_body(a, SMG_BLK_HW); }     \
+    __global__ __launch_bounds__(BOUNDS) void NAME##_grp(const GroupEntry *tab, int n)         \
+    {                                                                                          \
+        const ARGS *a;                                                                         \
+        Blk blk;                                                                               \
+        if (!group_entry(tab, n, a, blk)) return;                                              \
+        NAME##_body(*a, blk);                                                                  \
+    }
+
+// r = b - A x (or r = b when x_zero) and partial sums of r^2, b^2; grid-stride
+__device__ __forceinline__ void k_init_resid_body(const ResidArgs &a, const Blk &blk)
 {
     __shared__ double lds[kRB / 64];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
     const long long n = static_cast<long long>(nx) * ny * nz;
     double rr = 0.0, bb = 0.0;
-    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-         c += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const double bv = b[c];
+    for (long long c = static_cast<long long>(blk.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(blk.gx) * blockDim.x) {
+        const double bv = a.b[c];
         double rv = bv;
-        if (!x_zero) {
+        if (!a.x_zero) {
             const int i = static_cast<int>(c % nx);
             const long long t = c / nx;
             const int j = static_cast<int>(t % ny), k = static_cast<int>(t / ny);
-            rv -= a7(x, c, i, j, k, nx, ny, nz, cx, cy, cz);
+            rv -= a7(a.x, c, i, j, k, nx, ny, nz, a.cx, a.cy, a.cz);
         }
-        r[c] = rv;
+        a.r[c] = rv;
         rr += rv * rv;
         bb += bv * bv;
     }
     rr = block_sum(rr, lds);
     bb = block_sum(bb, lds);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = rr;
-        partials[kRedBlocks + blockIdx.x] = bb;
+        a.partials[blk.x] = rr;
+        a.partials[kRedBlocks + blk.x] = bb;
     }
 }
+SMG_GROUPED_KERNEL(k_init_resid, kRB, ResidArgs)
 
-__global__ __launch_bounds__(kRB) void k_dots_sr_sq(const double *s, const double *r, const double *q, int want_sq,
-                                                    long long n, double *partials)
+__device__ __forceinline__ void k_dots_sr_sq_body(const DotsArgs &a, const Blk &blk)
 {
     __shared__ double lds[kRB / 64];
     double sr = 0.0, sq = 0.0;
-    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-         c += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const double sv = s[c];
-        sr += sv * r[c];
-        if (want_sq) sq += sv * q[c];
+    for (long long c = static_cast<long long>(blk.x) * blockDim.x + threadIdx.x; c < a.n;
+         c += static_cast<long long>(blk.gx) * blockDim.x) {
+        const double sv = a.s[c];
+        sr += sv * a.r[c];
+        if (a.want_sq) sq += sv * a.q[c];
     }
     sr = block_sum(sr, lds);
     sq = block_sum(sq, lds);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = sr;
-        partials[kRedBlocks + blockIdx.x] = sq;
+        a.partials[blk.x] = sr;
+        a.partials[kRedBlocks + blk.x] = sq;
     }
 }
+SMG_GROUPED_KERNEL(k_dots_sr_sq, kRB, DotsArgs)
 
-__global__ __launch_bounds__(kRB) void k_update_p_q(const double *s, const double *p_old, double *p_new, double *q,
-                                                    const KScalars *sc, int nx, int ny, int nz, double cx, double cy,
-                                                    double cz, double *partials)
+__device__ __forceinline__ void k_update_p_q_body(const UpdPQArgs &a, const Blk &blk)
 {
     __shared__ double lds[kRB / 64];
-    const double beta = sc->beta;
+    const double beta = a.sc->beta;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const double cx = a.cx, cy = a.cy, cz = a.cz;
+    const double *s = a.s, *p_old = a.p_old;
     const long long pl = static_cast<long long>(nx) * ny;
     const long long n = pl * nz;
     double pq = 0.0;
-    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+    for (long long c = static_cast<long long>(blk.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(blk.gx) * blockDim.x) {
         const int i = static_cast<int>(c % nx);
         const long long t = c / nx;
         const int j = static_cast<int>(t % ny), k = static_cast<int>(t / ny);
@@ -138,13 +152,14 @@ __global__ __launch_bounds__(kRB) void k_update_p_q(const double *s, const doubl
         if (j < ny - 1) qv -= cy * pv(c + nx);
         if (k > 0) qv -= cz * pv(c - pl);
         if (k < nz - 1) qv -= cz * pv(c + pl);
-        p_new[c] = p0;
-        q[c] = qv;
+        a.p_new[c] = p0;
+        a.q[c] = qv;
         pq += p0 * qv;
     }
     pq = block_sum(pq, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = pq;
+    if (threadIdx.x == 0) a.partials[blk.x] = pq;
 }
+SMG_GROUPED_KERNEL(k_update_p_q, kRB, UpdPQArgs)
 
 // The same pass as a z-marching stencil: a block owns a 64 x 8 (i, j) tile and
 // a run of planes; p at k-1, k, k+1 stays in registers, the in-plane
@@ -153,24 +168,13 @@ __global__ __launch_bounds__(kRB) void k_update_p_q(const double *s, const doubl
 // are read about once, p_k and q written once.
 constexpr int kTX = 64, kTY = 8, kTileThreads = kTX * kTY;
 
-__global__ __launch_bounds__(kTileThreads) void k_update_p_q_tiled(const double *s, const double *p_old,
-                                                                   double *p_new, double *q, const KScalars *sc,
-                                                                   int nx, int ny, int nz, double cx, double cy,
-                                                                   double cz, int kchunk, double *partials)
+
+// halo point of thread t of a kTX x kTY tile (threads 0 .. 2*(kTX+kTY)-1),
+// in tile coordinates (hy, hx); -1 when the thread has none
+__device__ inline void tile_halo(int t, int &hy, int &hx)
 {
-    __shared__ double tile[(kTY + 2) * (kTX + 2)];
-    __shared__ double lds[kTileThreads / 64];
-    const double beta = sc->beta;
-    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-    const int i = blockIdx.x * kTX + tx, j = blockIdx.y * kTY + ty;
-    const bool in = i < nx && j < ny;
-    const long long pl = static_cast<long long>(nx) * ny;
-    const long long c2 = static_cast<long long>(j) * nx + i;
-    const int k0 = blockIdx.z * kchunk, k1 = min(nz, k0 + kchunk);
-    auto pv = [&](long long c) { return beta == 0.0 ? s[c] : s[c] + beta * p_old[c]; };
-    // halo point of this thread (threads 0..143), tile coordinates (hy, hx)
-    int hy = -1, hx = -1, hi = -1, hj = -1;
-    const int t = threadIdx.x;
+    hy = -1;
+    hx = -1;
     if (t < kTX) {
         hy = 0; hx = t + 1;
     } else if (t < 2 * kTX) {
@@ -180,9 +184,29 @@ __global__ __launch_bounds__(kTileThreads) void k_update_p_q_tiled(const double 
     } else if (t < 2 * kTX + 2 * kTY) {
         hy = t - 2 * kTX - kTY + 1; hx = kTX + 1;
     }
+}
+
+__device__ __forceinline__ void k_update_p_q_tiled_body(const UpdPQArgs &a, const Blk &blk)
+{
+    __shared__ double tile[(kTY + 2) * (kTX + 2)];
+    __shared__ double lds[kTileThreads / 64];
+    const double beta = a.sc->beta;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const double cx = a.cx, cy = a.cy, cz = a.cz;
+    const double *s = a.s, *p_old = a.p_old;
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+    const int i = blk.x * kTX + tx, j = blk.y * kTY + ty;
+    const bool in = i < nx && j < ny;
+    const long long pl = static_cast<long long>(nx) * ny;
+    const long long c2 = static_cast<long long>(j) * nx + i;
+    const int k0 = blk.z * a.kchunk, k1 = min(nz, k0 + a.kchunk);
+    auto pv = [&](long long c) { return beta == 0.0 ? s[c] : s[c] + beta * p_old[c]; };
+    int hy, hx;
+    tile_halo(threadIdx.x, hy, hx);
+    int hi = -1, hj = -1;
     if (hy >= 0) {
-        hi = blockIdx.x * kTX + hx - 1;
-        hj = blockIdx.y * kTY + hy - 1;
+        hi = blk.x * kTX + hx - 1;
+        hj = blk.y * kTY + hy - 1;
     }
     const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
     const long long hc2 = static_cast<long long>(hj) * nx + hi;
@@ -199,8 +223,8 @@ __global__ __launch_bounds__(kTileThreads) void k_update_p_q_tiled(const double 
             const int cc = (ty + 1) * (kTX + 2) + tx + 1;
             const double qv = diag * pc - cx * (tile[cc - 1] + tile[cc + 1]) -
                               cy * (tile[cc - (kTX + 2)] + tile[cc + (kTX + 2)]) - cz * (pm + pn);
-            p_new[k * pl + c2] = pc;
-            q[k * pl + c2] = qv;
+            a.p_new[k * pl + c2] = pc;
+            a.q[k * pl + c2] = qv;
             pq += pc * qv;
         }
         __syncthreads();
@@ -208,41 +232,35 @@ __global__ __launch_bounds__(kTileThreads) void k_update_p_q_tiled(const double 
         pc = pn;
     }
     pq = block_sum(pq, lds);
-    const int nb = gridDim.x * gridDim.y * gridDim.z;
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    if (threadIdx.x == 0) partials[bid] = pq;
+    const int nb = blk.gx * blk.gy * blk.gz;
+    const int bid = (blk.z * blk.gy + blk.y) * blk.gx + blk.x;
+    if (threadIdx.x == 0) a.partials[bid] = pq;
     if (bid == 0)
-        for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) partials[e] = 0.0;
+        for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) a.partials[e] = 0.0;
 }
+SMG_GROUPED_KERNEL(k_update_p_q_tiled, kTileThreads, UpdPQArgs)
 
 // r = b - A x with partial sums of r^2 and b^2 (x tiled through LDS, marching
 // in z like k_update_p_q_tiled); block 0 zeroes the unused partial slots.
-__global__ __launch_bounds__(kTileThreads) void k_resid_tiled(const double *b, const double *x, double *r, int nx,
-                                                              int ny, int nz, double cx, double cy, double cz,
-                                                              int kchunk, double *partials)
+__device__ __forceinline__ void k_resid_tiled_body(const ResidArgs &a, const Blk &blk)
 {
     __shared__ double tile[(kTY + 2) * (kTX + 2)];
     __shared__ double lds[kTileThreads / 64];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const double cx = a.cx, cy = a.cy, cz = a.cz;
+    const double *x = a.x;
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-    const int i = blockIdx.x * kTX + tx, j = blockIdx.y * kTY + ty;
+    const int i = blk.x * kTX + tx, j = blk.y * kTY + ty;
     const bool in = i < nx && j < ny;
     const long long pl = static_cast<long long>(nx) * ny;
     const long long c2 = static_cast<long long>(j) * nx + i;
-    const int k0 = blockIdx.z * kchunk, k1 = min(nz, k0 + kchunk);
-    int hy = -1, hx = -1, hi = -1, hj = -1;
-    const int t = threadIdx.x;
-    if (t < kTX) {
-        hy = 0; hx = t + 1;
-    } else if (t < 2 * kTX) {
-        hy = kTY + 1; hx = t - kTX + 1;
-    } else if (t < 2 * kTX + kTY) {
-        hy = t - 2 * kTX + 1; hx = 0;
-    } else if (t < 2 * kTX + 2 * kTY) {
-        hy = t - 2 * kTX - kTY + 1; hx = kTX + 1;
-    }
+    const int k0 = blk.z * a.kchunk, k1 = min(nz, k0 + a.kchunk);
+    int hy, hx;
+    tile_halo(threadIdx.x, hy, hx);
+    int hi = -1, hj = -1;
     if (hy >= 0) {
-        hi = blockIdx.x * kTX + hx - 1;
-        hj = blockIdx.y * kTY + hy - 1;
+        hi = blk.x * kTX + hx - 1;
+        hj = blk.y * kTY + hy - 1;
     }
     const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
     const long long hc2 = static_cast<long long>(hj) * nx + hi;
@@ -259,9 +277,9 @@ __global__ __launch_bounds__(kTileThreads) void k_resid_tiled(const double *b, c
             const int cc = (ty + 1) * (kTX + 2) + tx + 1;
             const double ax = diag * xc - cx * (tile[cc - 1] + tile[cc + 1]) -
                               cy * (tile[cc - (kTX + 2)] + tile[cc + (kTX + 2)]) - cz * (xm + xn);
-            const double bv = b[k * pl + c2];
+            const double bv = a.b[k * pl + c2];
             const double rv = bv - ax;
-            r[k * pl + c2] = rv;
+            a.r[k * pl + c2] = rv;
             rr += rv * rv;
             bb += bv * bv;
         }
@@ -271,35 +289,36 @@ __global__ __launch_bounds__(kTileThreads) void k_resid_tiled(const double *b, c
     }
     rr = block_sum(rr, lds);
     bb = block_sum(bb, lds);
-    const int nb = gridDim.x * gridDim.y * gridDim.z;
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int nb = blk.gx * blk.gy * blk.gz;
+    const int bid = (blk.z * blk.gy + blk.y) * blk.gx + blk.x;
     if (threadIdx.x == 0) {
-        partials[bid] = rr;
-        partials[kRedBlocks + bid] = bb;
+        a.partials[bid] = rr;
+        a.partials[kRedBlocks + bid] = bb;
     }
     if (bid == 0)
         for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) {
-            partials[e] = 0.0;
-            partials[kRedBlocks + e] = 0.0;
+            a.partials[e] = 0.0;
+            a.partials[kRedBlocks + e] = 0.0;
         }
 }
+SMG_GROUPED_KERNEL(k_resid_tiled, kTileThreads, ResidArgs)
 
-__global__ __launch_bounds__(kRB) void k_update_xr(double *x, double *r, const double *p, const double *q,
-                                                   const KScalars *sc, long long n, double *partials)
+__device__ __forceinline__ void k_update_xr_body(const UpdXRArgs &a, const Blk &blk)
 {
     __shared__ double lds[kRB / 64];
-    const double alpha = sc->alpha;
+    const double alpha = a.sc->alpha;
     double rr = 0.0;
-    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-         c += static_cast<long long>(gridDim.x) * blockDim.x) {
-        x[c] += alpha * p[c];
-        const double rv = r[c] - alpha * q[c];
-        r[c] = rv;
+    for (long long c = static_cast<long long>(blk.x) * blockDim.x + threadIdx.x; c < a.n;
+         c += static_cast<long long>(blk.gx) * blockDim.x) {
+        a.x[c] += alpha * a.p[c];
+        const double rv = a.r[c] - alpha * a.q[c];
+        a.r[c] = rv;
         rr += rv * rv;
     }
     rr = block_sum(rr, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = rr;
+    if (threadIdx.x == 0) a.partials[blk.x] = rr;
 }
+SMG_GROUPED_KERNEL(k_update_xr, kRB, UpdXRArgs)
 
 __device__ inline double sum_partials(const double *p, double *lds)
 {
@@ -308,60 +327,92 @@ __device__ inline double sum_partials(const double *p, double *lds)
     return block_sum(v, lds);
 }
 
-// method: 0 = PCG (1), 1 = FPCG (2), 2 = PSD
-__global__ __launch_bounds__(kRB) void k_finalize(int which, int method, int k, const double *partials,
-                                                  KScalars *sc)
+// Stage 2 of the reductions and the scalar recurrence.  method: 0 = PCG (1),
+// 1 = FPCG (2), 2 = PSD.  which: 0 = start (rr, bb), 1 = beta (sr, sq),
+// 2 = alpha (pq), 3 = rr, 4 = true residual.  With a.batched the iteration
+// index and the stopping test live on the device (KScalars::iters, active),
+// using the same expressions as the host loop: ||r||/||b|| > rtol and
+// iters < max_iter.
+__device__ __forceinline__ void k_finalize_body(const FinArgs &a, const Blk &)
 {
     __shared__ double lds[kRB / 64];
-    const double v0 = sum_partials(partials, lds);
-    const double v1 = (which <= 1) ? sum_partials(partials + kRedBlocks, lds) : 0.0;
+    KScalars *sc = a.sc;
+    const double v0 = sum_partials(a.partials, lds);
+    const double v1 = (a.which <= 1) ? sum_partials(a.partials + kRedBlocks, lds) : 0.0;
     if (threadIdx.x != 0) return;
-    if (which == 0) {
+    if (a.which == 0) {
         sc->rr = v0;
         sc->bb = v1;
         sc->breakdown = 0;
         sc->sr_prev = 0.0;
         sc->alpha_prev = 0.0;
-    } else if (which == 1) {
+        if (a.batched) {
+            const double bn = sqrt(v1);
+            const double bden = bn > 0.0 ? bn : 1.0;
+            sc->bden = bden;
+            sc->rtol = a.rtol;
+            sc->max_iter = a.max_iter;
+            sc->iters = 0;
+            const bool finite = isfinite(v0) && isfinite(v1);
+            sc->nonfinite = finite ? 0 : 1;
+            sc->active = (finite && a.max_iter > 0 && sqrt(v0) / bden > a.rtol) ? 1 : 0;
+        }
+    } else if (a.which == 1) {
+        const int k = a.batched ? sc->iters : a.k;
         sc->sr = v0;
         sc->sq = v1;
         double beta = 0.0;
-        if (k > 0 && method == 0) beta = v0 / sc->sr_prev;
-        if (k > 0 && method == 1) beta = -sc->alpha_prev * v1 / sc->sr_prev;
+        if (k > 0 && a.method == 0) beta = v0 / sc->sr_prev;
+        if (k > 0 && a.method == 1) beta = -sc->alpha_prev * v1 / sc->sr_prev;
         // first check of an iteration: a re-evaluation with another s_k replaces it
         sc->breakdown = (!isfinite(beta) || !isfinite(v0)) ? 1 : 0;
         sc->beta = beta;
-    } else if (which == 2) {
+    } else if (a.which == 2) {
         sc->pq = v0;
         const double alpha = sc->sr / v0;
         if (!isfinite(alpha)) sc->breakdown = 1;
         sc->alpha = alpha;
         sc->alpha_prev = alpha;
         sc->sr_prev = sc->sr;
-    } else {
+    } else if (a.which == 3) {
         sc->rr = v0;
+        if (a.batched) {
+            if (sc->breakdown) {
+                sc->active = 0;
+            } else {
+                sc->iters += 1;
+                const double rel = sqrt(v0) / sc->bden;
+                sc->active = (isfinite(rel) && rel > sc->rtol && sc->iters < sc->max_iter) ? 1 : 0;
+            }
+        }
+    } else {
+        sc->true_rr = v0;
     }
 }
+SMG_GROUPED_KERNEL(k_finalize, kRB, FinArgs)
 
-__global__ void k_copy(const double *src, double *dst, long long n)
+__device__ __forceinline__ void k_copy_body(const CopyArgs &a, const Blk &blk)
 {
-    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-         c += static_cast<long long>(gridDim.x) * blockDim.x)
-        dst[c] = src[c];
+    for (long long c = static_cast<long long>(blk.x) * blockDim.x + threadIdx.x; c < a.n;
+         c += static_cast<long long>(blk.gx) * blockDim.x)
+        a.dst[c] = a.src[c];
 }
+SMG_GROUPED_KERNEL(k_copy, 256, CopyArgs)
 
-__global__ void k_fill(double *dst, double v, long long n)
+__device__ __forceinline__ void k_fill_body(const FillArgs &a, const Blk &blk)
 {
-    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-         c += static_cast<long long>(gridDim.x) * blockDim.x)
-        dst[c] = v;
+    for (long long c = static_cast<long long>(blk.x) * blockDim.x + threadIdx.x; c < a.n;
+         c += static_cast<long long>(blk.gx) * blockDim.x)
+        a.dst[c] = a.v;
 }
+SMG_GROUPED_KERNEL(k_fill, 256, FillArgs)
 
 }  // namespace
 
 void launch_fill(double *dst, double v, size_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fill, dim3(kRedBlocks), dim3(256), 0, st, dst, v, static_cast<long long>(n));
+    const FillArgs a{dst, v, static_cast<long long>(n)};
+    SMG_LAUNCH_G(LaunchEv{}, k_fill, k_fill_grp, dim3(kRedBlocks), dim3(256), 0, st, a);
 }
 
 void launch_matvec7(const double *x, double *y, long long ld, int nrhs, int nx, int ny, int nz, double cx, double cy,
@@ -371,64 +422,89 @@ void launch_matvec7(const double *x, double *y, long long ld, int nrhs, int nx, 
     hipLaunchKernelGGL(k_matvec7, grid, dim3(256), 0, st, x, y, ld, nx, ny, nz, cx, cy, cz);
 }
 
+// z-chunking of the tiled stencil passes: at most kRedBlocks blocks, so each
+// block owns one partial-sum slot
+static bool tile_grid(int nx, int ny, int nz, dim3 &grid, int &kchunk)
+{
+    const int gx = (nx + kTX - 1) / kTX, gy = (ny + kTY - 1) / kTY;
+    if (gx * gy > kRedBlocks) return false;
+    int gz = kRedBlocks / (gx * gy);
+    gz = gz < 1 ? 1 : (gz > nz ? nz : gz);
+    kchunk = (nz + gz - 1) / gz;
+    gz = (nz + kchunk - 1) / kchunk;
+    grid = dim3(gx, gy, gz);
+    return true;
+}
+
 void launch_init_resid(const double *b, const double *x, double *r, int x_zero, int nx, int ny, int nz, double cx,
                        double cy, double cz, double *partials, hipStream_t st)
 {
-    const int gx = (nx + kTX - 1) / kTX, gy = (ny + kTY - 1) / kTY;
-    if (!x_zero && gx * gy <= kRedBlocks) {
-        int gz = kRedBlocks / (gx * gy);
-        gz = gz < 1 ? 1 : (gz > nz ? nz : gz);
-        const int kchunk = (nz + gz - 1) / gz;
-        gz = (nz + kchunk - 1) / kchunk;
-        hipLaunchKernelGGL(k_resid_tiled, dim3(gx, gy, gz), dim3(kTileThreads), 0, st, b, x, r, nx, ny, nz, cx, cy,
-                           cz, kchunk, partials);
+    ResidArgs a{b, x, r, nx, ny, nz, cx, cy, cz, 0, x_zero, partials};
+    dim3 grid;
+    if (!x_zero && tile_grid(nx, ny, nz, grid, a.kchunk)) {
+        SMG_LAUNCH_G(LaunchEv{}, k_resid_tiled, k_resid_tiled_grp, grid, dim3(kTileThreads), 0, st, a);
         return;
     }
-    hipLaunchKernelGGL(k_init_resid, dim3(kRedBlocks), dim3(kRB), 0, st, b, x, r, x_zero, nx, ny, nz, cx, cy, cz,
-                       partials);
+    SMG_LAUNCH_G(LaunchEv{}, k_init_resid, k_init_resid_grp, dim3(kRedBlocks), dim3(kRB), 0, st, a);
 }
 
 void launch_dots_sr_sq(const double *s, const double *r, const double *q, int want_sq, size_t n, double *partials,
                        hipStream_t st)
 {
-    hipLaunchKernelGGL(k_dots_sr_sq, dim3(kRedBlocks), dim3(kRB), 0, st, s, r, q, want_sq,
-                       static_cast<long long>(n), partials);
+    const DotsArgs a{s, r, q, want_sq, static_cast<long long>(n), partials};
+    SMG_LAUNCH_G(LaunchEv{}, k_dots_sr_sq, k_dots_sr_sq_grp, dim3(kRedBlocks), dim3(kRB), 0, st, a);
 }
 
 void launch_update_p_q(const double *s, const double *p_old, double *p_new, double *q, const KScalars *sc, int nx,
                        int ny, int nz, double cx, double cy, double cz, double *partials, hipStream_t st)
 {
-    const int gx = (nx + kTX - 1) / kTX, gy = (ny + kTY - 1) / kTY;
-    if (gx * gy <= kRedBlocks) {
-        int gz = kRedBlocks / (gx * gy);
-        gz = gz < 1 ? 1 : (gz > nz ? nz : gz);
-        const int kchunk = (nz + gz - 1) / gz;
-        gz = (nz + kchunk - 1) / kchunk;
-        hipLaunchKernelGGL(k_update_p_q_tiled, dim3(gx, gy, gz), dim3(kTileThreads), 0, st, s, p_old, p_new, q, sc,
-                           nx, ny, nz, cx, cy, cz, kchunk, partials);
+    UpdPQArgs a{s, p_old, p_new, q, sc, nx, ny, nz, cx, cy, cz, 0, partials};
+    dim3 grid;
+    if (tile_grid(nx, ny, nz, grid, a.kchunk)) {
+        SMG_LAUNCH_G(LaunchEv{}, k_update_p_q_tiled, k_update_p_q_tiled_grp, grid, dim3(kTileThreads), 0, st, a);
         return;
     }
-    hipLaunchKernelGGL(k_update_p_q, dim3(kRedBlocks), dim3(kRB), 0, st, s, p_old, p_new, q, sc, nx, ny, nz, cx, cy,
-                       cz, partials);
+    SMG_LAUNCH_G(LaunchEv{}, k_update_p_q, k_update_p_q_grp, dim3(kRedBlocks), dim3(kRB), 0, st, a);
 }
 
 void launch_update_xr(double *x, double *r, const double *p, const double *q, const KScalars *sc, size_t n,
                       double *partials, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_update_xr, dim3(kRedBlocks), dim3(kRB), 0, st, x, r, p, q, sc, static_cast<long long>(n),
-                       partials);
+    const UpdXRArgs a{x, r, p, q, sc, static_cast<long long>(n), partials};
+    SMG_LAUNCH_G(LaunchEv{}, k_update_xr, k_update_xr_grp, dim3(kRedBlocks), dim3(kRB), 0, st, a);
 }
 
 void launch_finalize(int which, int method, int k, const double *partials, KScalars *sc, KScalars *host_copy,
                      hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRB), 0, st, which, method, k, partials, sc);
+    FinArgs a{};
+    a.which = which;
+    a.method = method;
+    a.k = k;
+    a.partials = partials;
+    a.sc = sc;
+    SMG_LAUNCH_G(LaunchEv{}, k_finalize, k_finalize_grp, dim3(1), dim3(kRB), 0, st, a);
     if (host_copy) (void)hipMemcpyAsync(host_copy, sc, sizeof(KScalars), hipMemcpyDeviceToHost, st);
+}
+
+void launch_finalize_batched(int which, int method, const double *partials, KScalars *sc, double rtol, int max_iter,
+                             hipStream_t st)
+{
+    FinArgs a{};
+    a.which = which;
+    a.method = method;
+    a.partials = partials;
+    a.sc = sc;
+    a.batched = 1;
+    a.rtol = rtol;
+    a.max_iter = max_iter;
+    SMG_LAUNCH_G(LaunchEv{}, k_finalize, k_finalize_grp, dim3(1), dim3(kRB), 0, st, a);
 }
 
 void launch_copy(const double *src, double *dst, size_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_copy, dim3(kRedBlocks), dim3(256), 0, st, src, dst, static_cast<long long>(n));
+    const CopyArgs a{src, dst, static_cast<long long>(n)};
+    SMG_LAUNCH_G(LaunchEv{}, k_copy, k_copy_grp, dim3(kRedBlocks), dim3(256), 0, st, a);
 }
 
 void launch_true_resid(const double *b, const double *x, double *tmp, int nx, int ny, int nz, double cx, double cy,

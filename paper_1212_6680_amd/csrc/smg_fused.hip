@@ -21,6 +21,7 @@
 // every global load a workgroup needs is issued before its first barrier.
 // Lines are held in registers (E = ceil(nx/64) points per lane) and stored in
 // LDS lane-interleaved (point e of lane l at [e*64 + l]): conflict-free.
+#include "group.h"
 #include "line_ops.hpp"
 
 namespace smg {
@@ -48,15 +49,15 @@ __device__ inline const LineCoef<A> *plane_lines(const PlaneCoef<A> *pc, int k, 
 // keeps S <= W - 3 so that every phase is one line per wave.
 // ---------------------------------------------------------------------------
 template <typename T, typename A, int E>
-__global__ __launch_bounds__(kThreads) void k2_down(Down2Args<T, A> a)
+__device__ __forceinline__ void k2_down_body(const Down2Args<T, A> &a, const Blk &blk)
 {
     extern __shared__ unsigned char smem_raw[];
     A *xs = reinterpret_cast<A *>(smem_raw);
     const int lane = threadIdx.x & 63, w = wave_id();
     const int nstrip = (a.nyc + a.S - 1) / a.S;
-    const int strip = blockIdx.x % nstrip;
-    const int p = (blockIdx.x / nstrip) % a.np;
-    const int r = blockIdx.x / (nstrip * a.np);
+    const int strip = blk.x % nstrip;
+    const int p = (blk.x / nstrip) % a.np;
+    const int r = blk.x / (nstrip * a.np);
     const int J0 = strip * a.S, J1 = min(J0 + a.S, a.nyc);
     const int ny = a.ny, nx = a.nx, nxp = a.nxp;
     const int base = 2 * J0 - 2;
@@ -144,6 +145,36 @@ __global__ __launch_bounds__(kThreads) void k2_down(Down2Args<T, A> a)
     }
 }
 
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(kThreads) void k2_down(Down2Args<T, A> a)
+{
+    k2_down_body<T, A, E>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(kThreads) void k2_down_grp(const GroupEntry *tab, int n)
+{
+    const Down2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k2_down_body<T, A, E>(*a, blk);
+}
+
+// grouped launch for any E <= 4 (boxes of different widths share one launch)
+template <typename T, typename A>
+__global__ __launch_bounds__(kThreads) void k2_down_grp_e4(const GroupEntry *tab, int n)
+{
+    const Down2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    switch (a->nxp / 64) {
+    case 1: k2_down_body<T, A, 1>(*a, blk); break;
+    case 2: k2_down_body<T, A, 2>(*a, blk); break;
+    case 3: k2_down_body<T, A, 3>(*a, blk); break;
+    default: k2_down_body<T, A, 4>(*a, blk); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k2_down_reg: the same stage with one wave per coarse line J and nothing but
 // registers: the wave solves the F lines 2J-2, 2J, 2J+2, 2J+4 and the C lines
@@ -153,10 +184,10 @@ __global__ __launch_bounds__(kThreads) void k2_down(Down2Args<T, A> a)
 // line fits in 4 points per lane (nx <= 256).
 // ---------------------------------------------------------------------------
 template <typename T, typename A, int E>
-__global__ __launch_bounds__(256) void k2_down_reg(Down2Args<T, A> a)
+__device__ __forceinline__ void k2_down_reg_body(const Down2Args<T, A> &a, const Blk &blk)
 {
     const int lane = threadIdx.x & 63;
-    const long long wv = static_cast<long long>(blockIdx.x) * 4 + wave_id();
+    const long long wv = static_cast<long long>(blk.x) * 4 + wave_id();
     const long long total = static_cast<long long>(a.nyc) * a.np * a.nrhs;
     if (wv >= total) return;   // whole waves
     const int J = static_cast<int>(wv % a.nyc);
@@ -253,6 +284,36 @@ __global__ __launch_bounds__(256) void k2_down_reg(Down2Args<T, A> a)
     gstore<T, A, E>(a.bc + r * a.crs + p * a.cps + static_cast<long long>(J) * nx, acc, nx, lane);
 }
 
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(256) void k2_down_reg(Down2Args<T, A> a)
+{
+    k2_down_reg_body<T, A, E>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(256) void k2_down_reg_grp(const GroupEntry *tab, int n)
+{
+    const Down2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k2_down_reg_body<T, A, E>(*a, blk);
+}
+
+// grouped launch for any E <= 4 (boxes of different widths share one launch)
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k2_down_reg_grp_e4(const GroupEntry *tab, int n)
+{
+    const Down2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    switch (a->nxp / 64) {
+    case 1: k2_down_reg_body<T, A, 1>(*a, blk); break;
+    case 2: k2_down_reg_body<T, A, 2>(*a, blk); break;
+    case 3: k2_down_reg_body<T, A, 3>(*a, blk); break;
+    default: k2_down_reg_body<T, A, 4>(*a, blk); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k2_coarse: the 2D sub-cycle from level l0 down, every line in LDS; one
 // workgroup per (plane, rhs).  Generic smoothing counts, F-then-C order.
@@ -284,12 +345,12 @@ __device__ inline void lds_relax(A *xs, const A *bs, const LineCoef<A> *lc, cons
 }
 
 template <typename T, typename A, int E>
-__global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
+__device__ __forceinline__ void k2_coarse_body(const Coarse2Args<T, A> &a, const Blk &blk)
 {
     extern __shared__ unsigned char smem_raw[];
     A *sm = reinterpret_cast<A *>(smem_raw);
     const int lane = threadIdx.x & 63, w = wave_id();
-    const int p = blockIdx.x % a.np, r = blockIdx.x / a.np;
+    const int p = blk.x % a.np, r = blk.x / a.np;
     const int nx = a.nx, nxp = a.nxp;
     const int k = p * a.kmul + a.koff;
     const LineCoef<A> *lcp = plane_lines(a.pc, k, a.lc, a.lines_total);
@@ -420,6 +481,36 @@ __global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
     }
 }
 
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(kThreads) void k2_coarse(Coarse2Args<T, A> a)
+{
+    k2_coarse_body<T, A, E>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(kThreads) void k2_coarse_grp(const GroupEntry *tab, int n)
+{
+    const Coarse2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k2_coarse_body<T, A, E>(*a, blk);
+}
+
+// grouped launch for any E <= 4 (boxes of different widths share one launch)
+template <typename T, typename A>
+__global__ __launch_bounds__(kThreads) void k2_coarse_grp_e4(const GroupEntry *tab, int n)
+{
+    const Coarse2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    switch (a->nxp / 64) {
+    case 1: k2_coarse_body<T, A, 1>(*a, blk); break;
+    case 2: k2_coarse_body<T, A, 2>(*a, blk); break;
+    case 3: k2_coarse_body<T, A, 3>(*a, blk); break;
+    default: k2_coarse_body<T, A, 4>(*a, blk); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Prolongation chains.  For a run [j0, j1) of fine indices the chain needs,
 // at every coarser level, the index window [lo, hi] with lo = floor((lo_f-1)/2)
@@ -461,13 +552,13 @@ __device__ inline A prolong_point(const A *vc, Win wc, int jj, int nc, int col)
 }
 
 template <typename T, typename A>
-__global__ __launch_bounds__(256) void k2_chain(Chain2Args<T, A> a)
+__device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const Blk &blk)
 {
     __shared__ A vs[2][kChainWin * kChainCols];
     const int nx = a.nx;
     const int ncol = (nx + kChainCols - 1) / kChainCols;
     const int nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
-    int bid = blockIdx.x;
+    int bid = blk.x;
     const int ct = bid % ncol;
     bid /= ncol;
     const int rt = bid % nrun;
@@ -516,15 +607,30 @@ __global__ __launch_bounds__(256) void k2_chain(Chain2Args<T, A> a)
 }
 
 template <typename T, typename A>
-__global__ __launch_bounds__(256) void k3_chain(Chain3Args<T, A> a)
+__global__ __launch_bounds__(256) void k2_chain(Chain2Args<T, A> a)
+{
+    k2_chain_body<T, A>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k2_chain_grp(const GroupEntry *tab, int n)
+{
+    const Chain2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k2_chain_body<T, A>(*a, blk);
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const Blk &blk)
 {
     __shared__ A vs[2][kChainWin * kChainCols];
     const long long pl = static_cast<long long>(a.nx) * a.ny;
     const int ncol = static_cast<int>((pl + kChainCols - 1) / kChainCols);
     const int nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
-    const int ct = blockIdx.x % ncol;
-    const int rt = blockIdx.x / ncol;
-    const int r = blockIdx.y;
+    const int ct = blk.x % ncol;
+    const int rt = blk.x / ncol;
+    const int r = blk.y;
     const int col = threadIdx.x & (kChainCols - 1), row0 = threadIdx.x >> 6;
     const long long c = static_cast<long long>(ct) * kChainCols + col;
     const Win w0{rt * kChainRun, min(a.nz[0], rt * kChainRun + kChainRun) - 1};
@@ -562,6 +668,21 @@ __global__ __launch_bounds__(256) void k3_chain(Chain3Args<T, A> a)
     }
 }
 
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k3_chain(Chain3Args<T, A> a)
+{
+    k3_chain_body<T, A>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k3_chain_grp(const GroupEntry *tab, int n)
+{
+    const Chain3Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k3_chain_body<T, A>(*a, blk);
+}
+
 // ---------------------------------------------------------------------------
 // k2_up: prolongation and one post-smoothing sweep (C then F) of a strip of
 // fine lines [j0, j0 + 2S).  LDS slot s holds fine line j0 - 2 + s.
@@ -569,16 +690,16 @@ __global__ __launch_bounds__(256) void k3_chain(Chain3Args<T, A> a)
 // out: this level's result (a different buffer), assigned or accumulated.
 // ---------------------------------------------------------------------------
 template <typename T, typename A, int E>
-__global__ __launch_bounds__(kThreads) void k2_up(Up2Args<T, A> a)
+__device__ __forceinline__ void k2_up_body(const Up2Args<T, A> &a, const Blk &blk)
 {
     extern __shared__ unsigned char smem_raw[];
     A *xs = reinterpret_cast<A *>(smem_raw);
     const int lane = threadIdx.x & 63, w = wave_id();
     const int ny = a.ny, nyc = a.nyc, nx = a.nx, nxp = a.nxp;
     const int nstrip = (ny + 2 * a.S - 1) / (2 * a.S);
-    const int strip = blockIdx.x % nstrip;
-    const int p = (blockIdx.x / nstrip) % a.np;
-    const int r = blockIdx.x / (nstrip * a.np);
+    const int strip = blk.x % nstrip;
+    const int p = (blk.x / nstrip) % a.np;
+    const int r = blk.x / (nstrip * a.np);
     const int j0 = strip * 2 * a.S, j1 = min(j0 + 2 * a.S, ny);
     const int base = j0 - 2;
     const int jlo = max(0, j0 - 2), jhi = min(ny - 1, j1 + 1);
@@ -648,7 +769,44 @@ __global__ __launch_bounds__(kThreads) void k2_up(Up2Args<T, A> a)
     }
 }
 
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(kThreads) void k2_up(Up2Args<T, A> a)
+{
+    k2_up_body<T, A, E>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(kThreads) void k2_up_grp(const GroupEntry *tab, int n)
+{
+    const Up2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k2_up_body<T, A, E>(*a, blk);
+}
+
+// grouped launch for any E <= 4 (boxes of different widths share one launch)
+template <typename T, typename A>
+__global__ __launch_bounds__(kThreads) void k2_up_grp_e4(const GroupEntry *tab, int n)
+{
+    const Up2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    switch (a->nxp / 64) {
+    case 1: k2_up_body<T, A, 1>(*a, blk); break;
+    case 2: k2_up_body<T, A, 2>(*a, blk); break;
+    case 3: k2_up_body<T, A, 3>(*a, blk); break;
+    default: k2_up_body<T, A, 4>(*a, blk); break;
+    }
+}
+
 inline unsigned nb(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+// grouped twin for width E: the any-E kernel up to E = 4, else the E-specific one
+template <int E, typename K4, typename KE>
+inline const void *grouped_e4(K4 k4, KE ke)
+{
+    return E <= 4 ? reinterpret_cast<const void *>(k4) : reinterpret_cast<const void *>(ke);
+}
 
 template <typename K>
 inline void allow_lds(K kernel, size_t bytes)
@@ -684,10 +842,10 @@ void launch_down2(const Down2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
         if (waves == 0) return;
         const dim3 grid(static_cast<unsigned>((waves + 3) / 4));
         switch (E) {
-        case 1: SMG_LAUNCH(ev, (k2_down_reg<T, A, 1>), grid, dim3(256), 0, st, a); break;
-        case 2: SMG_LAUNCH(ev, (k2_down_reg<T, A, 2>), grid, dim3(256), 0, st, a); break;
-        case 3: SMG_LAUNCH(ev, (k2_down_reg<T, A, 3>), grid, dim3(256), 0, st, a); break;
-        default: SMG_LAUNCH(ev, (k2_down_reg<T, A, 4>), grid, dim3(256), 0, st, a); break;
+        case 1: SMG_LAUNCH_G(ev, (k2_down_reg<T, A, 1>), (k2_down_reg_grp_e4<T, A>), grid, dim3(256), 0, st, a); break;
+        case 2: SMG_LAUNCH_G(ev, (k2_down_reg<T, A, 2>), (k2_down_reg_grp_e4<T, A>), grid, dim3(256), 0, st, a); break;
+        case 3: SMG_LAUNCH_G(ev, (k2_down_reg<T, A, 3>), (k2_down_reg_grp_e4<T, A>), grid, dim3(256), 0, st, a); break;
+        default: SMG_LAUNCH_G(ev, (k2_down_reg<T, A, 4>), (k2_down_reg_grp_e4<T, A>), grid, dim3(256), 0, st, a); break;
         }
         return;
     }
@@ -695,8 +853,10 @@ void launch_down2(const Down2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
     const long long nblk = static_cast<long long>(nstrip) * a.np * a.nrhs;
     if (nblk == 0) return;
     const size_t lds = static_cast<size_t>(2 * a.S + 5) * a.nxp * sizeof(A);
-    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_down<T, A, EE>, lds);
-                 SMG_LAUNCH(ev, (k2_down<T, A, EE>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds, st, a));
+    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_down<T, A, EE>, lds); allow_lds(k2_down_grp<T, A, EE>, lds);
+                 allow_lds(k2_down_grp_e4<T, A>, lds);
+                 SMG_LAUNCH_G(ev, (k2_down<T, A, EE>), (grouped_e4<EE>(k2_down_grp_e4<T, A>, k2_down_grp<T, A, EE>)),
+                              dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds, st, a));
 }
 
 template <typename T, typename A>
@@ -704,9 +864,11 @@ void launch_coarse2(const Coarse2Args<T, A> &a, size_t lds_bytes, hipStream_t st
 {
     const long long nblk = static_cast<long long>(a.np) * a.nrhs;
     if (nblk == 0) return;
-    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_coarse<T, A, EE>, lds_bytes);
-                 SMG_LAUNCH(ev, (k2_coarse<T, A, EE>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds_bytes,
-                            st, a));
+    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_coarse<T, A, EE>, lds_bytes); allow_lds(k2_coarse_grp<T, A, EE>, lds_bytes);
+                 allow_lds(k2_coarse_grp_e4<T, A>, lds_bytes);
+                 SMG_LAUNCH_G(ev, (k2_coarse<T, A, EE>),
+                              (grouped_e4<EE>(k2_coarse_grp_e4<T, A>, k2_coarse_grp<T, A, EE>)),
+                              dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds_bytes, st, a));
 }
 
 template <typename T, typename A>
@@ -716,7 +878,7 @@ void launch_chain2(const Chain2Args<T, A> &a, hipStream_t st, const LaunchEv &ev
     const long long nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
     const long long nblk = ncol * nrun * a.np * a.nrhs;
     if (nblk == 0) return;
-    SMG_LAUNCH(ev, (k2_chain<T, A>), dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, a);
+    SMG_LAUNCH_G(ev, (k2_chain<T, A>), (k2_chain_grp<T, A>), dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
@@ -726,8 +888,10 @@ void launch_up2(const Up2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
     const long long nblk = static_cast<long long>(nstrip) * a.np * a.nrhs;
     if (nblk == 0) return;
     const size_t lds = static_cast<size_t>(2 * a.S + 4) * a.nxp * sizeof(A);
-    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_up<T, A, EE>, lds);
-                 SMG_LAUNCH(ev, (k2_up<T, A, EE>), dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds, st, a));
+    SMG_E_SWITCH(a.nxp / 64, allow_lds(k2_up<T, A, EE>, lds); allow_lds(k2_up_grp<T, A, EE>, lds);
+                 allow_lds(k2_up_grp_e4<T, A>, lds);
+                 SMG_LAUNCH_G(ev, (k2_up<T, A, EE>), (grouped_e4<EE>(k2_up_grp_e4<T, A>, k2_up_grp<T, A, EE>)),
+                              dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds, st, a));
 }
 
 template <typename T, typename A>
@@ -736,7 +900,8 @@ void launch_chain3(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const La
     const long long pl = static_cast<long long>(a.nx) * a.ny;
     const long long ncol = (pl + kChainCols - 1) / kChainCols;
     const long long nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
-    SMG_LAUNCH(ev, (k3_chain<T, A>), dim3(static_cast<unsigned>(ncol * nrun), nrhs), dim3(256), 0, st, a);
+    SMG_LAUNCH_G(ev, (k3_chain<T, A>), (k3_chain_grp<T, A>), dim3(static_cast<unsigned>(ncol * nrun), nrhs), dim3(256), 0,
+                 st, a);
 }
 
 #define SMG_FUSED_INSTANTIATE(T, A)                                                                      \

@@ -819,6 +819,27 @@ int smg_handle_size(const smg_handle *h, size_t *n)
 
 const smg_grid *smg_handle_grid(const smg_handle *h) { return h ? &h->g : nullptr; }
 
+int smg::krylov_view(smg_handle *h, KrylovView *v)
+{
+    if (!h || !v) return SMG_EINVAL;
+    v->r = h->at<double>(h->L.kr);
+    v->s = h->at<double>(h->L.ks);
+    v->q = h->at<double>(h->L.kq);
+    v->pa = h->at<double>(h->L.kp0);
+    v->pb = h->at<double>(h->L.kp1);
+    v->part = h->at<double>(h->L.part);
+    v->sc = h->at<KScalars>(h->L.sc);
+    v->g = h->g;
+    v->n = h->N;
+    v->precision = h->o.precision;
+    return SMG_OK;
+}
+
+void smg::vcycle_apply(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
+{
+    vcycle(h, r, s, nrhs, ld, st);
+}
+
 int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs)
 {
     if (!h || !max_nrhs) return SMG_EINVAL;

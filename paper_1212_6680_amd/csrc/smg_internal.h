@@ -19,9 +19,17 @@ struct LaunchEv {
     hipEvent_t e1 = nullptr;
 };
 
+// Launch recorder of the grouped (batched) path, see group.h.  A launch site
+// without a grouped twin marks the recording unusable.
+struct LaunchRec;
+extern thread_local std::vector<LaunchRec> *g_rec;
+extern thread_local int g_rec_unsupported;
+
 #define SMG_LAUNCH(EV, K, G, B, L, S, ...)                                          \
     do {                                                                            \
-        if ((EV).e0)                                                                \
+        if (smg::g_rec)                                                             \
+            smg::g_rec_unsupported = 1;                                             \
+        else if ((EV).e0)                                                           \
             hipExtLaunchKernelGGL(K, G, B, L, S, (EV).e0, (EV).e1, 0, __VA_ARGS__); \
         else                                                                        \
             hipLaunchKernelGGL(K, G, B, L, S, __VA_ARGS__);                         \
@@ -159,6 +167,7 @@ struct Restrict3Args {
     A cx, cy;
     const PlaneCoef<A> *pc;
     int x_zero;             // x is known to be zero: bc = P^T b
+    int kchunk;             // coarse planes per block of the marching kernel (set by the launcher)
 };
 
 template <typename T, typename A>
@@ -267,10 +276,62 @@ void launch_convert_out(const T *src, long long lds, double *dst, long long ldd,
 struct KScalars {           // device-resident recurrence scalars
     double sr, sr_prev, sq, pq, alpha, alpha_prev, beta, rr, bb;
     int breakdown;
-    int pad;
+    int nonfinite;          // batched: non-finite start
+    // batched solves: device-side iteration count and stopping test
+    double rtol, bden, true_rr;
+    int active, iters, max_iter, pad;
 };
 
 constexpr int kRedBlocks = 1024;   // fixed grid of the first reduction stage
+
+// argument blocks of the Krylov kernels
+struct ResidArgs {
+    const double *b, *x;
+    double *r;
+    int nx, ny, nz;
+    double cx, cy, cz;
+    int kchunk, x_zero;
+    double *partials;
+};
+struct DotsArgs {
+    const double *s, *r, *q;
+    int want_sq;
+    long long n;
+    double *partials;
+};
+struct UpdPQArgs {
+    const double *s, *p_old;
+    double *p_new, *q;
+    const KScalars *sc;
+    int nx, ny, nz;
+    double cx, cy, cz;
+    int kchunk;
+    double *partials;
+};
+struct UpdXRArgs {
+    double *x, *r;
+    const double *p, *q;
+    const KScalars *sc;
+    long long n;
+    double *partials;
+};
+struct FinArgs {
+    int which, method, k, batched;
+    const double *partials;
+    KScalars *sc;
+    double rtol;
+    int max_iter, pad;
+};
+struct CopyArgs {
+    const double *src;
+    double *dst;
+    long long n;
+};
+struct FillArgs {
+    double *dst;
+    double v;
+    long long n;
+};
 
 void launch_matvec7(const double *x, double *y, long long ld, int nrhs, int nx, int ny, int nz,
                     double cx, double cy, double cz, hipStream_t st);
@@ -286,11 +347,27 @@ void launch_update_xr(double *x, double *r, const double *p, const double *q, co
 // which: 0 = init (rr, bb), 1 = beta (sr, sq), 2 = alpha (pq), 3 = rr
 void launch_finalize(int which, int method, int k, const double *partials, KScalars *sc, KScalars *host_copy,
                      hipStream_t st);
+// batched mode of finalize: stopping test on the device (see KScalars)
+void launch_finalize_batched(int which, int method, const double *partials, KScalars *sc, double rtol, int max_iter,
+                             hipStream_t st);
 void launch_copy(const double *src, double *dst, size_t n, hipStream_t st);
 void launch_fill(double *dst, double v, size_t n, hipStream_t st);
 void launch_true_resid(const double *b, const double *x, double *tmp, int nx, int ny, int nz, double cx,
                        double cy, double cz, double *partials, hipStream_t st);
 
+}  // namespace smg
+
+namespace smg {
+// The Krylov buffers of a handle and its V-cycle, for the batched driver.
+struct KrylovView {
+    double *r, *s, *q, *pa, *pb, *part;
+    KScalars *sc;
+    smg_grid g;
+    size_t n;
+    int precision;
+};
+int krylov_view(smg_handle *h, KrylovView *v);
+void vcycle_apply(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st);
 }  // namespace smg
 
 // Handle queries shared by the library's translation units.

@@ -16,6 +16,7 @@
 // lives in the registers of one wave (E = ceil(nx/64) points per lane) and
 // the two first-order recurrences of the Thomas algorithm are evaluated as
 // affine-map scans across the 64 lanes.
+#include "group.h"
 #include "smg_internal.h"
 
 namespace smg {
@@ -258,16 +259,31 @@ __device__ inline A resid3_point(const T *x, const T *b, const PlaneCoef<A> *pc,
 }
 
 template <typename T, typename A>
-__global__ __launch_bounds__(256) void k_resid3(Resid3Args<T, A> a)
+__device__ __forceinline__ void k_resid3_body(const Resid3Args<T, A> &a, const Blk &blk)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blk.x * blockDim.x + threadIdx.x;
     if (c >= a.nx * a.ny) return;
     const int i = c % a.nx, j = c / a.nx;
-    const int p = blockIdx.y, r = blockIdx.z;
+    const int p = blk.y, r = blk.z;
     const int k = p * a.kmul + a.koff;
     const A v = resid3_point<T, A>(a.x + r * a.xrs, a.b + r * a.brs, a.pc, a.cx, a.cy, a.nx, a.ny, a.nz, k, i, j,
                                    a.self_zero != 0);
     stv(a.r + r * a.rrs + p * a.rps + c, v);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k_resid3(Resid3Args<T, A> a)
+{
+    k_resid3_body<T, A>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k_resid3_grp(const GroupEntry *tab, int n)
+{
+    const Resid3Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k_resid3_body<T, A>(*a, blk);
 }
 
 template <typename T, typename A>
@@ -283,12 +299,12 @@ __global__ __launch_bounds__(256) void k_correct3(Correct3Args<T, A> a)
 }
 
 template <typename T, typename A>
-__global__ __launch_bounds__(256) void k_restrict3(Restrict3Args<T, A> a)
+__device__ __forceinline__ void k_restrict3_body(const Restrict3Args<T, A> &a, const Blk &blk)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blk.x * blockDim.x + threadIdx.x;
     if (c >= a.nx * a.ny) return;
     const int i = c % a.nx, j = c / a.nx;
-    const int K = blockIdx.y, r = blockIdx.z;
+    const int K = blk.y, r = blk.z;
     const T *x = a.x + r * a.xrs;
     const T *b = a.b + r * a.brs;
     const bool xz = a.x_zero != 0;
@@ -298,6 +314,21 @@ __global__ __launch_bounds__(256) void k_restrict3(Restrict3Args<T, A> a)
         v += A(0.5) * resid3_point<T, A>(x, b, a.pc, a.cx, a.cy, a.nx, a.ny, a.nz, 2 * K + 2, i, j, false, xz);
     const long long pl = static_cast<long long>(a.nx) * a.ny;
     stv(a.bc + r * a.crs + K * pl + c, v);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k_restrict3(Restrict3Args<T, A> a)
+{
+    k_restrict3_body<T, A>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k_restrict3_grp(const GroupEntry *tab, int n)
+{
+    const Restrict3Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k_restrict3_body<T, A>(*a, blk);
 }
 
 template <typename T, typename A>
@@ -372,18 +403,18 @@ __global__ void k_convert_out(const T *src, long long lds, double *dst, long lon
 constexpr int kRTX = 64, kRTY = 8, kRThreads = kRTX * kRTY;
 
 template <typename T, typename A>
-__global__ __launch_bounds__(kRThreads) void k_restrict3_march(Restrict3Args<T, A> a, int kchunk)
+__device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A> &a, const Blk &blk)
 {
     __shared__ A tile[(kRTY + 2) * (kRTX + 2)];
     const int tx = threadIdx.x % kRTX, ty = threadIdx.x / kRTX;
-    const int i = blockIdx.x * kRTX + tx, j = blockIdx.y * kRTY + ty;
+    const int i = blk.x * kRTX + tx, j = blk.y * kRTY + ty;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const bool in = i < nx && j < ny;
     const long long pl = static_cast<long long>(nx) * ny;
     const long long c2 = static_cast<long long>(j) * nx + i;
-    const int r = blockIdx.z / ((a.nzc + kchunk - 1) / kchunk);
-    const int K0 = (blockIdx.z % ((a.nzc + kchunk - 1) / kchunk)) * kchunk;
-    const int K1 = min(a.nzc, K0 + kchunk);
+    const int r = blk.z / ((a.nzc + a.kchunk - 1) / a.kchunk);
+    const int K0 = (blk.z % ((a.nzc + a.kchunk - 1) / a.kchunk)) * a.kchunk;
+    const int K1 = min(a.nzc, K0 + a.kchunk);
     const T *x = a.x + r * a.xrs;
     const T *b = a.b + r * a.brs;
     // this thread's halo point, if any
@@ -393,7 +424,7 @@ __global__ __launch_bounds__(kRThreads) void k_restrict3_march(Restrict3Args<T, 
     else if (t < 2 * kRTX) { hy = kRTY + 1; hx = t - kRTX + 1; }
     else if (t < 2 * kRTX + kRTY) { hy = t - 2 * kRTX + 1; hx = 0; }
     else if (t < 2 * kRTX + 2 * kRTY) { hy = t - 2 * kRTX - kRTY + 1; hx = kRTX + 1; }
-    const int hi = blockIdx.x * kRTX + hx - 1, hj = blockIdx.y * kRTY + hy - 1;
+    const int hi = blk.x * kRTX + hx - 1, hj = blk.y * kRTY + hy - 1;
     const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
     const long long hc2 = static_cast<long long>(hj) * nx + hi;
     const int cc = (ty + 1) * (kRTX + 2) + tx + 1;
@@ -434,6 +465,21 @@ __global__ __launch_bounds__(kRThreads) void k_restrict3_march(Restrict3Args<T, 
         if (in) stv(a.bc + r * a.crs + K * pl + c2, A(0.5) * r_even + r_odd + A(0.5) * r_next);
         r_even = r_next;
     }
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(kRThreads) void k_restrict3_march(Restrict3Args<T, A> a)
+{
+    k_restrict3_march_body<T, A>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(kRThreads) void k_restrict3_march_grp(const GroupEntry *tab, int n)
+{
+    const Restrict3Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    k_restrict3_march_body<T, A>(*a, blk);
 }
 
 inline unsigned blocks_for(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
@@ -487,7 +533,7 @@ void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st, const LaunchEv &ev
 {
     if (a.np == 0) return;
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.np, a.nrhs);
-    SMG_LAUNCH(ev, (k_resid3<T, A>), grid, dim3(256), 0, st, a);
+    SMG_LAUNCH_G(ev, (k_resid3<T, A>), (k_resid3_grp<T, A>), grid, dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
@@ -509,11 +555,13 @@ void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st, const Launch
         const int kchunk = (a.nzc + nzb - 1) / nzb;
         nzb = (a.nzc + kchunk - 1) / kchunk;
         const dim3 grid(gx, gy, nzb * a.nrhs);
-        SMG_LAUNCH(ev, (k_restrict3_march<T, A>), grid, dim3(kRThreads), 0, st, a, kchunk);
+        Restrict3Args<T, A> am = a;
+        am.kchunk = kchunk;
+        SMG_LAUNCH_G(ev, (k_restrict3_march<T, A>), (k_restrict3_march_grp<T, A>), grid, dim3(kRThreads), 0, st, am);
         return;
     }
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.nzc, a.nrhs);
-    SMG_LAUNCH(ev, (k_restrict3<T, A>), grid, dim3(256), 0, st, a);
+    SMG_LAUNCH_G(ev, (k_restrict3<T, A>), (k_restrict3_grp<T, A>), grid, dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>

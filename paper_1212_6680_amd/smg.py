@@ -94,6 +94,11 @@ def lib():
             L.lobpcg_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
             L.lobpcg_solve.argtypes = [p, i32, p, p, p, p, C.c_size_t,
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
+        L.smg_batch_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
+        L.smg_batch_create.argtypes = [p, i32, p, p, p, C.c_size_t, i32, p, C.POINTER(p)]
+        L.smg_batch_fpcg.argtypes = [p, C.POINTER(krylov_opts), p, p]
+        L.smg_batch_destroy.argtypes = [p]
+        L.smg_batch_stats.argtypes = [p, C.POINTER(i32), C.POINTER(i32)]
         L.net_workspace_bytes.argtypes = [i64, i32, i32, C.POINTER(C.c_size_t)]
         L.net_setup.argtypes = [i64, i32, i32, p, C.c_size_t, p, C.POINTER(p)]
         L.net_destroy.argtypes = [p]
@@ -371,3 +376,55 @@ class Net:
                                     C.c_void_p(targets.data_ptr()), C.c_void_p(sig.ctypes.data), _stream()),
                "net_make_pairs")
         return inputs, targets, sig
+
+
+class SMGBatch:
+    """Batched flexible PCG over independent boxes (smg_batch_* in include/smg.h).
+
+    smgs: list of FP64 SMG handles (one per box); b, x: lists of device vectors
+    bound to the batch.  use_graph: replay one captured iteration per step."""
+
+    def __init__(self, smgs, b, x, use_graph=True):
+        L = lib()
+        n = len(smgs)
+        if not (len(b) == len(x) == n) or n < 1:
+            raise SMGError("need one b and one x per box")
+        self.smgs, self.b, self.x = list(smgs), list(b), list(x)
+        for G, bi, xi in zip(self.smgs, self.b, self.x):
+            _dptr(bi, G.n)
+            _dptr(xi, G.n)
+        self._hs = (C.c_void_p * n)(*[G.h.value for G in self.smgs])
+        self._bp = (C.c_void_p * n)(*[bi.data_ptr() for bi in self.b])
+        self._xp = (C.c_void_p * n)(*[xi.data_ptr() for xi in self.x])
+        nbytes = C.c_size_t(0)
+        _check(L.smg_batch_workspace_bytes(C.cast(self._hs, C.c_void_p), n, C.byref(nbytes)),
+               "smg_batch_workspace_bytes")
+        self.ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.b[0].device)
+        h = C.c_void_p()
+        _check(L.smg_batch_create(C.cast(self._hs, C.c_void_p), n, C.cast(self._bp, C.c_void_p),
+                                  C.cast(self._xp, C.c_void_p), C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                  1 if use_graph else 0, _stream(), C.byref(h)), "smg_batch_create")
+        self.h = h
+        self.nbox = n
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.smg_batch_destroy(h)
+            self.h = None
+
+    def stats(self):
+        """(grouped launches per iteration, per-box launches they replace)."""
+        a, b = C.c_int32(0), C.c_int32(0)
+        _check(lib().smg_batch_stats(self.h, C.byref(a), C.byref(b)), "smg_batch_stats")
+        return a.value, b.value
+
+    def fpcg(self, rtol=1e-8, max_iter=500, zero_x0=True):
+        """Solves every box; returns one Info per box (status, iters, rel_res, true_rel_res, seconds)."""
+        o = krylov_opts(rtol, max_iter, PRECOND["smg"], 1 if zero_x0 else 0, 0, None, None)
+        infos = (krylov_info * self.nbox)()
+        code = lib().smg_batch_fpcg(self.h, C.byref(o), C.cast(infos, C.c_void_p), _stream())
+        if code < 0 and code != -4 and code != -5:
+            _check(code, "smg_batch_fpcg")
+        return [Info(iters=i.iters, status=i.status, rel_res=i.rel_res, true_rel_res=i.true_rel_res,
+                     seconds=i.solve_seconds) for i in infos]

@@ -73,3 +73,21 @@ def box_dims(count: int, lo: int, hi: int, seed: int) -> list:
     d = lo + np.floor(u * (hi - lo + 1)).astype(np.int64)
     d = np.minimum(d, hi)
     return [tuple(int(v) for v in d[3 * i:3 * i + 3]) for i in range(count)]
+
+
+NET_CHANNELS = (1, 16, 16, 16, 1)
+
+
+def he_init(seed: int) -> np.ndarray:
+    """Initial parameters of the learned post-smoother in the library's flat
+    order (per layer W[3][3][3][cin][cout], then b): weights normal with
+    variance 2/(27 cin) (He et al. 2015), biases normal with deviation 0.01,
+    from the Gaussian stream of `seed`."""
+    out, pos = [], 0
+    for ci, co in zip(NET_CHANNELS[:-1], NET_CHANNELS[1:]):
+        nw = 27 * ci * co
+        out.append(gaussian(seed, nw, pos) * np.sqrt(2.0 / (27 * ci)))
+        pos += nw
+        out.append(0.01 * gaussian(seed, co, pos))
+        pos += co
+    return np.concatenate(out)
