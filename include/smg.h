@@ -196,6 +196,22 @@ int smg_batch_fpcg(smg_batch *bt, const krylov_opts *o, krylov_info *infos, void
 int smg_batch_stats(const smg_batch *bt, int32_t *steps_per_iteration, int32_t *launches_per_iteration);
 int smg_batch_destroy(smg_batch *bt);
 
+/* Autotuner of the fused V-cycle schedule: times `reps` V-cycles s = T r for
+ * each distinct schedule given by candidate LDS budgets (which 2D levels the
+ * LDS-resident coarse kernel absorbs, and the strip heights of the wide-line
+ * kernels), keeps the fastest in the handle and reports it in info
+ * (nullable).  Every schedule computes the same V-cycle (up to rounding
+ * order).  s is overwritten.  Synchronises the stream. */
+typedef struct smg_tune_info {
+    int32_t candidates;     /* schedules timed, including the default */
+    int32_t l0;             /* first 2D level handled by the coarse kernel */
+    int32_t s_down, s_up;   /* strip heights */
+    int64_t coarse_lds;     /* LDS bytes of the coarse kernel */
+    double default_ms;      /* V-cycle time of the schedule before tuning */
+    double best_ms;         /* V-cycle time of the chosen schedule */
+} smg_tune_info;
+int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *stream, smg_tune_info *info);
+
 /* Releases the host-side handle (the caller's workspace is not freed). */
 int smg_destroy(smg_handle *h);
 

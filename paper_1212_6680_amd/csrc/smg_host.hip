@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <utility>
 
@@ -105,6 +106,7 @@ struct smg_handle {
     int l0;
     size_t coarse_lds;
     int S_down, S_up;
+    size_t coarse_budget, strip_budget;   // LDS budgets the schedule was built for
     char *ws;
     Layout L;
     KScalars *host_sc;            // pinned host mirror of the device scalars
@@ -144,7 +146,10 @@ size_t arith_size(int prec) { return prec == SMG_PREC_F64 ? 8 : 4; }
 constexpr size_t kCoarseLds = 128 * 1024;
 constexpr size_t kStripLds = 48 * 1024;
 
-void choose_fused_schedule(smg_handle *h)
+// Schedule of the fused 2D cycle for given LDS budgets: the coarse kernel
+// takes every 2D level from l0 down whose lines fit coarse_budget; the strip
+// kernels size their strips to strip_budget.
+void apply_fused_schedule(smg_handle *h, size_t coarse_budget, size_t strip_budget)
 {
     const size_t line = static_cast<size_t>(h->nxp) * arith_size(h->o.precision);
     const int nl = static_cast<int>(h->ny2.size());
@@ -154,19 +159,24 @@ void choose_fused_schedule(smg_handle *h)
         size_t lines = 0;
         for (int m = l; m < nl; ++m) lines += h->ny2[m];
         const size_t bytes = 2 * lines * line;
-        if (bytes > kCoarseLds) break;
+        if (bytes > coarse_budget) break;
         h->l0 = l;
         h->coarse_lds = bytes;
     }
     // k2_down handles one F line, one C line and one coarse line per wave
-    int S = static_cast<int>((kStripLds / line - 5) / 2);
+    const long long sl = static_cast<long long>(strip_budget / line);
+    long long S = (sl - 5) / 2;
     const int smax = fused_waves() - 3;
-    h->S_down = S < 1 ? 1 : (S > smax ? smax : S);
-    S = static_cast<int>((kStripLds / line - 4) / 2);
-    h->S_up = S < 1 ? 1 : (S > 16 ? 16 : S);
+    h->S_down = S < 1 ? 1 : (S > smax ? smax : static_cast<int>(S));
+    S = (sl - 4) / 2;
+    h->S_up = S < 1 ? 1 : (S > 16 ? 16 : static_cast<int>(S));
+    h->coarse_budget = coarse_budget;
+    h->strip_budget = strip_budget;
     h->fused = h->o.kernel_mode == 0 && nl <= kMaxLev && h->nz.size() <= static_cast<size_t>(kMaxLev3) &&
                h->coarse_lds > 0;
 }
+
+void choose_fused_schedule(smg_handle *h) { apply_fused_schedule(h, kCoarseLds, kStripLds); }
 
 // Table sizes need the dedup counts, which depend only on the grid; the
 // host part of the setup is cheap, so sizing runs it too.
@@ -976,6 +986,85 @@ const char *smg_strerror(int status)
     case SMG_ENONFINITE: return "non-finite input";
     default: return "unknown status";
     }
+}
+
+int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *stream, smg_tune_info *info)
+{
+    if (!h || !r || !s || reps < 1) return SMG_EINVAL;
+    hipStream_t st = as_stream(stream);
+    smg_tune_info inf{};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SMG_EHIP;
+    // a schedule whose launches the device rejects (e.g. too much LDS) is not a candidate
+    auto time_cycle = [&](double *ms) {
+        (void)hipGetLastError();
+        vcycle(h, r, s, 1, static_cast<long long>(h->N), st);   // warm-up (and LDS attributes)
+        if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) return false;
+        if (hipEventRecord(e0, st) != hipSuccess) return false;
+        for (int i = 0; i < reps; ++i) vcycle(h, r, s, 1, static_cast<long long>(h->N), st);
+        float t = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            return false;
+        *ms = t / reps;
+        return true;
+    };
+    int rc = SMG_OK;
+    double best = 0.0;
+    size_t best_c = h->coarse_budget, best_s = h->strip_budget;
+    if (!time_cycle(&best)) rc = SMG_EHIP;
+    inf.default_ms = best;
+    inf.candidates = 1;
+    if (rc == SMG_OK && h->fused) {
+        // candidate LDS budgets; budgets giving the same schedule are timed once
+        const size_t cb[] = {16 << 10, 32 << 10, 64 << 10, 96 << 10, 128 << 10, 160 << 10};
+        const size_t sb[] = {32 << 10, 48 << 10, 64 << 10, 96 << 10};
+        const bool strips = h->nxp / 64 > 4;   // strip kernels only run on wide lines
+        int dev = 0, max_lds = 64 << 10;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
+            max_lds <= 0)
+            max_lds = 64 << 10;
+        std::vector<std::tuple<int, size_t, int, int>> seen;
+        seen.emplace_back(h->l0, h->coarse_lds, h->S_down, h->S_up);
+        for (size_t c : cb)
+            for (size_t sbud : sb) {
+                if (!strips && sbud != h->strip_budget) continue;
+                if (c > static_cast<size_t>(max_lds) || sbud > static_cast<size_t>(max_lds)) continue;
+                const size_t keep_c = h->coarse_budget, keep_s = h->strip_budget;
+                apply_fused_schedule(h, c, sbud);
+                const auto key = std::make_tuple(h->l0, h->coarse_lds, h->S_down, h->S_up);
+                bool dup = !h->fused;
+                for (const auto &k : seen) dup = dup || k == key;
+                if (dup) {
+                    apply_fused_schedule(h, keep_c, keep_s);
+                    continue;
+                }
+                seen.push_back(key);
+                double ms = 0.0;
+                if (!time_cycle(&ms)) {
+                    apply_fused_schedule(h, keep_c, keep_s);
+                    continue;
+                }
+                ++inf.candidates;
+                if (ms < best) {
+                    best = ms;
+                    best_c = c;
+                    best_s = sbud;
+                }
+                apply_fused_schedule(h, keep_c, keep_s);
+            }
+        apply_fused_schedule(h, best_c, best_s);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    inf.best_ms = best;
+    inf.l0 = h->l0;
+    inf.coarse_lds = static_cast<int64_t>(h->coarse_lds);
+    inf.s_down = h->S_down;
+    inf.s_up = h->S_up;
+    if (info) *info = inf;
+    return rc;
 }
 
 int smg_profile_kernel(smg_handle *h, int32_t family, const double *r, double *s, int32_t reps, void *stream,

@@ -49,6 +49,11 @@ class krylov_info(C.Structure):
                 ("true_rel_res", C.c_double), ("solve_seconds", C.c_double)]
 
 
+class smg_tune_info(C.Structure):
+    _fields_ = [("candidates", C.c_int32), ("l0", C.c_int32), ("s_down", C.c_int32), ("s_up", C.c_int32),
+                ("coarse_lds", C.c_int64), ("default_ms", C.c_double), ("best_ms", C.c_double)]
+
+
 class lobpcg_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32),
                 ("guard", C.c_int32), ("reserved", C.c_int32)]
@@ -94,6 +99,7 @@ def lib():
             L.lobpcg_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
             L.lobpcg_solve.argtypes = [p, i32, p, p, p, p, C.c_size_t,
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
+        L.smg_autotune.argtypes = [p, p, p, i32, p, C.POINTER(smg_tune_info)]
         L.smg_batch_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
         L.smg_batch_create.argtypes = [p, i32, p, p, p, C.c_size_t, i32, p, C.POINTER(p)]
         L.smg_batch_fpcg.argtypes = [p, C.POINTER(krylov_opts), p, p]
@@ -255,6 +261,15 @@ class SMG:
         out = Info(iters=info.iters, nconv=info.nconv, status=info.status, seconds=info.seconds,
                    resnorms=np.array(res[:]))
         return np.array(lam[:]), X, out
+
+    def autotune(self, r: torch.Tensor, reps: int = 5):
+        """Times the candidate fused schedules on r and keeps the fastest; returns the tuning info."""
+        s = torch.empty_like(r)
+        info = smg_tune_info()
+        _check(lib().smg_autotune(self.h, _dptr(r, self.n), _dptr(s, self.n), reps, _stream(), C.byref(info)),
+               "smg_autotune")
+        return Info(candidates=info.candidates, l0=info.l0, s_down=info.s_down, s_up=info.s_up,
+                    coarse_lds=info.coarse_lds, default_ms=info.default_ms, best_ms=info.best_ms)
 
     def profile_kernel(self, family: str, r: torch.Tensor, reps: int = 3):
         """(launches per V-cycle, kernel ms per V-cycle, algorithmic bytes per V-cycle) of one kernel family."""

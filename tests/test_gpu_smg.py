@@ -159,3 +159,18 @@ def test_fused_schedule_low_precision(prec):
         a = _smg(shape, c, *pp, precision=prec, kernel_mode=0).apply(r).cpu().numpy()
         b = _smg(shape, c, *pp, precision=prec, kernel_mode=1).apply(r).cpu().numpy()
         assert _relerr(a, b) <= (1e-5 if prec == "f32" else 3e-2)
+
+
+@pytest.mark.parametrize("shape", [(64, 40, 24), (300, 33, 9)])
+def test_autotuned_schedule_matches_oracle(shape):
+    """The autotuner only changes the schedule (which 2D levels run in the LDS
+    kernel, strip heights): the V-cycle stays the oracle's to 1e-12."""
+    from paper_1212_6680_amd.smg import SMG
+    c = (3.0, 2.0, 1.5)
+    r = synth.rhs(*shape, seed=77)
+    G = SMG(shape, c, 1, 0)
+    info = G.autotune(torch.from_numpy(r).cuda(), reps=2)
+    assert info.candidates >= 1 and info.best_ms <= info.default_ms
+    s = G.apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = O.SMG(shape, c, 1, 0).apply(r)
+    assert np.linalg.norm(s - ref) <= 1e-12 * np.linalg.norm(ref)
