@@ -51,10 +51,10 @@ KERNEL_NAMES = {
 }
 
 
-def read_traffic(family):
+def read_traffic(family, schedule=None):
     """HBM bytes per launch of `family` from the committed counter summary, or
-    None when it is missing, covers another kernel, or was taken on a
-    different kernel source."""
+    None when it is missing, covers another kernel, was taken on a different
+    kernel source, or on another V-cycle schedule than `schedule`."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -64,6 +64,9 @@ def read_traffic(family):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("family") != family:
         return None
+    if schedule is not None and (kv.get("schedule_l0") != str(schedule[0]) or
+                                 kv.get("schedule_coarse_lds") != str(schedule[1])):
+        return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -72,9 +75,44 @@ def read_traffic(family):
 
 def other_configs(torch, dev, learned=True):
     """The other workloads of the hot path, each timed once after a warm-up:
-    LOBPCG (m = 16 and m = 64 smallest eigenpairs of the 128^3 Laplacian,
-    SMG(1,0) applied to the active block in one batched V-cycle) and FPCG at
-    384^3 with the SMG preconditioner in FP64, FP32 and BF16 storage."""
+    LOBPCG at 128^3, FPCG at 384^3 with the SMG preconditioner in FP64, FP32
+    and BF16 storage, the 48 uneven boxes, and the learned post-smoother."""
+    import synth
+    from paper_1212_6680_amd.smg import SMG
+
+    res = lobpcg_configs(torch, dev)
+    n = 384
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    b = torch.from_numpy(synth.rhs(n, n, n, 5)).to(dev)
+    x64 = None
+    for prec in ("f64", "f32", "bf16"):
+        G = SMG(shape, c, 1, 0, precision=prec)
+        x = torch.empty_like(b)
+        G.fpcg(b, x, rtol=1e-8, max_iter=3, zero_x0=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = G.fpcg(b, x, rtol=1e-8, max_iter=500, zero_x0=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if prec == "f64":
+            x64 = x.clone()
+        err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+        res[f"fpcg_384_smg_{prec}"] = {"s": dt, "iters": info.iters, "status": info.status,
+                                       "true_rel_res": info.true_rel_res, "rel_err_vs_f64_solution": err}
+        del G
+    del b, x, x64
+    torch.cuda.empty_cache()
+    res["batch_48_uneven"] = batch_config(torch, dev)
+    if learned:
+        res["learned_256"] = learned_config(torch, dev)
+    return res
+
+
+def lobpcg_configs(torch, dev):
+    """LOBPCG for the m = 16 and m = 64 smallest eigenpairs of the 128^3
+    Laplacian (SMG(1,0) on the whole active block in one batched V-cycle),
+    checked against the closed-form spectrum, with the Gram product's rate on
+    the FP64 matrix cores."""
     import synth
     from paper_1212_6680_amd.smg import SMG
 
@@ -101,32 +139,14 @@ def other_configs(torch, dev, learned=True):
             "s": dt, "iters": info.iters, "nconv": info.nconv, "guard": guard, "status": info.status,
             "max_rel_eig_err_vs_closed_form": float(np.max(np.abs(lam[:m] - ex) / ex)),
             "max_resnorm": float(info.resnorms[:m].max())}
+        # the Gram product of the full basis [X, W, P] (k = 3(m + guard)) on the FP64 matrix cores
+        k = 3 * (m + guard)
+        gms = G.profile_gram(m + guard, k, reps=5)
+        tf = 2.0 * n ** 3 * k * k / (gms * 1e-3) / 1e12
+        res[f"lobpcg_128_m{m}"]["gram"] = {"k": k, "ms": gms, "tflops": tf, "peak_tflops": 78.6,
+                                           "mfma_frac": tf / 78.6}
         del G, X
         torch.cuda.empty_cache()
-    n = 384
-    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
-    b = torch.from_numpy(synth.rhs(n, n, n, 5)).to(dev)
-    x64 = None
-    for prec in ("f64", "f32", "bf16"):
-        G = SMG(shape, c, 1, 0, precision=prec)
-        x = torch.empty_like(b)
-        G.fpcg(b, x, rtol=1e-8, max_iter=3, zero_x0=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, info = G.fpcg(b, x, rtol=1e-8, max_iter=500, zero_x0=True)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if prec == "f64":
-            x64 = x.clone()
-        err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
-        res[f"fpcg_384_smg_{prec}"] = {"s": dt, "iters": info.iters, "status": info.status,
-                                       "true_rel_res": info.true_rel_res, "rel_err_vs_f64_solution": err}
-        del G
-    del b, x, x64
-    torch.cuda.empty_cache()
-    res["batch_48_uneven"] = batch_config(torch, dev)
-    if learned:
-        res["learned_256"] = learned_config(torch, dev)
     return res
 
 
@@ -167,7 +187,7 @@ def batch_config(torch, dev):
             "all_converged": all(i.status == 0 for i in infos), "bitwise_equal_to_single_solves": bool(same)}
 
 
-def learned_config(torch, dev):
+def learned_config(torch, dev, npairs=2000, steps=2000):
     """Learned post-smoother: trained at 128^3 on 2000 (r', e') pairs from
     SMG(1,0) (b seeds 10000 + i, energy-norm loss, one Adam step per pair),
     then used inside FPCG at 256^3 (b seed 6) beside SMG (1,0) and (1,1)."""
@@ -177,14 +197,13 @@ def learned_config(torch, dev):
     shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
     Gp, Ge = SMG(shape, c, 1, 0), SMG(shape, c, 1, 1)
     net = Net(n ** 3, "bf16", train=True)
-    npairs, steps = 2000, 2000
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     inputs, targets, _ = net.make_pairs(Gp, Ge, npairs, 10000, exact_rtol=1e-10)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
     net.set_params(synth.he_init(0))
-    order = np.random.default_rng(0).permutation(npairs)[:steps]
+    order = np.resize(np.random.default_rng(0).permutation(npairs), steps)
     lr = 2e-3 * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * np.arange(steps) / steps)))
     t0 = time.perf_counter()
     hist = net.train(shape, inputs, targets, order, lr, loss="energy")
@@ -229,6 +248,10 @@ def main():
                     help="skip the LOBPCG and mixed-precision workloads reported beside the headline")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for counter collection: a 512 MiB device copy, then one V-cycle")
+    ap.add_argument("--only", choices=["batch", "learned", "lobpcg"],
+                    help="run one of the other workloads alone and print its result (for profiling)")
+    ap.add_argument("--learned-pairs", type=int, default=2000)
+    ap.add_argument("--learned-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -242,6 +265,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        if args.only == "batch":
+            out = batch_config(torch, dev)
+        elif args.only == "learned":
+            out = learned_config(torch, dev, args.learned_pairs, args.learned_steps)
+        else:
+            out = lobpcg_configs(torch, dev)
+        print(json.dumps({"only": args.only, **out}))
+        return
     n = args.n
     shape = (n, n, n)
     c = ((n + 1.0) ** 2,) * 3
@@ -250,10 +282,9 @@ def main():
     b = torch.from_numpy(b_host).to(dev)
 
     if args.pmc_probe:
-        # the tuned schedule of the headline, then three 512 MiB copies (the
-        # calibration), then one V-cycle: the dispatches after the last copy
+        # the default schedule (the counters name it), three 512 MiB copies
+        # (the calibration), then one V-cycle: the dispatches after the last copy
         G = SMG(shape, c, 1, 0)
-        G.autotune(b, reps=1)
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -261,7 +292,9 @@ def main():
         torch.cuda.synchronize()
         G.apply(b)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": True, "copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8}))
+        l0, clds = G.schedule()
+        print(json.dumps({"pmc_probe": True, "copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8,
+                          "schedule_l0": l0, "schedule_coarse_lds": clds}))
         return
 
     torch.cuda.synchronize()
@@ -315,7 +348,7 @@ def main():
     dom = max(fams, key=lambda f: fams[f]["ms"])
     d = fams[dom]
     achieved = d["gbs"]
-    traffic = read_traffic(dom)
+    traffic = read_traffic(dom, (tune.l0, tune.coarse_lds))
 
     out = {
         "metric": METRIC,

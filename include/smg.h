@@ -211,6 +211,16 @@ typedef struct smg_tune_info {
     double best_ms;         /* V-cycle time of the chosen schedule */
 } smg_tune_info;
 int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *stream, smg_tune_info *info);
+/* The handle's current schedule (l0, s_down, s_up, coarse_lds; the timing
+ * fields are zero).  Host-only. */
+int smg_get_schedule(const smg_handle *h, smg_tune_info *info);
+
+/* Measurement: the Gram product G = S^T S of LOBPCG's FP64 MFMA kernels for an
+ * N x k block (k <= 3m) held in a workspace sized by lobpcg_workspace_bytes(h,
+ * m) (the block is filled with a constant first).  Returns the mean time of
+ * one product (partial products and the fixed-order reduction) over reps. */
+int lobpcg_profile_gram(smg_handle *h, int32_t m, int32_t k, void *ws, size_t ws_bytes, int32_t reps, void *stream,
+                        double *ms);
 
 /* Releases the host-side handle (the caller's workspace is not freed). */
 int smg_destroy(smg_handle *h);

@@ -370,6 +370,43 @@ int lobpcg_workspace_bytes(smg_handle *h, int32_t m, size_t *bytes)
     return SMG_OK;
 }
 
+int lobpcg_profile_gram(smg_handle *h, int32_t m, int32_t k, void *ws, size_t ws_bytes, int32_t reps, void *stream,
+                        double *ms)
+{
+    if (!h || !ws || !ms || m < 1 || k < 1 || k > 3 * m || reps < 1) return SMG_EINVAL;
+    size_t N = 0;
+    if (smg_handle_size(h, &N) != SMG_OK) return SMG_EINVAL;
+    Lob lb{h, reinterpret_cast<hipStream_t>(stream), N, m, static_cast<char *>(ws), lob_layout(N, m)};
+    if (ws_bytes < lb.L.total) return SMG_EWORKSPACE;
+    hipStream_t st = lb.st;
+    double *S = lb.at<double>(lb.L.S);
+    launch_fill(S, 1.0 / 1024.0, N * static_cast<size_t>(k), st);
+    const long long slice = (static_cast<long long>(N) + lb.L.nslices_gram - 1) / lb.L.nslices_gram;
+    const long long sl = (slice + kK - 1) / kK * kK;
+    const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
+    auto one = [&]() {
+        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(k, kT), nblk(k, kT), nz), dim3(256), 0, st, S,
+                           static_cast<long long>(N), k, S, static_cast<long long>(N), k, static_cast<long long>(N),
+                           sl, lb.at<double>(lb.L.part));
+        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(k) * k, 256)), dim3(256), 0, st,
+                           lb.at<double>(lb.L.part), nz, k * k, lb.at<double>(lb.L.G));
+    };
+    one();   // warm-up
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SMG_EHIP;
+    int rc = SMG_OK;
+    float t = 0.f;
+    if (hipEventRecord(e0, st) != hipSuccess) rc = SMG_EHIP;
+    for (int i = 0; rc == SMG_OK && i < reps; ++i) one();
+    if (rc == SMG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&t, e0, e1) != hipSuccess || !lb.ok()))
+        rc = SMG_EHIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = static_cast<double>(t) / reps;
+    return rc;
+}
+
 int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *resnorms, void *ws, size_t ws_bytes,
                  const lobpcg_opts *o, lobpcg_info *info, void *stream)
 {

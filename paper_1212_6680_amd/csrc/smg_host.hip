@@ -988,6 +988,17 @@ const char *smg_strerror(int status)
     }
 }
 
+int smg_get_schedule(const smg_handle *h, smg_tune_info *info)
+{
+    if (!h || !info) return SMG_EINVAL;
+    *info = smg_tune_info{};
+    info->l0 = h->l0;
+    info->coarse_lds = static_cast<int64_t>(h->coarse_lds);
+    info->s_down = h->S_down;
+    info->s_up = h->S_up;
+    return SMG_OK;
+}
+
 int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *stream, smg_tune_info *info)
 {
     if (!h || !r || !s || reps < 1) return SMG_EINVAL;
@@ -1047,7 +1058,8 @@ int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *
                     continue;
                 }
                 ++inf.candidates;
-                if (ms < best) {
+                // a schedule replaces the current choice only if clearly faster (timing noise)
+                if (ms < 0.98 * best) {
                     best = ms;
                     best_c = c;
                     best_s = sbud;

@@ -97,9 +97,11 @@ def lib():
         L.smg_profile_kernel.argtypes = [p, i32, p, p, i32, p, C.POINTER(i32), C.POINTER(d), C.POINTER(d)]
         if hasattr(L, "lobpcg_solve"):
             L.lobpcg_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
+            L.lobpcg_profile_gram.argtypes = [p, i32, i32, p, C.c_size_t, i32, p, C.POINTER(d)]
             L.lobpcg_solve.argtypes = [p, i32, p, p, p, p, C.c_size_t,
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
         L.smg_autotune.argtypes = [p, p, p, i32, p, C.POINTER(smg_tune_info)]
+        L.smg_get_schedule.argtypes = [p, C.POINTER(smg_tune_info)]
         L.smg_batch_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
         L.smg_batch_create.argtypes = [p, i32, p, p, p, C.c_size_t, i32, p, C.POINTER(p)]
         L.smg_batch_fpcg.argtypes = [p, C.POINTER(krylov_opts), p, p]
@@ -270,6 +272,22 @@ class SMG:
                "smg_autotune")
         return Info(candidates=info.candidates, l0=info.l0, s_down=info.s_down, s_up=info.s_up,
                     coarse_lds=info.coarse_lds, default_ms=info.default_ms, best_ms=info.best_ms)
+
+    def schedule(self):
+        """(l0, coarse kernel LDS bytes) of the fused 2D-cycle schedule in use."""
+        info = smg_tune_info()
+        _check(lib().smg_get_schedule(self.h, C.byref(info)), "smg_get_schedule")
+        return info.l0, info.coarse_lds
+
+    def profile_gram(self, m: int, k: int, reps: int = 5) -> float:
+        """ms of one LOBPCG Gram product S^T S for an n x k block (k <= 3m)."""
+        nbytes = C.c_size_t(0)
+        _check(lib().lobpcg_workspace_bytes(self.h, m, C.byref(nbytes)), "lobpcg_workspace_bytes")
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        ms = C.c_double(0)
+        _check(lib().lobpcg_profile_gram(self.h, m, k, C.c_void_p(ws.data_ptr()), nbytes.value, reps, _stream(),
+                                         C.byref(ms)), "lobpcg_profile_gram")
+        return ms.value
 
     def profile_kernel(self, family: str, r: torch.Tensor, reps: int = 3):
         """(launches per V-cycle, kernel ms per V-cycle, algorithmic bytes per V-cycle) of one kernel family."""
