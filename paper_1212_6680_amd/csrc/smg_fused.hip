@@ -357,12 +357,20 @@ __device__ __forceinline__ void k2_coarse_body(const Coarse2Args<T, A> &a, const
     int total = 0;
     for (int l = a.l0; l < a.nlev; ++l) total += a.ny2[l];
     A *xs = sm, *bs = sm + static_cast<size_t>(total) * nxp;
-    // line offset of level l inside xs / bs
+    // line rows of the levels held here, copied next to the lines: the
+    // relaxations then wait on one global load (the Thomas table), not two
+    LineCoef<A> *lcs = reinterpret_cast<LineCoef<A> *>(bs + static_cast<size_t>(total) * nxp);
+    // line offset of level l inside xs / bs / lcs
     auto off = [&](int l) {
         int o = 0;
         for (int m = a.l0; m < l; ++m) o += a.ny2[m];
         return o;
     };
+    for (int i = threadIdx.x; i < total; i += blockDim.x) {
+        int l = a.l0, o = 0;
+        while (i >= o + a.ny2[l]) o += a.ny2[l++];
+        lcs[i] = lcp[a.lev_off[l] + (i - o)];
+    }
     {
         const T *bpl = a.b + r * a.brs + p * a.bps;
         for (int j = w; j < a.ny2[a.l0]; j += kW) {
@@ -374,7 +382,7 @@ __device__ __forceinline__ void k2_coarse_body(const Coarse2Args<T, A> &a, const
     __syncthreads();
     for (int l = a.l0; l < a.nlev - 1; ++l) {
         const int ny = a.ny2[l], nyc = a.ny2[l + 1];
-        const LineCoef<A> *lc = lcp + a.lev_off[l];
+        const LineCoef<A> *lc = lcs + off(l);
         const int ol = off(l), oc = ol + ny;
         A *x = xs + ol * nxp, *b = bs + ol * nxp, *bc = bs + oc * nxp;
         for (int s = 0; s < a.ipre; ++s) {
@@ -423,14 +431,14 @@ __device__ __forceinline__ void k2_coarse_body(const Coarse2Args<T, A> &a, const
         if (w == 0) {
             A f[E];
             sload<A, E>(f, bs + ol * nxp, lane);
-            thomas<A, E>(f, a.fac + static_cast<size_t>((lcp + a.lev_off[l])[0].fac) * nxp, lane);
+            thomas<A, E>(f, a.fac + static_cast<size_t>(lcs[ol].fac) * nxp, lane);
             sstore<A, E>(xs + ol * nxp, f, lane);
         }
         __syncthreads();
     }
     for (int l = a.nlev - 2; l >= a.l0; --l) {
         const int ny = a.ny2[l], nyc = a.ny2[l + 1];
-        const LineCoef<A> *lc = lcp + a.lev_off[l];
+        const LineCoef<A> *lc = lcs + off(l);
         const int ol = off(l), oc = ol + ny;
         A *x = xs + ol * nxp, *b = bs + ol * nxp;
         const A *xc = xs + oc * nxp;

@@ -152,13 +152,15 @@ constexpr size_t kStripLds = 48 * 1024;
 void apply_fused_schedule(smg_handle *h, size_t coarse_budget, size_t strip_budget)
 {
     const size_t line = static_cast<size_t>(h->nxp) * arith_size(h->o.precision);
+    const size_t row = h->o.precision == SMG_PREC_F64 ? sizeof(LineCoef<double>) : sizeof(LineCoef<float>);
     const int nl = static_cast<int>(h->ny2.size());
     h->l0 = nl - 1;
     h->coarse_lds = 0;
     for (int l = nl - 1; l >= 0; --l) {
         size_t lines = 0;
         for (int m = l; m < nl; ++m) lines += h->ny2[m];
-        const size_t bytes = 2 * lines * line;
+        // x and b of every line, then the line rows
+        const size_t bytes = 2 * lines * line + lines * row;
         if (bytes > coarse_budget) break;
         h->l0 = l;
         h->coarse_lds = bytes;
