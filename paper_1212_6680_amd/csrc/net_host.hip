@@ -366,8 +366,8 @@ struct Impl {
                                 static_cast<A *>(targets) + i * N, N, st);
     }
 
-    static int train(net_handle *n, int nx, int ny, int nz, const void *inputs, const void *targets, int npairs,
-                     int steps, const int32_t *order, const double *lr, int kind, double *hist, hipStream_t st)
+    static int train(net_handle *n, int nx, int ny, int nz, const void *inputs, const void *targets, int steps,
+                     const int32_t *order, const double *lr, int kind, double *hist, hipStream_t st)
     {
         const long long N = static_cast<long long>(nx) * ny * nz;
         double *ring = n->at<double>(n->L.loss);
@@ -575,8 +575,8 @@ int net_train(net_handle *n, int32_t nx, int32_t ny, int32_t nz, const void *inp
         if (order[k] < 0 || order[k] >= npairs || !(lr[k] >= 0.0)) return SMG_EINVAL;
     hipStream_t st = as_st(stream);
     return dispatch(n, [&](auto impl) {
-        return decltype(impl)::train(n, nx, ny, nz, inputs, targets, npairs, steps, order, lr, loss_kind,
-                                     loss_history, st);
+        return decltype(impl)::train(n, nx, ny, nz, inputs, targets, steps, order, lr, loss_kind, loss_history,
+                                     st);
     });
 }
 

@@ -408,7 +408,6 @@ __global__ void k_pack_pairs(const bf16 *w, unsigned int *out)
 // shape without a bf16 kernel).  One output voxel per thread.
 // ---------------------------------------------------------------------------
 template <typename A> struct VecTile;
-template <> struct VecTile<float> { static constexpr int TX = 32, TY = 4, TZ = 2; };
 template <> struct VecTile<double> { static constexpr int TX = 16, TY = 4, TZ = 2; };
 
 // INM: 0 = storage input with CIN channels; 1 = FP64 single channel times

@@ -635,7 +635,6 @@ __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const B
     __shared__ A vs[2][kChainWin * kChainCols];
     const long long pl = static_cast<long long>(a.nx) * a.ny;
     const int ncol = static_cast<int>((pl + kChainCols - 1) / kChainCols);
-    const int nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
     const int ct = blk.x % ncol;
     const int rt = blk.x / ncol;
     const int r = blk.y;
@@ -806,8 +805,6 @@ __global__ __launch_bounds__(kThreads) void k2_up_grp_e4(const GroupEntry *tab, 
     default: k2_up_body<T, A, 4>(*a, blk); break;
     }
 }
-
-inline unsigned nb(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 
 // grouped twin for width E: the any-E kernel up to E = 4, else the E-specific one
 template <int E, typename K4, typename KE>

@@ -29,16 +29,6 @@ constexpr int kMaxNx = 512;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int levels_of(int n)
-{
-    int L = 1;
-    while (n > 1) {
-        n /= 2;
-        ++L;
-    }
-    return L;
-}
-
 // Galerkin coarsening of a block-tridiagonal operator with diagonal blocks
 // D_f = da[f]*S + db[f]*I and couplings O_f = oa[f]*S + ob[f]*I (f <-> f+1)
 // under linear interpolation from the odd points:
