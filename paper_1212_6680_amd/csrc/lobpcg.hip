@@ -31,54 +31,70 @@ constexpr int kLdsPad = 4;  // LDS row padding (doubles)
 
 // Partial Gram products over a slice of rows:
 //   part[z][i][j] = sum_{n in slice z} U[n + i*ldu] * V[n + j*ldv],  i < p, j < q.
-// Block: 4 waves; tile 64(i) x 64(j); wave w owns rows i in [16w, 16w+16).
+// Block: 4 waves; tile 128(i) x 128(j); wave w owns rows i in [32w, 32w+32)
+// (two 16-row MFMA blocks) and all 128 columns (eight 16-column blocks), so
+// each step of 4 in n costs 10 LDS reads for 16 MFMAs.
 // MFMA 16x16x4 f64 operand layout: A[i][k] from lane i + 16k, B[k][j] from
 // lane j + 16k, D[i][j] in lane j + 16*(i%4), element i/4.
+constexpr int kGT = 128;    // Gram output tile edge
+
 __global__ __launch_bounds__(256) void k_gram_partial(const double *U, long long ldu, int p, const double *V,
                                                       long long ldv, int q, long long n, long long slice,
                                                       double *part)
 {
-    __shared__ double Us[kK][kT + kLdsPad];
-    __shared__ double Vs[kK][kT + kLdsPad];
+    __shared__ double Us[kK][kGT + kLdsPad];
+    __shared__ double Vs[kK][kGT + kLdsPad];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int i0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+    const int i0 = blockIdx.x * kGT, j0 = blockIdx.y * kGT;
     const long long n_beg = static_cast<long long>(blockIdx.z) * slice;
     const long long n_end = n_beg + slice < n ? n_beg + slice : n;
-    v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    const int lc = tid >> 2;          // staging: column within the tile
-    const int lr = (tid & 3) * 4;     // staging: first of 4 rows
-    for (long long n0 = n_beg; n0 < n_end; n0 += kK) {
-        const int ci = i0 + lc, cj = j0 + lc;
+    v4d acc[2][8];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const long long nn = n0 + lr + r;
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+    // 16 x 16 blocks inside p x q only (the tile is padded to 128)
+    const bool in0 = i0 + 32 * w < p, in1 = i0 + 32 * w + 16 < p;
+    const int jn = (q - j0 + 15) / 16;
+    for (long long n0 = n_beg; n0 < n_end; n0 += kK) {
+        // stage 16 rows of 128 columns of U and V: thread e reads row e%16 of column e/16
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int e = tid + 256 * r;
+            const int ii = e & 15, col = e >> 4;
+            const long long nn = n0 + ii;
             const bool in = nn < n_end;
-            Us[lr + r][lc] = (in && ci < p) ? U[nn + ci * ldu] : 0.0;
-            Vs[lr + r][lc] = (in && cj < q) ? V[nn + cj * ldv] : 0.0;
+            Us[ii][col] = (in && i0 + col < p) ? U[nn + (i0 + col) * ldu] : 0.0;
+            Vs[ii][col] = (in && j0 + col < q) ? V[nn + (j0 + col) * ldv] : 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kK / 4; ++kk) {
             const int kr = 4 * kk + (lane >> 4);
-            const double a = Us[kr][16 * w + (lane & 15)];
+            const double a0 = Us[kr][32 * w + (lane & 15)];
+            const double a1 = Us[kr][32 * w + 16 + (lane & 15)];
 #pragma unroll
-            for (int jt = 0; jt < 4; ++jt) {
+            for (int jt = 0; jt < 8; ++jt) {
+                if (jt >= jn) break;            // 16-column blocks past q
                 const double b = Vs[kr][16 * jt + (lane & 15)];
-                acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
+                if (in0) acc[0][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][jt], 0, 0, 0);
+                if (in1) acc[1][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][jt], 0, 0, 0);
             }
         }
         __syncthreads();
     }
     double *out = part + static_cast<long long>(blockIdx.z) * p * q;
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) {
-        const int j = j0 + 16 * jt + (lane & 15);
+    for (int it = 0; it < 2; ++it)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = i0 + 16 * w + 4 * r + (lane >> 4);
-            if (i < p && j < q) out[static_cast<long long>(i) * q + j] = acc[jt][r];
+        for (int jt = 0; jt < 8; ++jt) {
+            const int j = j0 + 16 * jt + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 32 * w + 16 * it + 4 * r + (lane >> 4);
+                if (i < p && j < q) out[static_cast<long long>(i) * q + j] = acc[it][jt][r];
+            }
         }
-    }
 }
 
 // G[i][j] = sum_z part[z][i][j] in a fixed order (deterministic).
@@ -93,7 +109,8 @@ __global__ void k_gram_reduce(const double *part, int nz, int pq, double *G)
 
 // Y[n + j*ldy] = sum_{i<k} U[n + i*ldu] * C[i*mo + j]  for j < mo (C row-major k x mo).
 // Computed as the transposed tile Y^T = C^T U^T so that each MFMA output row
-// is a contiguous run of 16 n: wave w owns n in [16w, 16w+16) of the tile.
+// is a contiguous run of 16 n: wave w owns n in [16w, 16w+16) of the tile;
+// 16-column blocks past mo are skipped.
 __global__ __launch_bounds__(256) void k_block_update(const double *U, long long ldu, int k, const double *C, int mo,
                                                       double *Y, long long ldy, long long n)
 {
@@ -102,6 +119,7 @@ __global__ __launch_bounds__(256) void k_block_update(const double *U, long long
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const long long n0 = static_cast<long long>(blockIdx.x) * kT;
     const int j0 = blockIdx.y * kT;
+    const int jn = (mo - j0 + 15) / 16;
     v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
     for (int i0 = 0; i0 < k; i0 += kK) {
         // stage U[n0 .. n0+63][i0 .. i0+15] as Ut[i][n] and C[i0..][j0..j0+63] as Ct[i][j]
@@ -121,6 +139,7 @@ __global__ __launch_bounds__(256) void k_block_update(const double *U, long long
             const double b = Ut[kr][16 * w + (lane & 15)];
 #pragma unroll
             for (int jt = 0; jt < 4; ++jt) {
+                if (jt >= jn) break;
                 const double a = Ct[kr][16 * jt + (lane & 15)];
                 acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
             }
@@ -257,7 +276,7 @@ struct Lob {
         const long long slice = (static_cast<long long>(N) + L.nslices_gram - 1) / L.nslices_gram;
         const long long sl = (slice + kK - 1) / kK * kK;
         const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
-        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(p, kT), nblk(q, kT), nz), dim3(256), 0, st, U,
+        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(p, kGT), nblk(q, kGT), nz), dim3(256), 0, st, U,
                            static_cast<long long>(N), p, V, static_cast<long long>(N), q,
                            static_cast<long long>(N), sl, at<double>(L.part));
         hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 256)), dim3(256), 0, st,
@@ -385,7 +404,7 @@ int lobpcg_profile_gram(smg_handle *h, int32_t m, int32_t k, void *ws, size_t ws
     const long long sl = (slice + kK - 1) / kK * kK;
     const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
     auto one = [&]() {
-        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(k, kT), nblk(k, kT), nz), dim3(256), 0, st, S,
+        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(k, kGT), nblk(k, kGT), nz), dim3(256), 0, st, S,
                            static_cast<long long>(N), k, S, static_cast<long long>(N), k, static_cast<long long>(N),
                            sl, lb.at<double>(lb.L.part));
         hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(k) * k, 256)), dim3(256), 0, st,
