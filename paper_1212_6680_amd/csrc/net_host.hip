@@ -36,7 +36,7 @@ LayerTable layer_table()
 hipStream_t as_st(void *s) { return static_cast<hipStream_t>(s); }
 
 struct NetLayout {
-    size_t p, wst, wtr, frag, pairs, ns, part, rp, sl, a1, a2;   // inference
+    size_t p, wst, wtr, frag, ns, part, rp, sl, a1, a2;          // inference
     size_t a3, g0, g1, y, g4, grad, m, v, wpart, loss, b, xp, xs;  // training
     size_t total;
 };
@@ -57,7 +57,6 @@ NetLayout make_net_layout(long long nvox, int prec, int train)
     L.wst = take(NET_NPARAMS * es);
     L.wtr = take(NET_NPARAMS * es);
     L.frag = take(prec == NET_PREC_BF16 ? 4 * 14 * 64 * 8 * 2 : 0);
-    L.pairs = take(prec == NET_PREC_BF16 ? 2 * 16 * 14 * 4 : 0);
     L.ns = take(sizeof(NetScalars));
     L.part = take(2 * kRedBlocks * sizeof(double));
     L.rp = take(n * 8);
@@ -120,12 +119,6 @@ struct Impl {
         return c;
     }
 
-    // tap-pair weights of the bf16 1 -> 16 kernels: 0 = layer 0 forward, 1 = layer 3 input gradient
-    static const unsigned int *pairs(net_handle *n, int which)
-    {
-        return n->at<unsigned int>(n->L.pairs) + which * 16 * 14;
-    }
-
     static void pack(net_handle *n, hipStream_t st)
     {
         launch_pack<T, A>(p(n), wst(n), wtr(n), n->lt, st);
@@ -134,9 +127,6 @@ struct Impl {
                 for (int bwd = 0; bwd < 2; ++bwd)
                     launch_pack_frag(reinterpret_cast<const float *>(p(n)), n->lt.off[l], bwd,
                                      n->at<uint16_t>(n->L.frag) + ((l - 1) * 2 + bwd) * (14 * 64 * 8), st);
-            unsigned int *pr = n->at<unsigned int>(n->L.pairs);
-            launch_pack_pairs(wst(n) + n->lt.off[0], pr, st);
-            launch_pack_pairs(wtr(n) + n->lt.off[3], pr + 16 * 14, st);
         }
     }
 
@@ -150,7 +140,8 @@ struct Impl {
             a.in = in;
             a.in64 = in64;
             a.ns = ns;
-            a.wpair = pairs(n, which);
+            // [27][16] weights: layer 0 forward, or layer 3's flipped transpose (input gradient)
+            a.w = which == 0 ? wst(n) + n->lt.off[0] : wtr(n) + n->lt.off[3];
             a.bias = which == 0 ? bias(n, 0) : nullptr;
             a.mask = mask;
             a.out = out;

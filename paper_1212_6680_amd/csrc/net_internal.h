@@ -53,7 +53,7 @@ struct In16Args {            // bf16 1 -> 16 layer
     const bf16 *in;          // INM 0
     const double *in64;      // INM 1
     const NetScalars *ns;
-    const unsigned int *wpair;  // 16 x 14 packed tap pairs
+    const bf16 *w;           // [27][16] weights (tap, output channel)
     const float *bias;       // EPI 0
     const bf16 *mask;        // EPI 1
     bf16 *out;
@@ -82,7 +82,6 @@ struct WgradArgs {
 void launch_conv16_mfma(const Conv16Args &a, int epi, hipStream_t st);
 void launch_in16_bf16(const In16Args &a, int inm, int epi, hipStream_t st);
 void launch_out16_bf16(const Out16Args &a, int epi, hipStream_t st);
-void launch_pack_pairs(const bf16 *w, unsigned int *out, hipStream_t st);
 template <typename T, typename A, int CIN, int COUT, int INM, int EPI>
 void launch_conv_vec(const ConvVecArgs<T, A> &a, hipStream_t st);
 int wgrad_blocks(int nx, int ny, int nz);

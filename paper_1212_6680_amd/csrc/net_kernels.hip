@@ -177,21 +177,42 @@ __device__ inline float dot2(unsigned int a, unsigned int b, float c)
     return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
 }
 
-// 1 -> 16 (layer 0 forward; input gradient of layer 3).  INM 0: bf16 input;
-// INM 1: FP64 input times ns->in_scale, rounded to bf16.  EPI 0: bias + ReLU;
-// EPI 1: mask.  wpair[co*14 + m] packs the weights of taps 2m and 2m+1; the
-// block keeps them in LDS and each thread computes SRY voxels along y.
+// 1 -> 16 (layer 0 forward; input gradient of layer 3) on the matrix cores:
+// out[co][voxel] = sum_t W[t][co] in[voxel + off_t] is one
+// v_mfma_f32_16x16x32_bf16 per 16 voxels (A = the 16 x 32 weight matrix, taps
+// 27..31 zero; B = each voxel's 27 neighbours gathered from the staged
+// planes).  INM 0: bf16 input; INM 1: FP64 input times ns->in_scale, rounded
+// to bf16.  EPI 0: bias + ReLU; EPI 1: mask.  w: the [27][16] bf16 weights.
 template <int INM, int EPI>
 __global__ __launch_bounds__(256) void k_in16_bf16(In16Args a)
 {
     constexpr int PER = (SPLANE + 255) / 256;
     __shared__ uint16_t lds[3 * SPLANE];
-    __shared__ u32x4 wl[16 * 14 / 4];
-    const int tx = threadIdx.x % STX, ty = threadIdx.x / STX;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int x0 = blockIdx.x * STX, y0 = blockIdx.y * STY;
     const int z0 = blockIdx.z * a.zc, z1 = min(z0 + a.zc, a.nz);
     const double in_scale = INM == 1 ? a.ns->in_scale : 1.0;
-    if (threadIdx.x < 16 * 14 / 4) wl[threadIdx.x] = reinterpret_cast<const u32x4 *>(a.wpair)[threadIdx.x];
+    const int j = lane & 15, q = lane >> 4;
+    // A fragment: lane (co = j, taps 8q .. 8q+7)
+    bf16x8 wf;
+    int toff[8], slot_of[8][3];
+    unsigned int keep[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int t = 8 * q + e;
+        wf[e] = t < 27 ? __builtin_bit_cast(__bf16, a.w[t * 16 + j].bits) : static_cast<__bf16>(0.0f);
+        const int tc = t < 27 ? t : 26;
+        toff[e] = ((tc / 3) % 3) * SHX + tc % 3;
+        keep[e] = t < 27 ? 0xffffu : 0u;
+        // LDS offset of the plane z + dz - 1 for each ring position of plane z - 1
+#pragma unroll
+        for (int b3 = 0; b3 < 3; ++b3) slot_of[e][b3] = ((b3 + tc / 9) % 3) * SPLANE;
+    }
+    float bias[4] = {0.f, 0.f, 0.f, 0.f};
+    if (EPI == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[e] = a.bias[4 * q + e];
+    }
     auto fetch = [&](int zi, uint16_t *reg) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
@@ -224,76 +245,47 @@ __global__ __launch_bounds__(256) void k_in16_bf16(In16Args a)
     fetch(z0, reg);
     stage(1, reg);
     fetch(z0 + 1, reg);
-    const int gx = x0 + tx;
     for (int z = z0; z < z1; ++z) {
         const int base = z - z0;
         stage((base + 2) % 3, reg);
         __syncthreads();
         if (z + 2 <= z1) fetch(z + 2, reg);
-        unsigned int xp[SRY][14];
+        // wave w: rows 2w, 2w+1 of the tile, four 16-voxel segments each
 #pragma unroll
-        for (int r = 0; r < SRY; ++r)
+        for (int sg = 0; sg < 8; ++sg) {
+            const int row = 2 * w + (sg >> 2), xs = 16 * (sg & 3) + j;
+            // every gather reads a valid location (taps past 26 alias tap 26);
+            // the missing taps are then zeroed without branching
+            unsigned int pk[4];
 #pragma unroll
-            for (int m = 0; m < 14; ++m) {
-                unsigned int lo = 0, hi = 0;
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int t = 2 * m + u;
-                    if (t < 27) {
-                        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-                        const unsigned int v =
-                            lds[((base + dz) % 3) * SPLANE + (SRY * ty + r + dy) * SHX + tx + dx];
-                        if (u == 0) lo = v; else hi = v;
-                    }
-                }
-                xp[r][m] = lo | (hi << 16);
+            for (int h = 0; h < 4; ++h) {
+                const unsigned int lo = lds[slot_of[2 * h][base % 3] + row * SHX + xs + toff[2 * h]];
+                const unsigned int hi = lds[slot_of[2 * h + 1][base % 3] + row * SHX + xs + toff[2 * h + 1]];
+                pk[h] = (lo & keep[2 * h]) | ((hi & keep[2 * h + 1]) << 16);
             }
-        // four output channels at a time (a runtime loop keeps the weights in LDS)
-#pragma unroll 1
-        for (int c4 = 0; c4 < 4; ++c4) {
-            float o[SRY][4];
+            u32x4 pv = {pk[0], pk[1], pk[2], pk[3]};
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf, __builtin_bit_cast(bf16x8, pv), acc, 0, 0, 0);
+            const int gy = y0 + row, gx = x0 + xs;
+            if (gx < a.nx && gy < a.ny) {
+                const long long v = (static_cast<long long>(z) * a.ny + gy) * a.nx + gx;
+                float o4[4];
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-                float acc[SRY];
+                for (int e = 0; e < 4; ++e) o4[e] = acc[e];
+                if (EPI == 0) {
 #pragma unroll
-                for (int r = 0; r < SRY; ++r) acc[r] = 0.f;
-                const int cq = 4 * c4 + cc;
-#pragma unroll
-                for (int m4 = 0; m4 < 4; ++m4) {
-                    const int cnt = 14 - 4 * m4 < 4 ? 14 - 4 * m4 : 4;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if (e < cnt) {
-                            const int wi = cq * 14 + 4 * m4 + e;
-                            const unsigned int wv = wl[wi >> 2][wi & 3];
-#pragma unroll
-                            for (int r = 0; r < SRY; ++r) acc[r] = dot2(xp[r][4 * m4 + e], wv, acc[r]);
-                        }
-                    }
+                    for (int e = 0; e < 4; ++e) o4[e] = fmaxf(o4[e] + bias[e], 0.f);
+                } else {
+                    const u32x2 mk = reinterpret_cast<const u32x2 *>(a.mask)[v * 4 + q];
+                    if (!(lo_bf(mk.x) > 0.f)) o4[0] = 0.f;
+                    if (!(hi_bf(mk.x) > 0.f)) o4[1] = 0.f;
+                    if (!(lo_bf(mk.y) > 0.f)) o4[2] = 0.f;
+                    if (!(hi_bf(mk.y) > 0.f)) o4[3] = 0.f;
                 }
-#pragma unroll
-                for (int r = 0; r < SRY; ++r) o[r][cc] = acc[r];
-            }
-#pragma unroll
-            for (int r = 0; r < SRY; ++r) {
-                const int gy = y0 + SRY * ty + r;
-                if (gx < a.nx && gy < a.ny) {
-                    const long long v = (static_cast<long long>(z) * a.ny + gy) * a.nx + gx;
-                    if (EPI == 0) {
-#pragma unroll
-                        for (int cc = 0; cc < 4; ++cc) o[r][cc] = fmaxf(o[r][cc] + a.bias[4 * c4 + cc], 0.f);
-                    } else {
-                        const u32x2 mv = reinterpret_cast<const u32x2 *>(a.mask)[v * 4 + c4];
-                        if (!(lo_bf(mv.x) > 0.f)) o[r][0] = 0.f;
-                        if (!(hi_bf(mv.x) > 0.f)) o[r][1] = 0.f;
-                        if (!(lo_bf(mv.y) > 0.f)) o[r][2] = 0.f;
-                        if (!(hi_bf(mv.y) > 0.f)) o[r][3] = 0.f;
-                    }
-                    u32x2 st;
-                    st.x = pack2(o[r][0], o[r][1]);
-                    st.y = pack2(o[r][2], o[r][3]);
-                    reinterpret_cast<u32x2 *>(a.out)[v * 4 + c4] = st;
-                }
+                u32x2 st;
+                st.x = pack2(o4[0], o4[1]);
+                st.y = pack2(o4[2], o4[3]);
+                reinterpret_cast<u32x2 *>(a.out)[v * 4 + q] = st;
             }
         }
         __syncthreads();
@@ -389,18 +381,6 @@ __global__ __launch_bounds__(256) void k_out16_bf16(Out16Args a)
         }
         __syncthreads();
     }
-}
-
-// Packs a [27][16] bf16 weight array into tap pairs: out[co*14 + m] holds
-// (w[2m][co], w[2m+1][co]) with w[27][co] = 0.
-__global__ void k_pack_pairs(const bf16 *w, unsigned int *out)
-{
-    const int i = threadIdx.x;
-    if (i >= 16 * 14) return;
-    const int co = i / 14, m = i % 14;
-    const unsigned int lo = w[(2 * m) * 16 + co].bits;
-    const unsigned int hi = 2 * m + 1 < 27 ? w[(2 * m + 1) * 16 + co].bits : 0u;
-    out[i] = lo | (hi << 16);
 }
 
 // ---------------------------------------------------------------------------
@@ -799,11 +779,6 @@ void launch_out16_bf16(const Out16Args &a0, int epi, hipStream_t st)
         hipLaunchKernelGGL(k_out16_bf16<2>, grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_out16_bf16<3>, grid, dim3(256), 0, st, a);
-}
-
-void launch_pack_pairs(const bf16 *w, unsigned int *out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_pack_pairs, dim3(1), dim3(256), 0, st, w, out);
 }
 
 template <typename T, typename A, int CIN, int COUT, int INM, int EPI>
