@@ -39,7 +39,7 @@ def kernel_source_hash() -> str:
 
 
 KERNEL_NAMES = {
-    "down2": "k2_down_reg / k2_down (fused pre-smoothing + residual + restriction of a 2D level)",
+    "down2": "k2_down_march / k2_down_reg / k2_down (fused pre-smoothing + residual + restriction of a 2D level)",
     "coarse2": "k2_coarse (LDS-resident 2D sub-cycle)",
     "chain2": "k2_chain (2D prolongation chain + 3D correction)",
     "up2": "k2_up (fused prolongation + post-smoothing)",
@@ -65,7 +65,8 @@ def read_traffic(family, schedule=None):
     if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("family") != family:
         return None
     if schedule is not None and (kv.get("schedule_l0") != str(schedule[0]) or
-                                 kv.get("schedule_coarse_lds") != str(schedule[1])):
+                                 kv.get("schedule_coarse_lds") != str(schedule[1]) or
+                                 kv.get("schedule_march_waves") != str(schedule[2])):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -125,6 +126,17 @@ def lobpcg_configs(torch, dev):
     res = {}
     n = 128
     shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    # balanced smoothing for comparison (Section 4: fewer iterations, dearer ones)
+    G = SMG(shape, c, 1, 1, max_nrhs=16)
+    X0 = torch.from_numpy(synth.block(n ** 3, 16, 3)).to(dev)
+    G.lobpcg(X0, rtol=1e-8, max_iter=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, X, info = G.lobpcg(X0, rtol=1e-8, max_iter=400)
+    torch.cuda.synchronize()
+    res["lobpcg_128_m16_smg11"] = {"s": time.perf_counter() - t0, "iters": info.iters, "nconv": info.nconv,
+                                   "status": info.status}
+    del G, X
     for m, guard in ((16, 0), (64, 3)):
         G = SMG(shape, c, 1, 0, max_nrhs=m + guard)
         X0 = torch.from_numpy(synth.block(n ** 3, m + guard, 3)).to(dev)
@@ -292,9 +304,9 @@ def main():
         torch.cuda.synchronize()
         G.apply(b)
         torch.cuda.synchronize()
-        l0, clds = G.schedule()
+        l0, clds, mw = G.schedule()
         print(json.dumps({"pmc_probe": True, "copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8,
-                          "schedule_l0": l0, "schedule_coarse_lds": clds}))
+                          "schedule_l0": l0, "schedule_coarse_lds": clds, "schedule_march_waves": mw}))
         return
 
     torch.cuda.synchronize()
@@ -348,7 +360,7 @@ def main():
     dom = max(fams, key=lambda f: fams[f]["ms"])
     d = fams[dom]
     achieved = d["gbs"]
-    traffic = read_traffic(dom, (tune.l0, tune.coarse_lds))
+    traffic = read_traffic(dom, (tune.l0, tune.coarse_lds, tune.march_waves))
 
     out = {
         "metric": METRIC,
@@ -370,6 +382,7 @@ def main():
         "true_rel_res": infos[-1].true_rel_res,
         "setup_s": setup_s,
         "autotune": {"s": tune_s, "candidates": tune.candidates, "l0": tune.l0, "coarse_lds": tune.coarse_lds,
+                     "march_waves": tune.march_waves,
                      "default_vcycle_ms": tune.default_ms, "best_vcycle_ms": tune.best_ms},
         "vcycle_ms": vcycle_ms,
         "vcycle_gdof_per_s": N / (vcycle_ms * 1e-3) / 1e9,
@@ -405,6 +418,16 @@ def main():
             if Gv is not G:
                 del Gv
         var["fpcg_10"] = {"s": sec_per_solve, "iters": iters, "status": 0, "rel_res": infos[-1].rel_res}
+        # without a preconditioner: the cost per iteration of equation (2) against (1)
+        for name in ("pcg", "fpcg"):
+            fn = getattr(G, name)
+            fn(b, rtol=1e-8, max_iter=3, precond="none")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, inf = fn(b, rtol=1e-30, max_iter=200, precond="none")
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            var[f"{name}_noprec_200it"] = {"s": el, "iters": inf.iters, "ms_per_iter": el / max(inf.iters, 1) * 1e3}
         out["variants"] = var
 
     if not args.no_configs:

@@ -206,14 +206,22 @@ typedef struct smg_tune_info {
     int32_t candidates;     /* schedules timed, including the default */
     int32_t l0;             /* first 2D level handled by the coarse kernel */
     int32_t s_down, s_up;   /* strip heights */
+    int32_t march_waves;    /* lines up to 256 points: a pre-smoothing launch gives each wave a run of
+                               2, 4 or 8 coarse lines while it keeps >= march_waves waves (0: never) */
+    int32_t reserved;
     int64_t coarse_lds;     /* LDS bytes of the coarse kernel */
     double default_ms;      /* V-cycle time of the schedule before tuning */
     double best_ms;         /* V-cycle time of the chosen schedule */
 } smg_tune_info;
 int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *stream, smg_tune_info *info);
-/* The handle's current schedule (l0, s_down, s_up, coarse_lds; the timing
- * fields are zero).  Host-only. */
+/* The handle's current schedule (l0, s_down, s_up, march_waves, coarse_lds;
+ * the timing fields are zero).  Host-only. */
 int smg_get_schedule(const smg_handle *h, smg_tune_info *info);
+/* Sets the marching threshold of the register-only pre-smoothing kernels
+ * (march_waves >= 0; 0: one wave per coarse line everywhere).  Every value
+ * computes the same V-cycle up to rounding.  Host-only; SMG_EINVAL for a
+ * negative value. */
+int smg_set_march(smg_handle *h, int32_t march_waves);
 
 /* Measurement: the Gram product G = S^T S of LOBPCG's FP64 MFMA kernels for an
  * N x k block (k <= 3m) held in a workspace sized by lobpcg_workspace_bytes(h,

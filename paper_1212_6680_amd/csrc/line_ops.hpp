@@ -4,10 +4,11 @@
 // The exact line solve evaluates the two first-order recurrences of the
 // Thomas algorithm, y_i = g_i f_i + h_i y_{i-1} and u_i = y_i + h_i u_{i+1},
 // as scans of affine maps x -> a x + b across the 64 lanes.  Within each
-// 16-lane row the scan uses DPP row shifts (1, 2, 4, 8); the three row
-// aggregates are read as uniform values with readlane and folded in, and the
-// carry into each lane comes from a whole-wave DPP shift.  Everything stays in
-// VGPRs: no LDS, no ds_bpermute.
+// 16-lane row the scan uses DPP row shifts (1, 2, 4, 8); across rows the
+// forward scan uses DPP row broadcasts and the backward scan reads the row
+// aggregates as uniform values with readlane; the carry into each lane comes
+// from a whole-wave DPP shift.  Everything stays in VGPRs: no LDS, no
+// ds_bpermute.
 #pragma once
 
 #include "smg_internal.h"
@@ -48,59 +49,59 @@ __device__ inline double readlane(double v, int l)
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// (a, b) <- (a, b) o (pa, pb): first apply (pa, pb), then (a, b)
-template <typename A>
-__device__ inline void compose(A &a, A &b, A pa, A pb)
+// DPP move with bound_ctrl: lanes whose source lies outside the row (or the
+// wave) read 0, so no old value has to be set up.
+template <int CTRL>
+__device__ inline float dpp0(float v)
 {
-    b = a * pb + b;
-    a = a * pa;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 
-// Inclusive scan of lane maps in increasing lane order; on return b holds
-// the composed map of lanes 0..l applied to 0.
-template <typename A>
-__device__ inline void scan_up(A &a, A &b, int lane)
+template <int CTRL>
+__device__ inline double dpp0(double v)
 {
-    compose(a, b, dpp<kRowShr + 1>(A(1), a), dpp<kRowShr + 1>(A(0), b));
-    compose(a, b, dpp<kRowShr + 2>(A(1), a), dpp<kRowShr + 2>(A(0), b));
-    compose(a, b, dpp<kRowShr + 4>(A(1), a), dpp<kRowShr + 4>(A(0), b));
-    compose(a, b, dpp<kRowShr + 8>(A(1), a), dpp<kRowShr + 8>(A(0), b));
-    // row aggregates (uniform) and their prefixes
-    const A a0 = readlane(a, 15), b0 = readlane(b, 15);
-    const A a1 = readlane(a, 31), b1 = readlane(b, 31);
-    const A a2 = readlane(a, 47), b2 = readlane(b, 47);
-    A p1a = a0, p1b = b0;             // rows < 1
-    A p2a = a1, p2b = b1;
-    compose(p2a, p2b, p1a, p1b);      // rows < 2
-    A p3a = a2, p3b = b2;
-    compose(p3a, p3b, p2a, p2b);      // rows < 3
-    const int row = lane >> 4;
-    const A pa = row == 0 ? A(1) : row == 1 ? p1a : row == 2 ? p2a : p3a;
-    const A pb = row == 0 ? A(0) : row == 1 ? p1b : row == 2 ? p2b : p3b;
-    compose(a, b, pa, pb);
+    const long long s = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(s), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(s >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// Inclusive scan in decreasing lane order (lanes l..63).
-template <typename A>
-__device__ inline void scan_down(A &a, A &b, int lane)
+// Row broadcast (lane 15 or 31 of the wave into later rows) written only to
+// the rows in ROWS; the other rows read 0.
+constexpr int kRowBcast15 = 0x142;
+constexpr int kRowBcast31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ inline float dpp_rows(float v)
 {
-    compose(a, b, dpp<kRowShl + 1>(A(1), a), dpp<kRowShl + 1>(A(0), b));
-    compose(a, b, dpp<kRowShl + 2>(A(1), a), dpp<kRowShl + 2>(A(0), b));
-    compose(a, b, dpp<kRowShl + 4>(A(1), a), dpp<kRowShl + 4>(A(0), b));
-    compose(a, b, dpp<kRowShl + 8>(A(1), a), dpp<kRowShl + 8>(A(0), b));
-    const A a3 = readlane(a, 48), b3 = readlane(b, 48);
-    const A a2 = readlane(a, 32), b2 = readlane(b, 32);
-    const A a1 = readlane(a, 16), b1 = readlane(b, 16);
-    A q2a = a3, q2b = b3;             // rows > 2
-    A q1a = a2, q1b = b2;
-    compose(q1a, q1b, q2a, q2b);      // rows > 1
-    A q0a = a1, q0b = b1;
-    compose(q0a, q0b, q1a, q1b);      // rows > 0
-    const int row = lane >> 4;
-    const A qa = row == 3 ? A(1) : row == 2 ? q2a : row == 1 ? q1a : q0a;
-    const A qb = row == 3 ? A(0) : row == 2 ? q2b : row == 1 ? q1b : q0b;
-    compose(a, b, qa, qb);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
 }
+
+template <int CTRL, int ROWS>
+__device__ inline double dpp_rows(double v)
+{
+    const long long s = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(s), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(s >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// The exact line solve evaluates y_i = g_i f_i + h_i y_{i-1} (forward) and
+// u_i = y_i + h_i u_{i+1} (backward).  Over a lane's E points each recurrence
+// is an affine map x -> A_l x + B_l, where A_l (a product of h) depends on the
+// table only and B_l on the data.  The lane scans combine the maps with
+// B_l += M * B_{source}, where the multipliers M are products of A over
+// lane ranges: a LinePlan holds them, built once per table, so that every
+// solve with the table scans B alone (one DPP move and one FMA per step).
+template <typename A, int E>
+struct LinePlan {
+    A g[E], h[E];
+    A fm[4];          // forward row steps 1, 2, 4, 8: A over the lanes (l - s, l]
+    A f15, f31;       // forward row broadcasts: A from the row start (and earlier rows) to l
+    A bm[4];          // backward row steps: A over the lanes [l, l + s)
+    A bq;             // backward: A from l to the end of its row
+    A s16, s32;       // backward, uniform: A over all of row 1 and row 2
+};
 
 // This lane's part of a Thomas table (g_i, h_i).
 template <typename A, int E>
@@ -115,37 +116,92 @@ __device__ inline void load_fac(A (&g)[E], A (&h)[E], const Fac<A> *fac, int lan
     }
 }
 
-// Exact solve of one line in place with a Thomas table held in registers.
+// Plan of the Thomas table fac: the products of h the lane scans multiply by.
 template <typename A, int E>
-__device__ inline void thomas_gh(A (&f)[E], const A (&g)[E], const A (&h)[E], int lane)
+__device__ inline void make_plan(LinePlan<A, E> &P, const Fac<A> *fac, int lane)
+{
+    load_fac<A, E>(P.g, P.h, fac, lane);
+    A a0 = A(1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) a0 *= P.h[e];
+    // forward: lanes without a source compose with the identity (A = 1)
+    A a = a0;
+    P.fm[0] = a;
+    a *= dpp<kRowShr + 1>(A(1), a);
+    P.fm[1] = a;
+    a *= dpp<kRowShr + 2>(A(1), a);
+    P.fm[2] = a;
+    a *= dpp<kRowShr + 4>(A(1), a);
+    P.fm[3] = a;
+    a *= dpp<kRowShr + 8>(A(1), a);
+    P.f15 = a;
+    const int row = lane >> 4;
+    const A a15 = dpp<kRowBcast15>(A(1), a);   // lane 15 of the previous row
+    if (row == 1 || row == 3) a *= a15;
+    P.f31 = a;
+    // backward
+    a = a0;
+    P.bm[0] = a;
+    a *= dpp<kRowShl + 1>(A(1), a);
+    P.bm[1] = a;
+    a *= dpp<kRowShl + 2>(A(1), a);
+    P.bm[2] = a;
+    a *= dpp<kRowShl + 4>(A(1), a);
+    P.bm[3] = a;
+    a *= dpp<kRowShl + 8>(A(1), a);
+    P.bq = a;
+    P.s16 = readlane(a, 16);
+    P.s32 = readlane(a, 32);
+}
+
+// Exact solve of one line in place with a plan.
+template <typename A, int E>
+__device__ inline void solve_plan(A (&f)[E], const LinePlan<A, E> &P, int lane)
 {
     A pr[E];
     A acc = A(0), prod = A(1);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        acc = g[e] * f[e] + h[e] * acc;
-        prod *= h[e];
+        acc = P.g[e] * f[e] + P.h[e] * acc;
+        prod *= P.h[e];
         f[e] = acc;
         pr[e] = prod;
     }
-    A sa = pr[E - 1], sb = f[E - 1];
-    scan_up(sa, sb, lane);
-    const A carry_in = dpp<kWaveShr1>(A(0), sb);   // y at the last point of lane l-1
+    // inclusive forward scan: rows by shifts, then rows 1, 3 from lane 15 of
+    // the row before, rows 2, 3 from lane 31
+    A b = f[E - 1];
+    b = P.fm[0] * dpp0<kRowShr + 1>(b) + b;
+    b = P.fm[1] * dpp0<kRowShr + 2>(b) + b;
+    b = P.fm[2] * dpp0<kRowShr + 4>(b) + b;
+    b = P.fm[3] * dpp0<kRowShr + 8>(b) + b;
+    b = P.f15 * dpp_rows<kRowBcast15, 0xA>(b) + b;
+    b = P.f31 * dpp_rows<kRowBcast31, 0xC>(b) + b;
+    const A carry_in = dpp0<kWaveShr1>(b);   // y at the last point of lane l-1
 #pragma unroll
     for (int e = 0; e < E; ++e) f[e] += pr[e] * carry_in;
     acc = A(0);
     prod = A(1);
 #pragma unroll
     for (int e = E - 1; e >= 0; --e) {
-        acc = f[e] + h[e] * acc;
-        prod *= h[e];
+        acc = f[e] + P.h[e] * acc;
+        prod *= P.h[e];
         f[e] = acc;
         pr[e] = prod;
     }
-    sa = pr[0];
-    sb = f[0];
-    scan_down(sa, sb, lane);
-    const A carry_up = dpp<kWaveShl1>(A(0), sb);   // u at the first point of lane l+1
+    // inclusive backward scan: rows by shifts, then the later rows' totals
+    // (first lanes of rows 1..3) composed as uniform values
+    b = f[0];
+    b = P.bm[0] * dpp0<kRowShl + 1>(b) + b;
+    b = P.bm[1] * dpp0<kRowShl + 2>(b) + b;
+    b = P.bm[2] * dpp0<kRowShl + 4>(b) + b;
+    b = P.bm[3] * dpp0<kRowShl + 8>(b) + b;
+    const A b1 = readlane(b, 16), b2 = readlane(b, 32), b3 = readlane(b, 48);
+    const A q1 = P.s32 * b3 + b2;   // rows > 1
+    const A q0 = P.s16 * q1 + b1;   // rows > 0
+    const int row = lane >> 4;
+    const A q = row == 3 ? A(0) : row == 2 ? b3 : row == 1 ? q1 : q0;
+    b = P.bq * q + b;
+    const A carry_up = dpp0<kWaveShl1>(b);   // u at the first point of lane l+1
 #pragma unroll
     for (int e = 0; e < E; ++e) f[e] += pr[e] * carry_up;
 }
@@ -154,9 +210,9 @@ __device__ inline void thomas_gh(A (&f)[E], const A (&g)[E], const A (&h)[E], in
 template <typename A, int E>
 __device__ inline void thomas(A (&f)[E], const Fac<A> *fac, int lane)
 {
-    A g[E], h[E];
-    load_fac<A, E>(g, h, fac, lane);
-    thomas_gh<A, E>(f, g, h, lane);
+    LinePlan<A, E> P;
+    make_plan<A, E>(P, fac, lane);
+    solve_plan<A, E>(f, P, lane);
 }
 
 // f -= (a*Tx + b*I) w   (w zero beyond nx)
@@ -164,8 +220,8 @@ template <typename A, int E>
 __device__ inline void sub_op(A (&f)[E], const A (&w)[E], A a, A b)
 {
     if (a != A(0)) {
-        const A left = dpp<kWaveShr1>(A(0), w[E - 1]);
-        const A right = dpp<kWaveShl1>(A(0), w[0]);
+        const A left = dpp0<kWaveShr1>(w[E - 1]);
+        const A right = dpp0<kWaveShl1>(w[0]);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const A wl = e > 0 ? w[e - 1] : left;
@@ -178,9 +234,29 @@ __device__ inline void sub_op(A (&f)[E], const A (&w)[E], A a, A b)
     }
 }
 
+// Widest access a lane's E consecutive values allow (bytes; 0: element by element).
+template <typename T, int E>
+constexpr int chunk_align()
+{
+    constexpr int cb = E * static_cast<int>(sizeof(T));
+    return cb % 16 == 0 ? 16 : cb % 8 == 0 ? 8 : 0;
+}
+
+// A lane whose E points all lie inside the line reads them as one aligned
+// chunk (16-byte loads for FP64 with E = 2 or 4) when the row is aligned;
+// the lane holding the end of a ragged line goes point by point.
 template <typename T, typename A, int E>
 __device__ inline void gload(A (&v)[E], const T *row, int nx, int lane)
 {
+    constexpr int G = chunk_align<T, E>();
+    if constexpr (G > 0) {
+        if ((reinterpret_cast<uintptr_t>(row) % G) == 0 && (lane + 1) * E <= nx) {
+            const T *p = static_cast<const T *>(__builtin_assume_aligned(row + lane * E, G));
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = static_cast<A>(ldv(p + e));
+            return;
+        }
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = lane * E + e;
@@ -191,6 +267,15 @@ __device__ inline void gload(A (&v)[E], const T *row, int nx, int lane)
 template <typename T, typename A, int E>
 __device__ inline void gstore(T *row, const A (&v)[E], int nx, int lane)
 {
+    constexpr int G = chunk_align<T, E>();
+    if constexpr (G > 0) {
+        if ((reinterpret_cast<uintptr_t>(row) % G) == 0 && (lane + 1) * E <= nx) {
+            T *p = static_cast<T *>(__builtin_assume_aligned(row + lane * E, G));
+#pragma unroll
+            for (int e = 0; e < E; ++e) stv(p + e, v[e]);
+            return;
+        }
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = lane * E + e;

@@ -222,14 +222,14 @@ __device__ __forceinline__ void k2_down_reg_body(const Down2Args<T, A> &a, const
         b1[e] = cp1[e];
         b2[e] = fp2[e];
     }
-    // interior lines share one Thomas table: load it once
+    // interior lines share one Thomas table: plan it once
     const int fi = lc[j0].fac;
-    A g[E], h[E];
-    load_fac<A, E>(g, h, a.fac + static_cast<size_t>(fi) * nxp, lane);
+    LinePlan<A, E> plan;
+    make_plan<A, E>(plan, a.fac + static_cast<size_t>(fi) * nxp, lane);
     auto solve = [&](A (&x)[E], int j) {
         const int fj = lc[j].fac;
         if (fj == fi)
-            thomas_gh<A, E>(x, g, h, lane);
+            solve_plan<A, E>(x, plan, lane);
         else
             thomas<A, E>(x, a.fac + static_cast<size_t>(fj) * nxp, lane);
     };
@@ -311,6 +311,172 @@ __global__ __launch_bounds__(256) void k2_down_reg_grp_e4(const GroupEntry *tab,
     case 2: k2_down_reg_body<T, A, 2>(*a, blk); break;
     case 3: k2_down_reg_body<T, A, 3>(*a, blk); break;
     default: k2_down_reg_body<T, A, 4>(*a, blk); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k2_down_march: the same stage with one wave per run of K = a.kr coarse lines
+// J0 .. J0+K-1, marching upward in y.  The wave keeps x_{2J}, x_{2J+1},
+// x_{2J+2}, the residual r_{2J} and the right-hand sides b_{2J+1}, b_{2J+2};
+// each step solves F line 2J+4 and C line 2J+3 and forms r_{2J+1}, r_{2J+2}
+// and b_c[J].  A run costs 2K + 5 line solves for 2K lines (K = 1: the seven
+// solves of k2_down_reg) and reads each right-hand side once, apart from the
+// five lines its start-up shares with the previous run.  The right-hand sides
+// of the next step are loaded one step ahead.  Arithmetic per line is that of
+// k2_down_reg (up to how the compiler fuses multiply-adds).
+// ---------------------------------------------------------------------------
+template <typename T, typename A, int E>
+__device__ __forceinline__ void k2_down_march_body(const Down2Args<T, A> &a, const Blk &blk)
+{
+    const int lane = threadIdx.x & 63;
+    const int K = a.kr;
+    const int nrun = (a.nyc + K - 1) / K;
+    const long long wv = static_cast<long long>(blk.x) * 4 + wave_id();
+    const long long total = static_cast<long long>(nrun) * a.np * a.nrhs;
+    if (wv >= total) return;   // whole waves
+    const int run = static_cast<int>(wv % nrun);
+    const long long t = wv / nrun;
+    const int p = static_cast<int>(t % a.np), r = static_cast<int>(t / a.np);
+    const int ny = a.ny, nx = a.nx, nxp = a.nxp;
+    const int k = p * a.kmul + a.koff;
+    const LineCoef<A> *lc = plane_lines(a.pc, k, a.lc, a.lines_total);
+    const T *bpl = a.b + r * a.brs + p * a.bps;
+    T *xpl = a.x + r * a.xrs + p * a.xps;
+    T *bcpl = a.bc + r * a.crs + p * a.cps;
+    const int J0 = run * K, J1 = min(J0 + K, a.nyc);
+    const int j0 = 2 * J0;
+
+    const int fi = lc[j0].fac;
+    LinePlan<A, E> plan;
+    make_plan<A, E>(plan, a.fac + static_cast<size_t>(fi) * nxp, lane);
+    auto solve = [&](A (&x)[E], int j) {
+        const int fj = lc[j].fac;
+        if (fj == fi)
+            solve_plan<A, E>(x, plan, lane);
+        else
+            thomas<A, E>(x, a.fac + static_cast<size_t>(fj) * nxp, lane);
+    };
+    auto solve_c = [&](A (&x)[E], int j, const A (&xl)[E], const A (&xr)[E]) {
+        const LineCoef<A> cm = lc[j - 1];
+        sub_op<A, E>(x, xl, cm.va, cm.vb);
+        if (j + 1 < ny) {
+            const LineCoef<A> cj = lc[j];
+            sub_op<A, E>(x, xr, cj.va, cj.vb);
+        }
+        solve(x, j);
+    };
+    auto zero = [](A (&v)[E]) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = A(0);
+    };
+    auto copy = [](A (&d)[E], const A (&v)[E]) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) d[e] = v[e];
+    };
+
+    // start-up: x_{j0-2}, x_{j0-1} (first run: none), x_{j0}, x_{j0+1}, x_{j0+2}, r_{j0}
+    A xa[E], xc[E], xb[E], rp[E], b1[E], b2[E], n3[E], n4[E];
+    {
+        A fm2[E], cm1[E];
+        zero(fm2);
+        zero(cm1);
+        zero(xb);
+        zero(n3);
+        zero(n4);
+        const bool has_m2 = j0 >= 2;
+        if (has_m2) {
+            gload<T, A, E>(fm2, bpl + static_cast<long long>(j0 - 2) * nx, nx, lane);
+            gload<T, A, E>(cm1, bpl + static_cast<long long>(j0 - 1) * nx, nx, lane);
+        }
+        gload<T, A, E>(xa, bpl + static_cast<long long>(j0) * nx, nx, lane);
+        gload<T, A, E>(xc, bpl + static_cast<long long>(j0 + 1) * nx, nx, lane);
+        if (j0 + 2 < ny) gload<T, A, E>(xb, bpl + static_cast<long long>(j0 + 2) * nx, nx, lane);
+        if (j0 + 3 < ny) gload<T, A, E>(n3, bpl + static_cast<long long>(j0 + 3) * nx, nx, lane);
+        if (j0 + 4 < ny) gload<T, A, E>(n4, bpl + static_cast<long long>(j0 + 4) * nx, nx, lane);
+        copy(rp, xa);
+        copy(b1, xc);
+        copy(b2, xb);
+        if (has_m2) solve(fm2, j0 - 2);
+        solve(xa, j0);
+        if (j0 + 2 < ny) solve(xb, j0 + 2);
+        if (has_m2) solve_c(cm1, j0 - 1, fm2, xa);
+        solve_c(xc, j0 + 1, xa, xb);   // j0 + 1 < ny always (J0 < nyc)
+        const LineCoef<A> cj = lc[j0];
+        sub_op<A, E>(rp, xa, cj.la, cj.lb);
+        if (has_m2) {
+            const LineCoef<A> cm = lc[j0 - 1];
+            sub_op<A, E>(rp, cm1, cm.va, cm.vb);
+        }
+        sub_op<A, E>(rp, xc, cj.va, cj.vb);
+    }
+    for (int J = J0; J < J1; ++J) {
+        // state: xa = x_j, xc = x_{j+1}, xb = x_{j+2}, rp = r_j, b1 = b_{j+1}, b2 = b_{j+2},
+        // n3 = b_{j+3}, n4 = b_{j+4} (zero beyond the level)
+        const int j = 2 * J;
+        const bool h2 = j + 2 < ny, h3 = j + 3 < ny, h4 = j + 4 < ny;
+        A xe[E], xd[E], b3[E], b4[E];
+        copy(xe, n3);
+        copy(xd, n4);
+        copy(b3, n3);
+        copy(b4, n4);
+        if (J + 1 < J1) {   // the next step's right-hand sides, one step ahead
+            zero(n3);
+            zero(n4);
+            if (j + 5 < ny) gload<T, A, E>(n3, bpl + static_cast<long long>(j + 5) * nx, nx, lane);
+            if (j + 6 < ny) gload<T, A, E>(n4, bpl + static_cast<long long>(j + 6) * nx, nx, lane);
+        }
+        // r_{j+1} (needs nothing new)
+        A acc[E];
+        {
+            const LineCoef<A> cj = lc[j + 1], cm = lc[j];
+            sub_op<A, E>(b1, xc, cj.la, cj.lb);
+            sub_op<A, E>(b1, xa, cm.va, cm.vb);
+            if (h2) sub_op<A, E>(b1, xb, cj.va, cj.vb);
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = A(0.5) * rp[e] + b1[e];
+        }
+        gstore<T, A, E>(xpl + static_cast<long long>(j) * nx, xa, nx, lane);
+        gstore<T, A, E>(xpl + static_cast<long long>(j + 1) * nx, xc, nx, lane);
+        if (J == a.nyc - 1 && h2) gstore<T, A, E>(xpl + static_cast<long long>(j + 2) * nx, xb, nx, lane);
+        // x_{j+4}, x_{j+3}
+        if (h4) solve(xd, j + 4);
+        if (h3) solve_c(xe, j + 3, xb, xd);
+        // r_{j+2}
+        if (h2) {
+            const LineCoef<A> cj = lc[j + 2], cm = lc[j + 1];
+            sub_op<A, E>(b2, xb, cj.la, cj.lb);
+            sub_op<A, E>(b2, xc, cm.va, cm.vb);
+            if (h3) sub_op<A, E>(b2, xe, cj.va, cj.vb);
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] += A(0.5) * b2[e];
+        }
+        gstore<T, A, E>(bcpl + static_cast<long long>(J) * nx, acc, nx, lane);
+        copy(xa, xb);
+        copy(xc, xe);
+        copy(xb, xd);
+        copy(rp, b2);
+        copy(b1, b3);
+        copy(b2, b4);
+    }
+}
+
+template <typename T, typename A, int E>
+__global__ __launch_bounds__(256) void k2_down_march(Down2Args<T, A> a)
+{
+    k2_down_march_body<T, A, E>(a, SMG_BLK_HW);
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void k2_down_march_grp_e4(const GroupEntry *tab, int n)
+{
+    const Down2Args<T, A> *a;
+    Blk blk;
+    if (!group_entry(tab, n, a, blk)) return;
+    switch (a->nxp / 64) {
+    case 1: k2_down_march_body<T, A, 1>(*a, blk); break;
+    case 2: k2_down_march_body<T, A, 2>(*a, blk); break;
+    case 3: k2_down_march_body<T, A, 3>(*a, blk); break;
+    default: k2_down_march_body<T, A, 4>(*a, blk); break;
     }
 }
 
@@ -842,9 +1008,29 @@ template <typename T, typename A>
 void launch_down2(const Down2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     const int E = a.nxp / 64;
-    if (E <= 4) {   // register-only variant: one wave per coarse line
+    if (E <= 4) {   // register-only variants: one wave per coarse line, or per run of them
         const long long waves = static_cast<long long>(a.nyc) * a.np * a.nrhs;
         if (waves == 0) return;
+        int kr = 1;
+        if (a.march_waves > 0)
+            for (const int c : {8, 4, 2})
+                if (waves / c >= a.march_waves) {
+                    kr = c;
+                    break;
+                }
+        if (kr > 1) {
+            Down2Args<T, A> m = a;
+            m.kr = kr;
+            const long long mw = static_cast<long long>((a.nyc + kr - 1) / kr) * a.np * a.nrhs;
+            const dim3 mgrid(static_cast<unsigned>((mw + 3) / 4));
+            switch (E) {
+            case 1: SMG_LAUNCH_G(ev, (k2_down_march<T, A, 1>), (k2_down_march_grp_e4<T, A>), mgrid, dim3(256), 0, st, m); break;
+            case 2: SMG_LAUNCH_G(ev, (k2_down_march<T, A, 2>), (k2_down_march_grp_e4<T, A>), mgrid, dim3(256), 0, st, m); break;
+            case 3: SMG_LAUNCH_G(ev, (k2_down_march<T, A, 3>), (k2_down_march_grp_e4<T, A>), mgrid, dim3(256), 0, st, m); break;
+            default: SMG_LAUNCH_G(ev, (k2_down_march<T, A, 4>), (k2_down_march_grp_e4<T, A>), mgrid, dim3(256), 0, st, m); break;
+            }
+            return;
+        }
         const dim3 grid(static_cast<unsigned>((waves + 3) / 4));
         switch (E) {
         case 1: SMG_LAUNCH_G(ev, (k2_down_reg<T, A, 1>), (k2_down_reg_grp_e4<T, A>), grid, dim3(256), 0, st, a); break;

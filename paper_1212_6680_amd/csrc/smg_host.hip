@@ -96,6 +96,7 @@ struct smg_handle {
     int l0;
     size_t coarse_lds;
     int S_down, S_up;
+    int march_waves;              // down2 launches march runs of coarse lines while they keep this many waves
     size_t coarse_budget, strip_budget;   // LDS budgets the schedule was built for
     char *ws;
     Layout L;
@@ -135,6 +136,10 @@ size_t arith_size(int prec) { return prec == SMG_PREC_F64 ? 8 : 4; }
 // 160 KB: every extra 2D level it absorbs removes one launch per 2D cycle.
 constexpr size_t kCoarseLds = 128 * 1024;
 constexpr size_t kStripLds = 48 * 1024;
+// Register-only pre-smoothing: a launch with at least twice this many
+// coarse-line waves gives each wave a run of 2, 4 or 8 coarse lines (fewer
+// redundant line solves, fewer waves); below it every wave takes one line.
+constexpr int kMarchWaves = 2048;
 
 // Schedule of the fused 2D cycle for given LDS budgets: the coarse kernel
 // takes every 2D level from l0 down whose lines fit coarse_budget; the strip
@@ -444,6 +449,7 @@ struct VCycle {
             d.nx = nx; d.nxp = h->nxp; d.ny = h->ny2[l]; d.nyc = h->ny2[l + 1]; d.S = h->S_down;
             d.np = bt.np; d.nrhs = nrhs; d.kmul = bt.kmul; d.koff = bt.koff;
             d.pc = bt.pc; d.lc = LC(l); d.lines_total = h->lines_total; d.fac = h->at<Fac<A>>(h->L.fac);
+            d.march_waves = h->march_waves;
             launch_down2<T, A>(d, st, ev_for(SMG_KERNEL_DOWN2,
                                              (2.0 * d.ny + d.nyc) * nx * bt.np * static_cast<double>(nrhs)));
         }
@@ -899,6 +905,7 @@ int smg_setup(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, void *ws, 
         h->P2 = (g->nz + 1) / 2;
         h->elem = elem_size(o->precision);
         choose_fused_schedule(h);
+        h->march_waves = kMarchWaves;
         h->L = make_layout(*g, *o, max_nrhs, t, h->nxp);
         if (ws_bytes < h->L.total) {
             delete h;
@@ -980,6 +987,13 @@ const char *smg_strerror(int status)
     }
 }
 
+int smg_set_march(smg_handle *h, int32_t march_waves)
+{
+    if (!h || march_waves < 0) return SMG_EINVAL;
+    h->march_waves = march_waves;
+    return SMG_OK;
+}
+
 int smg_get_schedule(const smg_handle *h, smg_tune_info *info)
 {
     if (!h || !info) return SMG_EINVAL;
@@ -988,6 +1002,7 @@ int smg_get_schedule(const smg_handle *h, smg_tune_info *info)
     info->coarse_lds = static_cast<int64_t>(h->coarse_lds);
     info->s_down = h->S_down;
     info->s_up = h->S_up;
+    info->march_waves = h->march_waves;
     return SMG_OK;
 }
 
@@ -1059,6 +1074,24 @@ int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *
                 apply_fused_schedule(h, keep_c, keep_s);
             }
         apply_fused_schedule(h, best_c, best_s);
+        // then the marching threshold of the register-only pre-smoothing
+        // kernels (0: one wave per coarse line everywhere)
+        const int cand_mw[] = {0, 1024, 2048, 4096, 8192};
+        int best_mw = h->march_waves;
+        const int keep_mw = h->march_waves;
+        for (int mw : cand_mw) {
+            if (mw == keep_mw) continue;
+            h->march_waves = mw;
+            double ms = 0.0;
+            if (time_cycle(&ms)) {
+                ++inf.candidates;
+                if (ms < 0.98 * best) {
+                    best = ms;
+                    best_mw = mw;
+                }
+            }
+        }
+        h->march_waves = best_mw;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1067,6 +1100,7 @@ int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *
     inf.coarse_lds = static_cast<int64_t>(h->coarse_lds);
     inf.s_down = h->S_down;
     inf.s_up = h->S_up;
+    inf.march_waves = h->march_waves;
     if (info) *info = inf;
     return rc;
 }

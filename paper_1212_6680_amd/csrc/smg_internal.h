@@ -191,6 +191,8 @@ struct Down2Args {
     const LineCoef<A> *lc;      // rows of this 2D level, plane type 0
     int lines_total;
     const Fac<A> *fac;
+    int march_waves;        // a launch marches runs of coarse lines while it keeps >= this many waves (0: never)
+    int kr;                 // coarse lines per wave of the marching kernel (set by the launcher)
 };
 
 template <typename T, typename A>

@@ -51,6 +51,7 @@ class krylov_info(C.Structure):
 
 class smg_tune_info(C.Structure):
     _fields_ = [("candidates", C.c_int32), ("l0", C.c_int32), ("s_down", C.c_int32), ("s_up", C.c_int32),
+                ("march_waves", C.c_int32), ("reserved", C.c_int32),
                 ("coarse_lds", C.c_int64), ("default_ms", C.c_double), ("best_ms", C.c_double)]
 
 
@@ -102,6 +103,7 @@ def lib():
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
         L.smg_autotune.argtypes = [p, p, p, i32, p, C.POINTER(smg_tune_info)]
         L.smg_get_schedule.argtypes = [p, C.POINTER(smg_tune_info)]
+        L.smg_set_march.argtypes = [p, i32]
         L.smg_batch_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
         L.smg_batch_create.argtypes = [p, i32, p, p, p, C.c_size_t, i32, p, C.POINTER(p)]
         L.smg_batch_fpcg.argtypes = [p, C.POINTER(krylov_opts), p, p]
@@ -271,13 +273,18 @@ class SMG:
         _check(lib().smg_autotune(self.h, _dptr(r, self.n), _dptr(s, self.n), reps, _stream(), C.byref(info)),
                "smg_autotune")
         return Info(candidates=info.candidates, l0=info.l0, s_down=info.s_down, s_up=info.s_up,
-                    coarse_lds=info.coarse_lds, default_ms=info.default_ms, best_ms=info.best_ms)
+                    march_waves=info.march_waves, coarse_lds=info.coarse_lds, default_ms=info.default_ms,
+                    best_ms=info.best_ms)
 
     def schedule(self):
-        """(l0, coarse kernel LDS bytes) of the fused 2D-cycle schedule in use."""
+        """(l0, coarse kernel LDS bytes, marching threshold) of the fused 2D-cycle schedule in use."""
         info = smg_tune_info()
         _check(lib().smg_get_schedule(self.h, C.byref(info)), "smg_get_schedule")
-        return info.l0, info.coarse_lds
+        return info.l0, info.coarse_lds, info.march_waves
+
+    def set_march(self, march_waves: int):
+        """Marching threshold of the register-only pre-smoothing kernels (0: never march)."""
+        _check(lib().smg_set_march(self.h, int(march_waves)), "smg_set_march")
 
     def profile_gram(self, m: int, k: int, reps: int = 5) -> float:
         """ms of one LOBPCG Gram product S^T S for an n x k block (k <= 3m)."""
