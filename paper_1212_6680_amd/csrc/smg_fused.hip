@@ -73,15 +73,20 @@ __device__ __forceinline__ void k2_down_body(const Down2Args<T, A> &a, const Blk
     const int jf = f0 + 2 * w, jc = c0 + 2 * w, J = J0 + w;
     const bool hf = w < nf, hc = w < nc, hr = J < J1;
 
-    // every global read of the workgroup, issued up front
+    // every global read of the workgroup, issued up front (the residual rows
+    // of very wide FP64 lines only after the solves: registers)
+    constexpr bool kEarly = E * sizeof(A) <= 48;
     A fb[E], cb[E], rb0[E], rb1[E], rb2[E];
+    auto load_rows = [&]() {
+        if (hr) {
+            gload<T, A, E>(rb0, bpl + static_cast<long long>(2 * J) * nx, nx, lane);
+            gload<T, A, E>(rb1, bpl + static_cast<long long>(2 * J + 1) * nx, nx, lane);
+            if (2 * J + 2 < ny) gload<T, A, E>(rb2, bpl + static_cast<long long>(2 * J + 2) * nx, nx, lane);
+        }
+    };
     if (hf) gload<T, A, E>(fb, bpl + static_cast<long long>(jf) * nx, nx, lane);
     if (hc) gload<T, A, E>(cb, bpl + static_cast<long long>(jc) * nx, nx, lane);
-    if (hr) {
-        gload<T, A, E>(rb0, bpl + static_cast<long long>(2 * J) * nx, nx, lane);
-        gload<T, A, E>(rb1, bpl + static_cast<long long>(2 * J + 1) * nx, nx, lane);
-        if (2 * J + 2 < ny) gload<T, A, E>(rb2, bpl + static_cast<long long>(2 * J + 2) * nx, nx, lane);
-    }
+    if constexpr (kEarly) load_rows();
     // F lines: x_j = L_j^{-1} b_j
     if (hf) {
         thomas<A, E>(fb, a.fac + static_cast<size_t>(lc[jf].fac) * nxp, lane);
@@ -114,6 +119,7 @@ __device__ __forceinline__ void k2_down_body(const Down2Args<T, A> &a, const Blk
         }
     }
     // restricted residual of coarse line J
+    if constexpr (!kEarly) load_rows();
     if (hr) {
         A acc[E];
 #pragma unroll
@@ -729,6 +735,9 @@ template <typename T, typename A>
 __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const Blk &blk)
 {
     __shared__ A vs[2][kChainWin * kChainCols];
+    constexpr int kPreLev = 4;                  // chain levels whose reads are issued up front
+    constexpr int kRowsLev = kChainWin / 4;     // window lines per thread at a level >= 1
+    constexpr int kRows0 = kChainRun / 4;       // fine lines per thread
     const int nx = a.nx;
     const int ncol = (nx + kChainCols - 1) / kChainCols;
     const int nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
@@ -747,36 +756,74 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
         for (int m = 0; m < l; ++m) wv = coarser(wv, a.ny2[m + 1]);
         return wv;
     };
+    auto level_row = [&](int l, const Win &wl, int jj) -> A {
+        const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
+        return jj <= wl.hi && i < nx ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * nx + i)) : A(0);
+    };
+    // every global read of the first kPreLev chain levels and of the fine
+    // run, issued before the first barrier (each would otherwise wait for
+    // the level above it)
+    A pre[kPreLev][kRowsLev];
+#pragma unroll
+    for (int q = 0; q < kPreLev; ++q) {
+        const int l = a.lc - q;
+        if (l < 1) break;
+        const Win wl = win(l);
+#pragma unroll
+        for (int t = 0; t < kRowsLev; ++t) pre[q][t] = level_row(l, wl, wl.lo + row0 + 4 * t);
+    }
+    const T *x0 = a.x0 + r * a.x0rs + p * a.x0ps;
+    T *out = a.out + r * a.ors + p * a.ops;
+    A xf[kRows0], of[kRows0];
+#pragma unroll
+    for (int t = 0; t < kRows0; ++t) {
+        const int jj = w0.lo + row0 + 4 * t;
+        xf[t] = of[t] = A(0);
+        if (jj <= w0.hi && i < nx) {
+            const long long o = static_cast<long long>(jj) * nx + i;
+            xf[t] = static_cast<A>(ldv(x0 + o));
+            if (a.accumulate) of[t] = static_cast<A>(ldv(out + o));
+        }
+    }
     int cur = 0;
     {   // coarsest level of the chain: v = x_lc
-        const int l = a.lc;
-        const Win wl = win(l);
-        const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
-        for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4)
-            vs[cur][(jj - wl.lo) * kChainCols + col] =
-                i < nx ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * nx + i)) : A(0);
+        const Win wl = win(a.lc);
+#pragma unroll
+        for (int t = 0; t < kRowsLev; ++t) {
+            const int jj = wl.lo + row0 + 4 * t;
+            if (jj <= wl.hi) vs[cur][(jj - wl.lo) * kChainCols + col] = pre[0][t];
+        }
         __syncthreads();
     }
-    for (int l = a.lc - 1; l >= 1; --l) {
+    // v_l = x_l + P v_{l+1}
+    auto step = [&](int l, auto &&xval) {
         const Win wl = win(l), wc = win(l + 1);
-        const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
-        for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4) {
-            A s = i < nx ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * nx + i)) : A(0);
-            s += prolong_point(vs[cur], wc, jj, a.ny2[l + 1], col);
+#pragma unroll
+        for (int t = 0; t < kRowsLev; ++t) {
+            const int jj = wl.lo + row0 + 4 * t;
+            if (jj > wl.hi) break;
+            const A s = xval(t, jj, wl) + prolong_point(vs[cur], wc, jj, a.ny2[l + 1], col);
             vs[cur ^ 1][(jj - wl.lo) * kChainCols + col] = s;
         }
         cur ^= 1;
         __syncthreads();
+    };
+#pragma unroll
+    for (int q = 1; q < kPreLev; ++q) {
+        const int l = a.lc - q;
+        if (l < 1) break;
+        step(l, [&](int t, int, const Win &) { return pre[q][t]; });
     }
+    for (int l = a.lc - kPreLev; l >= 1; --l) step(l, [&](int, int jj, const Win &wl) { return level_row(l, wl, jj); });
     if (i >= nx) return;
     const Win wc = win(1);
-    const T *x0 = a.x0 + r * a.x0rs + p * a.x0ps;
-    T *out = a.out + r * a.ors + p * a.ops;
-    for (int jj = w0.lo + row0; jj <= w0.hi; jj += 4) {
-        const long long o = static_cast<long long>(jj) * nx + i;
-        A s = static_cast<A>(ldv(x0 + o)) + prolong_point(vs[cur], wc, jj, a.ny2[1], col);
-        if (a.accumulate) s += static_cast<A>(ldv(out + o));
-        stv(out + o, s);
+#pragma unroll
+    for (int t = 0; t < kRows0; ++t) {
+        const int jj = w0.lo + row0 + 4 * t;
+        if (jj > w0.hi) break;
+        A s = xf[t] + prolong_point(vs[cur], wc, jj, a.ny2[1], col);
+        if (a.accumulate) s += of[t];
+        stv(out + static_cast<long long>(jj) * nx + i, s);
     }
 }
 

@@ -399,7 +399,7 @@ __global__ void k_convert_out(const T *src, long long lds, double *dst, long lon
 // and a window of three planes (x and T2 x) in registers feeds the 15-point
 // residuals r_k = b_k - C_k x_k - U_{k-1} x_{k-1} - U_k x_{k+1}, which are
 // combined into b_c[K] = 1/2 r_{2K} + r_{2K+1} + 1/2 r_{2K+2} as the march
-// passes.  x and b are read about once.
+// passes.  x and b are read about once, a few planes ahead of their use.
 constexpr int kRTX = 64, kRTY = 8, kRThreads = kRTX * kRTY;
 
 template <typename T, typename A>
@@ -429,15 +429,39 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
     const long long hc2 = static_cast<long long>(hj) * nx + hi;
     const int cc = (ty + 1) * (kRTX + 2) + tx + 1;
     const A cx = a.cx, cy = a.cy;
+    // planes this block reads: x up to 2 K1 + 1, b up to 2 K1
+    const int kx_last = min(nz - 1, 2 * K1 + 1), kb_last = min(nz - 1, 2 * K1);
+    // the next kPre planes of x (centre and halo point) and of b are loaded
+    // ahead into small register rings, so that a step waits on a load issued
+    // kPre steps before rather than on its own
+    constexpr int kPre = 4;
+    auto load_x = [&](int k, A &xc, A &xh) {
+        const bool live = k >= 0 && k <= kx_last && !a.x_zero;
+        xc = (in && live) ? static_cast<A>(ldv(x + k * pl + c2)) : A(0);
+        xh = (hin && live) ? static_cast<A>(ldv(x + k * pl + hc2)) : A(0);
+    };
+    auto load_b = [&](int k) { return in && k <= kb_last ? static_cast<A>(ldv(b + k * pl + c2)) : A(0); };
     // window of planes kl-2, kl-1, kl: x and T2 x at this point
     A xw0 = 0, xw1 = 0, xw2 = 0, tw0 = 0, tw1 = 0, tw2 = 0;
-    int kl = 2 * K0 - 2;   // next advance loads plane kl + 1
+    int kl = 2 * K0 - 2;   // next advance takes plane kl + 1
+    int kb = 2 * K0;       // next residual plane
+    A xq[kPre], hq[kPre], bq[kPre];
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        load_x(kl + 1 + q, xq[q], hq[q]);
+        bq[q] = load_b(kb + q);
+    }
     auto advance = [&]() {
         ++kl;
-        const bool live = kl >= 0 && kl < nz && !a.x_zero;
-        const A xc = (in && live) ? static_cast<A>(ldv(x + kl * pl + c2)) : A(0);
+        const A xc = xq[0];
         tile[cc] = xc;
-        if (hy >= 0) tile[hy * (kRTX + 2) + hx] = (hin && live) ? static_cast<A>(ldv(x + kl * pl + hc2)) : A(0);
+        if (hy >= 0) tile[hy * (kRTX + 2) + hx] = hq[0];
+#pragma unroll
+        for (int q = 0; q + 1 < kPre; ++q) {
+            xq[q] = xq[q + 1];
+            hq[q] = hq[q + 1];
+        }
+        load_x(kl + kPre, xq[kPre - 1], hq[kPre - 1]);
         __syncthreads();
         const A t2 = cx * (A(2) * xc - tile[cc - 1] - tile[cc + 1]) +
                      cy * (A(2) * xc - tile[cc - (kRTX + 2)] - tile[cc + (kRTX + 2)]);
@@ -445,10 +469,13 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
         xw0 = xw1; xw1 = xw2; xw2 = xc;
         tw0 = tw1; tw1 = tw2; tw2 = t2;
     };
-    // residual of fine plane k (0 <= k < nz); needs planes k-1, k, k+1 loaded
+    // residual of fine plane k = kb (0 <= k < nz); needs planes k-1, k, k+1 loaded
     auto resid = [&](int k) {
         while (kl < k + 1) advance();
-        A v = in ? static_cast<A>(ldv(b + k * pl + c2)) : A(0);
+        A v = bq[0];
+#pragma unroll
+        for (int q = 0; q + 1 < kPre; ++q) bq[q] = bq[q + 1];
+        bq[kPre - 1] = load_b(++kb + kPre - 1);
         const PlaneCoef<A> ck = a.pc[k];
         v -= ck.ca * tw1 + ck.cb * xw1;
         if (k > 0) {
