@@ -842,10 +842,24 @@ __global__ __launch_bounds__(256) void k2_chain_grp(const GroupEntry *tab, int n
     k2_chain_body<T, A>(*a, blk);
 }
 
+// Window planes per thread (4 rows of threads) of 3D chain level l for a fine
+// run of 32 planes: the windows hold at most 17, 9, 5 and then 3 planes
+// (any level sizes), so 5, 3, 2 and then 1 per thread.
+constexpr int kChain3Pre = 8;   // chain levels whose reads are issued up front
+__host__ __device__ constexpr int chain3_rows(int l) { return l == 1 ? 5 : l == 2 ? 3 : l == 3 ? 2 : 1; }
+__host__ __device__ constexpr int chain3_off(int l)
+{
+    int o = 0;
+    for (int m = 1; m < l; ++m) o += chain3_rows(m);
+    return o;
+}
+static_assert(kChainRun == 32, "chain3_rows assumes runs of 32 fine planes");
+
 template <typename T, typename A>
 __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const Blk &blk)
 {
     __shared__ A vs[2][kChainWin * kChainCols];
+    constexpr int kRows0 = kChainRun / 4;       // fine planes per thread
     const long long pl = static_cast<long long>(a.nx) * a.ny;
     const int ncol = static_cast<int>((pl + kChainCols - 1) / kChainCols);
     const int ct = blk.x % ncol;
@@ -859,32 +873,63 @@ __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const B
         for (int m = 0; m < l; ++m) wv = coarser(wv, a.nz[m + 1]);
         return wv;
     };
-    int cur = 0;
-    {
-        const int l = a.L;
+    auto level_row = [&](int l, const Win &wl, int kk) -> A {
+        const T *xl = a.x[l] + r * a.rs[l];
+        return kk <= wl.hi && c < pl ? static_cast<A>(ldv(xl + kk * pl + c)) : A(0);
+    };
+    // every global read of chain levels 1..kChainPre and of the fine run,
+    // issued before the first barrier
+    A pre[chain3_off(kChain3Pre + 1)];
+#pragma unroll
+    for (int l = 1; l <= kChain3Pre; ++l) {
+        if (l > a.L) break;
         const Win wl = win(l);
-        const T *xl = a.x[l] + r * a.rs[l];
-        for (int kk = wl.lo + row0; kk <= wl.hi; kk += 4)
-            vs[cur][(kk - wl.lo) * kChainCols + col] = c < pl ? static_cast<A>(ldv(xl + kk * pl + c)) : A(0);
-        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < chain3_rows(l); ++t) pre[chain3_off(l) + t] = level_row(l, wl, wl.lo + row0 + 4 * t);
     }
-    for (int l = a.L - 1; l >= 1; --l) {
-        const Win wl = win(l), wc = win(l + 1);
-        const T *xl = a.x[l] + r * a.rs[l];
-        for (int kk = wl.lo + row0; kk <= wl.hi; kk += 4) {
-            A s = c < pl ? static_cast<A>(ldv(xl + kk * pl + c)) : A(0);
-            s += prolong_point(vs[cur], wc, kk, a.nz[l + 1], col);
-            vs[cur ^ 1][(kk - wl.lo) * kChainCols + col] = s;
+    T *x0 = a.x[0] + r * a.rs[0];
+    A xf[kRows0];
+#pragma unroll
+    for (int t = 0; t < kRows0; ++t) {
+        const int kk = w0.lo + row0 + 4 * t;
+        xf[t] = kk <= w0.hi && c < pl ? static_cast<A>(ldv(x0 + kk * pl + c)) : A(0);
+    }
+    int cur = 0;
+    bool first = true;   // the coarsest level is stored as it is
+    auto step = [&](int l, int nrows, auto &&xval) {
+        const Win wl = win(l);
+        if (first) {
+            for (int t = 0; t < nrows; ++t) {
+                const int kk = wl.lo + row0 + 4 * t;
+                if (kk <= wl.hi) vs[cur][(kk - wl.lo) * kChainCols + col] = xval(t, kk, wl);
+            }
+            first = false;
+        } else {
+            const Win wc = win(l + 1);
+            for (int t = 0; t < nrows; ++t) {
+                const int kk = wl.lo + row0 + 4 * t;
+                if (kk > wl.hi) break;
+                const A s = xval(t, kk, wl) + prolong_point(vs[cur], wc, kk, a.nz[l + 1], col);
+                vs[cur ^ 1][(kk - wl.lo) * kChainCols + col] = s;
+            }
+            cur ^= 1;
         }
-        cur ^= 1;
         __syncthreads();
+    };
+    for (int l = a.L; l > kChain3Pre; --l)
+        step(l, kChainWin / 4, [&](int, int kk, const Win &wl) { return level_row(l, wl, kk); });
+#pragma unroll
+    for (int l = kChain3Pre; l >= 1; --l) {
+        if (l > a.L) continue;
+        step(l, chain3_rows(l), [&](int t, int, const Win &) { return pre[chain3_off(l) + t]; });
     }
     if (c >= pl) return;
     const Win wc = win(1);
-    T *x0 = a.x[0] + r * a.rs[0];
-    for (int kk = w0.lo + row0; kk <= w0.hi; kk += 4) {
-        T *o = x0 + kk * pl + c;
-        stv(o, static_cast<A>(ldv(o)) + prolong_point(vs[cur], wc, kk, a.nz[1], col));
+#pragma unroll
+    for (int t = 0; t < kRows0; ++t) {
+        const int kk = w0.lo + row0 + 4 * t;
+        if (kk > w0.hi) break;
+        stv(x0 + kk * pl + c, xf[t] + prolong_point(vs[cur], wc, kk, a.nz[1], col));
     }
 }
 
