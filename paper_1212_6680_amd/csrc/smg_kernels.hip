@@ -399,13 +399,14 @@ __global__ void k_convert_out(const T *src, long long lds, double *dst, long lon
 // and a window of three planes (x and T2 x) in registers feeds the 15-point
 // residuals r_k = b_k - C_k x_k - U_{k-1} x_{k-1} - U_k x_{k+1}, which are
 // combined into b_c[K] = 1/2 r_{2K} + r_{2K+1} + 1/2 r_{2K+2} as the march
-// passes.  x and b are read about once, a few planes ahead of their use.
+// passes.  x and b are read about once, a few planes ahead of their use; two
+// LDS tiles alternate, so each plane takes one barrier.
 constexpr int kRTX = 64, kRTY = 8, kRThreads = kRTX * kRTY;
 
 template <typename T, typename A>
 __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A> &a, const Blk &blk)
 {
-    __shared__ A tile[(kRTY + 2) * (kRTX + 2)];
+    __shared__ A tiles[2][(kRTY + 2) * (kRTX + 2)];   // alternate planes: one barrier per plane
     const int tx = threadIdx.x % kRTX, ty = threadIdx.x / kRTX;
     const int i = blk.x * kRTX + tx, j = blk.y * kRTY + ty;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -451,9 +452,12 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
         load_x(kl + 1 + q, xq[q], hq[q]);
         bq[q] = load_b(kb + q);
     }
+    int buf = 0;
     auto advance = [&]() {
         ++kl;
         const A xc = xq[0];
+        A *tile = tiles[buf];
+        buf ^= 1;
         tile[cc] = xc;
         if (hy >= 0) tile[hy * (kRTX + 2) + hx] = hq[0];
 #pragma unroll
@@ -462,10 +466,11 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
             hq[q] = hq[q + 1];
         }
         load_x(kl + kPre, xq[kPre - 1], hq[kPre - 1]);
+        // a tile is rewritten two planes later, after the next plane's barrier:
+        // every read of it is done by then
         __syncthreads();
         const A t2 = cx * (A(2) * xc - tile[cc - 1] - tile[cc + 1]) +
                      cy * (A(2) * xc - tile[cc - (kRTX + 2)] - tile[cc + (kRTX + 2)]);
-        __syncthreads();
         xw0 = xw1; xw1 = xw2; xw2 = xc;
         tw0 = tw1; tw1 = tw2; tw2 = t2;
     };
