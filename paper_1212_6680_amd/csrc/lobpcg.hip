@@ -11,6 +11,7 @@
 // The only dense contractions are the tall-skinny Gram products S^T Y and
 // the block updates S C, which run on FP64 MFMA (v_mfma_f64_16x16x4f64);
 // the k x k (k <= 3m) Cholesky and eigen-decompositions run on the host.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -38,72 +39,113 @@ constexpr int kLdsPad = 4;  // LDS row padding (doubles)
 // lane j + 16k, D[i][j] in lane j + 16*(i%4), element i/4.
 constexpr int kGT = 128;    // Gram output tile edge
 
+// Gram slices (blocks along N per output tile): about 1024 blocks in all,
+// two rounds of two resident blocks per CU
+inline int gram_slices(int tiles) { return std::max(1, 1024 / std::max(1, tiles)); }
+
 __global__ __launch_bounds__(256) void k_gram_partial(const double *U, long long ldu, int p, const double *V,
                                                       long long ldv, int q, long long n, long long slice,
-                                                      double *part)
+                                                      double *part, int sym)
 {
-    __shared__ double Us[kK][kGT + kLdsPad];
-    __shared__ double Vs[kK][kGT + kLdsPad];
+    // sym: the product is symmetric (p == q); tiles below the diagonal are
+    // left out and read mirrored by the reduction
+    if (sym && blockIdx.x > blockIdx.y) return;
+    constexpr int TILE = kGT;
+    constexpr int RB = TILE / 64;      // 16-row MFMA blocks per wave (4 waves)
+    constexpr int CB = TILE / 16;      // 16-column MFMA blocks
+    constexpr int R = TILE / 16;       // values per thread per slice and operand
+    // two LDS stages: the next slice is read into registers while the MFMAs
+    // run on this one, then stored into the other stage (one barrier a slice)
+    __shared__ double Us[2][kK][TILE + kLdsPad];
+    __shared__ double Vs[2][kK][TILE + kLdsPad];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int i0 = blockIdx.x * kGT, j0 = blockIdx.y * kGT;
+    const int i0 = blockIdx.x * TILE, j0 = blockIdx.y * TILE;
     const long long n_beg = static_cast<long long>(blockIdx.z) * slice;
     const long long n_end = n_beg + slice < n ? n_beg + slice : n;
-    v4d acc[2][8];
+    v4d acc[RB][CB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RB; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] = v4d{0, 0, 0, 0};
-    // 16 x 16 blocks inside p x q only (the tile is padded to 128)
-    const bool in0 = i0 + 32 * w < p, in1 = i0 + 32 * w + 16 < p;
+        for (int b = 0; b < CB; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+    // 16 x 16 blocks inside p x q only (the tile is padded)
+    bool in[RB];
+#pragma unroll
+    for (int a = 0; a < RB; ++a) in[a] = i0 + 16 * (RB * w + a) < p;
     const int jn = (q - j0 + 15) / 16;
-    for (long long n0 = n_beg; n0 < n_end; n0 += kK) {
-        // stage 16 rows of 128 columns of U and V: thread e reads row e%16 of column e/16
+    // thread e of a slice holds row e % 16 of tile column e / 16
+    double ru[R], rv[R];
+    auto fetch = [&](long long n0) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < R; ++r) {
             const int e = tid + 256 * r;
             const int ii = e & 15, col = e >> 4;
             const long long nn = n0 + ii;
-            const bool in = nn < n_end;
-            Us[ii][col] = (in && i0 + col < p) ? U[nn + (i0 + col) * ldu] : 0.0;
-            Vs[ii][col] = (in && j0 + col < q) ? V[nn + (j0 + col) * ldv] : 0.0;
+            const bool inn = nn < n_end;
+            ru[r] = (inn && i0 + col < p) ? U[nn + (i0 + col) * ldu] : 0.0;
+            rv[r] = (inn && j0 + col < q) ? V[nn + (j0 + col) * ldv] : 0.0;
         }
-        __syncthreads();
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = tid + 256 * r;
+            Us[st][e & 15][e >> 4] = ru[r];
+            Vs[st][e & 15][e >> 4] = rv[r];
+        }
+    };
+    if (n_beg < n_end) {
+        fetch(n_beg);
+        stash(0);
+    }
+    __syncthreads();
+    int st = 0;
+    for (long long n0 = n_beg; n0 < n_end; n0 += kK) {
+        const bool more = n0 + kK < n_end;
+        if (more) fetch(n0 + kK);
 #pragma unroll
         for (int kk = 0; kk < kK / 4; ++kk) {
             const int kr = 4 * kk + (lane >> 4);
-            const double a0 = Us[kr][32 * w + (lane & 15)];
-            const double a1 = Us[kr][32 * w + 16 + (lane & 15)];
+            double a[RB];
 #pragma unroll
-            for (int jt = 0; jt < 8; ++jt) {
+            for (int ra = 0; ra < RB; ++ra) a[ra] = Us[st][kr][16 * (RB * w + ra) + (lane & 15)];
+#pragma unroll
+            for (int jt = 0; jt < CB; ++jt) {
                 if (jt >= jn) break;            // 16-column blocks past q
-                const double b = Vs[kr][16 * jt + (lane & 15)];
-                if (in0) acc[0][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][jt], 0, 0, 0);
-                if (in1) acc[1][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][jt], 0, 0, 0);
+                const double b = Vs[st][kr][16 * jt + (lane & 15)];
+#pragma unroll
+                for (int ra = 0; ra < RB; ++ra)
+                    if (in[ra]) acc[ra][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ra], b, acc[ra][jt], 0, 0, 0);
             }
         }
+        // the other stage was last read before the previous barrier
+        if (more) stash(st ^ 1);
         __syncthreads();
+        st ^= 1;
     }
     double *out = part + static_cast<long long>(blockIdx.z) * p * q;
 #pragma unroll
-    for (int it = 0; it < 2; ++it)
+    for (int ra = 0; ra < RB; ++ra)
 #pragma unroll
-        for (int jt = 0; jt < 8; ++jt) {
+        for (int jt = 0; jt < CB; ++jt) {
             const int j = j0 + 16 * jt + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + 32 * w + 16 * it + 4 * r + (lane >> 4);
-                if (i < p && j < q) out[static_cast<long long>(i) * q + j] = acc[it][jt][r];
+                const int i = i0 + 16 * (RB * w + ra) + 4 * r + (lane >> 4);
+                if (i < p && j < q) out[static_cast<long long>(i) * q + j] = acc[ra][jt][r];
             }
         }
 }
 
-// G[i][j] = sum_z part[z][i][j] in a fixed order (deterministic).
-__global__ void k_gram_reduce(const double *part, int nz, int pq, double *G)
+// G[i][j] = sum_z part[z][i][j] in a fixed order (deterministic); with sym,
+// entries of tiles below the diagonal come from the mirrored entry.
+__global__ void k_gram_reduce(const double *part, int nz, int p, int q, int tile, int sym, double *G)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= pq) return;
+    if (e >= p * q) return;
+    const int i = e / q, j = e % q;
+    const int src = sym && i / tile > j / tile ? j * q + i : e;
     double s = 0.0;
-    for (int z = 0; z < nz; ++z) s += part[static_cast<long long>(z) * pq + e];
+    for (int z = 0; z < nz; ++z) s += part[static_cast<long long>(z) * p * q + src];
     G[e] = s;
 }
 
@@ -240,9 +282,8 @@ LobLayout lob_layout(size_t N, int m)
     L.P = take(N * m * 8);
     L.AP = take(N * m * 8);
     L.R = take(N * m * 8);
-    const int tiles = static_cast<int>(((k3 + kT - 1) / kT) * ((k3 + kT - 1) / kT));
-    long long ns = 4096 / tiles;
-    ns = ns < 64 ? 64 : ns;
+    // enough partial products for any product taken (one output tile at least)
+    long long ns = gram_slices(1);
     const long long maxs = static_cast<long long>((N + 1023) / 1024);
     if (ns > maxs) ns = maxs < 1 ? 1 : maxs;
     L.nslices_gram = static_cast<int>(ns);
@@ -270,17 +311,28 @@ struct Lob {
 
     bool ok() { return hipGetLastError() == hipSuccess; }
 
-    // host G (p x q row-major) = U^T V
-    bool gram(const double *U, int p, const double *V, int q, std::vector<double> &G)
+    // device G (p x q row-major) = U^T V; sym: the product is symmetric (p == q)
+    void gram_launch(const double *U, int p, const double *V, int q, bool sym)
     {
-        const long long slice = (static_cast<long long>(N) + L.nslices_gram - 1) / L.nslices_gram;
+        const int s = sym && p == q ? 1 : 0;
+        const int tp = nblk(p, kGT), tq = nblk(q, kGT);
+        // slices by the full tile grid: the diagonal tiles bound the time, and
+        // more, shorter slices only add partial products
+        const long long want = std::min<long long>(gram_slices(tp * tq), L.nslices_gram);
+        const long long slice = (static_cast<long long>(N) + want - 1) / want;
         const long long sl = (slice + kK - 1) / kK * kK;
         const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
-        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(p, kGT), nblk(q, kGT), nz), dim3(256), 0, st, U,
-                           static_cast<long long>(N), p, V, static_cast<long long>(N), q,
-                           static_cast<long long>(N), sl, at<double>(L.part));
+        hipLaunchKernelGGL(k_gram_partial, dim3(tp, tq, nz), dim3(256), 0, st, U, static_cast<long long>(N), p, V,
+                           static_cast<long long>(N), q, static_cast<long long>(N), sl, at<double>(L.part), s);
         hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 256)), dim3(256), 0, st,
-                           at<double>(L.part), nz, p * q, at<double>(L.G));
+                           at<double>(L.part), nz, p, q, kGT, s, at<double>(L.G));
+    }
+
+    // host G (p x q row-major) = U^T V (every product taken here is symmetric:
+    // S^T S and S^T A S)
+    bool gram(const double *U, int p, const double *V, int q, std::vector<double> &G)
+    {
+        gram_launch(U, p, V, q, true);
         G.resize(static_cast<size_t>(p) * q);
         if (hipMemcpyAsync(G.data(), at<double>(L.G), G.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
             return false;
@@ -400,16 +452,7 @@ int lobpcg_profile_gram(smg_handle *h, int32_t m, int32_t k, void *ws, size_t ws
     hipStream_t st = lb.st;
     double *S = lb.at<double>(lb.L.S);
     launch_fill(S, 1.0 / 1024.0, N * static_cast<size_t>(k), st);
-    const long long slice = (static_cast<long long>(N) + lb.L.nslices_gram - 1) / lb.L.nslices_gram;
-    const long long sl = (slice + kK - 1) / kK * kK;
-    const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
-    auto one = [&]() {
-        hipLaunchKernelGGL(k_gram_partial, dim3(nblk(k, kGT), nblk(k, kGT), nz), dim3(256), 0, st, S,
-                           static_cast<long long>(N), k, S, static_cast<long long>(N), k, static_cast<long long>(N),
-                           sl, lb.at<double>(lb.L.part));
-        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(k) * k, 256)), dim3(256), 0, st,
-                           lb.at<double>(lb.L.part), nz, k * k, lb.at<double>(lb.L.G));
-    };
+    auto one = [&]() { lb.gram_launch(S, k, S, k, true); };
     one();   // warm-up
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SMG_EHIP;
