@@ -156,37 +156,57 @@ __global__ void k_gram_reduce(const double *part, int nz, int p, int q, int tile
 __global__ __launch_bounds__(256) void k_block_update(const double *U, long long ldu, int k, const double *C, int mo,
                                                       double *Y, long long ldy, long long n)
 {
-    __shared__ double Ut[kK][kT + kLdsPad];
-    __shared__ double Ct[kK][kT + kLdsPad];
+    // two LDS stages: the next 16 rows of C and U are read into registers
+    // while the MFMAs run on these (one barrier per step)
+    __shared__ double Ut[2][kK][kT + kLdsPad];
+    __shared__ double Ct[2][kK][kT + kLdsPad];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const long long n0 = static_cast<long long>(blockIdx.x) * kT;
     const int j0 = blockIdx.y * kT;
     const int jn = (mo - j0 + 15) / 16;
     v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    for (int i0 = 0; i0 < k; i0 += kK) {
-        // stage U[n0 .. n0+63][i0 .. i0+15] as Ut[i][n] and C[i0..][j0..j0+63] as Ct[i][j]
+    // U[n0 .. n0+63][i0 .. i0+15] as Ut[i][n] and C[i0..][j0..j0+63] as Ct[i][j]
+    double ru[4], rc[4];
+    auto fetch = [&](int i0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int e = tid + 256 * r;         // 0 .. 1023
-            const int ii = e >> 6, nn = e & 63;  // Ut: 16 x 64
+            const int ii = e >> 6, nn = e & 63;  // 16 x 64
             const long long ng = n0 + nn;
-            Ut[ii][nn] = (i0 + ii < k && ng < n) ? U[ng + (i0 + ii) * ldu] : 0.0;
-            const int jj = e & 63;
-            Ct[ii][jj] = (i0 + ii < k && j0 + jj < mo) ? C[static_cast<long long>(i0 + ii) * mo + j0 + jj] : 0.0;
+            ru[r] = (i0 + ii < k && ng < n) ? U[ng + (i0 + ii) * ldu] : 0.0;
+            rc[r] = (i0 + ii < k && j0 + nn < mo) ? C[static_cast<long long>(i0 + ii) * mo + j0 + nn] : 0.0;
         }
-        __syncthreads();
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r;
+            Ut[st][e >> 6][e & 63] = ru[r];
+            Ct[st][e >> 6][e & 63] = rc[r];
+        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    int st = 0;
+    for (int i0 = 0; i0 < k; i0 += kK) {
+        const bool more = i0 + kK < k;
+        if (more) fetch(i0 + kK);
 #pragma unroll
         for (int kk = 0; kk < kK / 4; ++kk) {
             const int kr = 4 * kk + (lane >> 4);
-            const double b = Ut[kr][16 * w + (lane & 15)];
+            const double b = Ut[st][kr][16 * w + (lane & 15)];
 #pragma unroll
             for (int jt = 0; jt < 4; ++jt) {
                 if (jt >= jn) break;
-                const double a = Ct[kr][16 * jt + (lane & 15)];
+                const double a = Ct[st][kr][16 * jt + (lane & 15)];
                 acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
             }
         }
+        // the other stage was last read before the previous barrier
+        if (more) stash(st ^ 1);
         __syncthreads();
+        st ^= 1;
     }
     const long long nn = n0 + 16 * w + (lane & 15);
     if (nn >= n) return;
