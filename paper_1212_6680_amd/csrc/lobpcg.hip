@@ -136,6 +136,113 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double *U, long long
         }
 }
 
+// Symmetric Gram products of narrow blocks (k <= kTriMax) without tiles: each
+// block takes a slice of rows and ALL 16 x 16 output blocks on or above the
+// diagonal (nb (nb + 1) / 2 of them, nb = ceil(k / 16)), dealt round-robin to
+// its 8 waves, so every block does the same work and no MFMA is spent on
+// padding beyond the last 16-block.  Slices of 16 rows (8 when U != V, to keep
+// both operands in the same LDS) are staged in two LDS stages with the next
+// slice read into registers meanwhile.  Writes part[z][i][j] for the upper
+// blocks only (the reduction mirrors).
+constexpr int kTriMax = 224;                  // 14 blocks of 16
+constexpr int kTriBlocks = 14 * 15 / 2;       // 105 output blocks at most
+constexpr int kTriWaves = 8;                  // waves per block (two per SIMD)
+constexpr int kTriPerWave = (kTriBlocks + kTriWaves - 1) / kTriWaves;
+constexpr int kTriLd = kTriMax + kLdsPad;
+
+template <bool SAME>
+__global__ __launch_bounds__(64 * kTriWaves) void k_gram_tri(const double *U, const double *V, long long ld, int k, long long n,
+                                                  long long slice, double *part)
+{
+    constexpr int KS = SAME ? 16 : 8;                    // rows per stage
+    constexpr int NT = 64 * kTriWaves;
+    constexpr int R = (KS * kTriMax + NT - 1) / NT;      // staged values per thread and operand
+    // stages: U in Ls[0], Ls[1]; V (when it differs) in Ls[2], Ls[3]
+    __shared__ double Ls[SAME ? 2 : 4][KS][kTriLd];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nb = (k + 15) / 16, T = nb * (nb + 1) / 2;
+    const long long n_beg = static_cast<long long>(blockIdx.x) * slice;
+    const long long n_end = n_beg + slice < n ? n_beg + slice : n;
+    // this wave's output blocks: t = w, w + 8, ... in row-major order of the
+    // upper triangle (uniform values)
+    int bi[kTriPerWave], bj[kTriPerWave];
+#pragma unroll
+    for (int b = 0; b < kTriPerWave; ++b) {
+        const int t = w + kTriWaves * b;
+        int i = 0, rem = t;
+        while (i < nb && rem >= nb - i) {
+            rem -= nb - i;
+            ++i;
+        }
+        bi[b] = t < T ? i : -1;
+        bj[b] = t < T ? i + rem : -1;
+    }
+    v4d acc[kTriPerWave];
+#pragma unroll
+    for (int b = 0; b < kTriPerWave; ++b) acc[b] = v4d{0, 0, 0, 0};
+    const int kp = nb * 16;   // staged columns (zero past k)
+    double ru[R], rv[SAME ? 1 : R];
+    auto fetch = [&](long long n0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = tid + NT * r;
+            const int ii = e % KS, col = e / KS;
+            const long long nn = n0 + ii;
+            const bool in = col < k && nn < n_end;
+            ru[r] = in ? U[nn + col * ld] : 0.0;
+            if constexpr (!SAME) rv[r] = in ? V[nn + col * ld] : 0.0;
+        }
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = tid + NT * r;
+            const int ii = e % KS, col = e / KS;
+            if (col < kp) {
+                Ls[st][ii][col] = ru[r];
+                if constexpr (!SAME) Ls[2 + st][ii][col] = rv[r];
+            }
+        }
+    };
+    if (n_beg < n_end) {
+        fetch(n_beg);
+        stash(0);
+    }
+    __syncthreads();
+    int st = 0;
+    for (long long n0 = n_beg; n0 < n_end; n0 += KS) {
+        const bool more = n0 + KS < n_end;
+        if (more) fetch(n0 + KS);
+        const double(*Ua)[kTriLd] = Ls[st];
+        const double(*Vb)[kTriLd] = Ls[SAME ? st : 2 + st];
+#pragma unroll
+        for (int kk = 0; kk < KS / 4; ++kk) {
+            const int kr = 4 * kk + (lane >> 4);
+#pragma unroll
+            for (int b = 0; b < kTriPerWave; ++b) {
+                if (bi[b] < 0) break;
+                const double a = Ua[kr][16 * bi[b] + (lane & 15)];
+                const double v = Vb[kr][16 * bj[b] + (lane & 15)];
+                acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v, acc[b], 0, 0, 0);
+            }
+        }
+        if (more) stash(st ^ 1);
+        __syncthreads();
+        st ^= 1;
+    }
+    double *out = part + static_cast<long long>(blockIdx.x) * k * k;
+#pragma unroll
+    for (int b = 0; b < kTriPerWave; ++b) {
+        if (bi[b] < 0) break;
+        const int j = 16 * bj[b] + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * bi[b] + 4 * r + (lane >> 4);
+            if (i < k && j < k) out[static_cast<long long>(i) * k + j] = acc[b][r];
+        }
+    }
+}
+
 // G[i][j] = sum_z part[z][i][j] in a fixed order (deterministic); with sym,
 // entries of tiles below the diagonal come from the mirrored entry.
 __global__ void k_gram_reduce(const double *part, int nz, int p, int q, int tile, int sym, double *G)
@@ -335,6 +442,21 @@ struct Lob {
     void gram_launch(const double *U, int p, const double *V, int q, bool sym)
     {
         const int s = sym && p == q ? 1 : 0;
+        if (s && p <= kTriMax) {   // narrow: all upper 16-blocks per block, slices of N
+            const long long want = std::min<long long>(256, L.nslices_gram);   // one block per CU
+            const long long slice = (static_cast<long long>(N) + want - 1) / want;
+            const long long sl = (slice + 15) / 16 * 16;
+            const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
+            if (U == V)
+                hipLaunchKernelGGL(k_gram_tri<true>, dim3(nz), dim3(64 * kTriWaves), 0, st, U, V, static_cast<long long>(N), p,
+                                   static_cast<long long>(N), sl, at<double>(L.part));
+            else
+                hipLaunchKernelGGL(k_gram_tri<false>, dim3(nz), dim3(64 * kTriWaves), 0, st, U, V, static_cast<long long>(N), p,
+                                   static_cast<long long>(N), sl, at<double>(L.part));
+            hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 256)), dim3(256), 0, st,
+                               at<double>(L.part), nz, p, q, 16, 1, at<double>(L.G));
+            return;
+        }
         const int tp = nblk(p, kGT), tq = nblk(q, kGT);
         // slices by the full tile grid: the diagonal tiles bound the time, and
         // more, shorter slices only add partial products
