@@ -82,6 +82,19 @@ def other_configs(torch, dev, learned=True):
     from paper_1212_6680_amd.smg import SMG
 
     res = lobpcg_configs(torch, dev)
+    res.update(precision_configs(torch, dev))
+    res["batch_48_uneven"] = batch_config(torch, dev)
+    if learned:
+        res["learned_256"] = learned_config(torch, dev)
+    return res
+
+
+def precision_configs(torch, dev):
+    """FPCG at 384^3 with the SMG preconditioner in FP64, FP32 and BF16 storage."""
+    import synth
+    from paper_1212_6680_amd.smg import SMG
+
+    res = {}
     n = 384
     shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
     b = torch.from_numpy(synth.rhs(n, n, n, 5)).to(dev)
@@ -103,9 +116,6 @@ def other_configs(torch, dev, learned=True):
         del G
     del b, x, x64
     torch.cuda.empty_cache()
-    res["batch_48_uneven"] = batch_config(torch, dev)
-    if learned:
-        res["learned_256"] = learned_config(torch, dev)
     return res
 
 
@@ -261,7 +271,7 @@ def main():
                     help="skip the LOBPCG and mixed-precision workloads reported beside the headline")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for counter collection: a 512 MiB device copy, then one V-cycle")
-    ap.add_argument("--only", choices=["batch", "learned", "lobpcg"],
+    ap.add_argument("--only", choices=["batch", "learned", "lobpcg", "precision"],
                     help="run one of the other workloads alone and print its result (for profiling)")
     ap.add_argument("--learned-pairs", type=int, default=2000)
     ap.add_argument("--learned-steps", type=int, default=2000)
@@ -283,6 +293,8 @@ def main():
             out = batch_config(torch, dev)
         elif args.only == "learned":
             out = learned_config(torch, dev, args.learned_pairs, args.learned_steps)
+        elif args.only == "precision":
+            out = precision_configs(torch, dev)
         else:
             out = lobpcg_configs(torch, dev)
         print(json.dumps({"only": args.only, **out}))

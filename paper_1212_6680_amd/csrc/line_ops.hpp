@@ -239,11 +239,12 @@ template <typename T, int E>
 constexpr int chunk_align()
 {
     constexpr int cb = E * static_cast<int>(sizeof(T));
-    return cb % 16 == 0 ? 16 : cb % 8 == 0 ? 8 : 0;
+    return cb % 16 == 0 ? 16 : cb % 8 == 0 ? 8 : cb % 4 == 0 ? 4 : 0;
 }
 
 // A lane whose E points all lie inside the line reads them as one aligned
-// chunk (16-byte loads for FP64 with E = 2 or 4) when the row is aligned;
+// chunk (16-byte loads for FP64 with E = 2 or 4, whole dwords for BF16) when
+// the row is aligned;
 // the lane holding the end of a ragged line goes point by point.
 template <typename T, typename A, int E>
 __device__ inline void gload(A (&v)[E], const T *row, int nx, int lane)

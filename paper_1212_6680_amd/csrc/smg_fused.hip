@@ -44,7 +44,11 @@ __device__ inline const LineCoef<A> *plane_lines(const PlaneCoef<A> *pc, int k, 
 // ---------------------------------------------------------------------------
 // k2_down: one pre-smoothing zebra sweep (F then C, zero initial guess) of a
 // strip of coarse lines [J0, J1), the strip's own lines of x, and the
-// restricted residual b_c[J] = 1/2 r_{2J} + r_{2J+1} + 1/2 r_{2J+2}.
+// restricted residual b_c[J] = 1/2 r_{2J} + r_{2J+1} + 1/2 r_{2J+2}.  After
+// such a sweep r_{2J+1} = 0 (the C line was solved against its final
+// neighbours) and r_j = -V_{j-1} x_{j-1} - V_j x_{j+1} on an F line (it was
+// solved with zero neighbours, so b_j - L_j x_j = 0): the restriction needs
+// the C lines only.  Equal to the explicit residual up to rounding.
 // LDS slot s holds fine line j = 2*J0 - 2 + s, s in [0, 2S+5).  The host
 // keeps S <= W - 3 so that every phase is one line per wave.
 // ---------------------------------------------------------------------------
@@ -73,20 +77,10 @@ __device__ __forceinline__ void k2_down_body(const Down2Args<T, A> &a, const Blk
     const int jf = f0 + 2 * w, jc = c0 + 2 * w, J = J0 + w;
     const bool hf = w < nf, hc = w < nc, hr = J < J1;
 
-    // every global read of the workgroup, issued up front (the residual rows
-    // of very wide FP64 lines only after the solves: registers)
-    constexpr bool kEarly = E * sizeof(A) <= 48;
-    A fb[E], cb[E], rb0[E], rb1[E], rb2[E];
-    auto load_rows = [&]() {
-        if (hr) {
-            gload<T, A, E>(rb0, bpl + static_cast<long long>(2 * J) * nx, nx, lane);
-            gload<T, A, E>(rb1, bpl + static_cast<long long>(2 * J + 1) * nx, nx, lane);
-            if (2 * J + 2 < ny) gload<T, A, E>(rb2, bpl + static_cast<long long>(2 * J + 2) * nx, nx, lane);
-        }
-    };
+    // every global read of the workgroup, issued up front
+    A fb[E], cb[E];
     if (hf) gload<T, A, E>(fb, bpl + static_cast<long long>(jf) * nx, nx, lane);
     if (hc) gload<T, A, E>(cb, bpl + static_cast<long long>(jc) * nx, nx, lane);
-    if constexpr (kEarly) load_rows();
     // F lines: x_j = L_j^{-1} b_j
     if (hf) {
         thomas<A, E>(fb, a.fac + static_cast<size_t>(lc[jf].fac) * nxp, lane);
@@ -118,34 +112,30 @@ __device__ __forceinline__ void k2_down_body(const Down2Args<T, A> &a, const Blk
             gstore<T, A, E>(xpl + static_cast<long long>(j) * nx, v, nx, lane);
         }
     }
-    // restricted residual of coarse line J
-    if constexpr (!kEarly) load_rows();
+    // restricted residual of coarse line J after one sweep from zero: the C
+    // lines' residuals are zero and an F line's is -V_{j-1} x_{j-1} - V_j x_{j+1}
     if (hr) {
-        A acc[E];
+        A acc[E], t[E], v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] = A(0);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int j = 2 * J + d;
+        for (int d = 0; d < 2; ++d) {
+            const int j = 2 * J + 2 * d;   // F lines 2J and 2J + 2
             if (j >= ny) break;
-            A f[E], v[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) f[e] = d == 0 ? rb0[e] : d == 1 ? rb1[e] : rb2[e];
-            const LineCoef<A> cj = lc[j];
-            sload<A, E>(v, xs + (j - base) * nxp, lane);
-            sub_op<A, E>(f, v, cj.la, cj.lb);
+            for (int e = 0; e < E; ++e) t[e] = A(0);
             if (j > 0) {
                 const LineCoef<A> cm = lc[j - 1];
                 sload<A, E>(v, xs + (j - 1 - base) * nxp, lane);
-                sub_op<A, E>(f, v, cm.va, cm.vb);
+                sub_op<A, E>(t, v, cm.va, cm.vb);
             }
             if (j + 1 < ny) {
+                const LineCoef<A> cj = lc[j];
                 sload<A, E>(v, xs + (j + 1 - base) * nxp, lane);
-                sub_op<A, E>(f, v, cj.va, cj.vb);
+                sub_op<A, E>(t, v, cj.va, cj.vb);
             }
-            const A wgt = d == 1 ? A(1) : A(0.5);
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] += wgt * f[e];
+            for (int e = 0; e < E; ++e) acc[e] += A(0.5) * t[e];
         }
         gstore<T, A, E>(a.bc + r * a.crs + p * a.cps + static_cast<long long>(J) * nx, acc, nx, lane);
     }
@@ -220,14 +210,6 @@ __device__ __forceinline__ void k2_down_reg_body(const Down2Args<T, A> &a, const
     if (has_p2) gload<T, A, E>(fp2, bpl + static_cast<long long>(j0 + 2) * nx, nx, lane);
     if (has_p3) gload<T, A, E>(cp3, bpl + static_cast<long long>(j0 + 3) * nx, nx, lane);
     if (has_p4) gload<T, A, E>(fp4, bpl + static_cast<long long>(j0 + 4) * nx, nx, lane);
-    // copies of b_j0, b_j0+1, b_j0+2 for the residual
-    A b0[E], b1[E], b2[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        b0[e] = f0[e];
-        b1[e] = cp1[e];
-        b2[e] = fp2[e];
-    }
     // interior lines share one Thomas table: plan it once
     const int fi = lc[j0].fac;
     LinePlan<A, E> plan;
@@ -260,32 +242,34 @@ __device__ __forceinline__ void k2_down_reg_body(const Down2Args<T, A> &a, const
     gstore<T, A, E>(xpl + static_cast<long long>(j0) * nx, f0, nx, lane);
     gstore<T, A, E>(xpl + static_cast<long long>(j0 + 1) * nx, cp1, nx, lane);
     if (J == a.nyc - 1 && has_p2) gstore<T, A, E>(xpl + static_cast<long long>(j0 + 2) * nx, fp2, nx, lane);
-    // r_j = b_j - L_j x_j - V_{j-1} x_{j-1} - V_j x_{j+1} for j = j0, j0+1, j0+2
+    // b_c[J] = 1/2 r_j0 + r_j0+1 + 1/2 r_j0+2 after one sweep from zero: the
+    // C line's residual is zero (just solved against its final neighbours)
+    // and an F line's is -V_{j-1} x_{j-1} - V_j x_{j+1} (b_j - L_j x_j = 0:
+    // it was solved with zero neighbours)
+    A acc[E], rf[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) rf[e] = A(0);
+    if (has_m2) {
+        const LineCoef<A> cm = lc[j0 - 1];
+        sub_op<A, E>(rf, cm1, cm.va, cm.vb);
+    }
     {
         const LineCoef<A> cj = lc[j0];
-        sub_op<A, E>(b0, f0, cj.la, cj.lb);
-        if (has_m2) {
-            const LineCoef<A> cm = lc[j0 - 1];
-            sub_op<A, E>(b0, cm1, cm.va, cm.vb);
-        }
-        sub_op<A, E>(b0, cp1, cj.va, cj.vb);
+        sub_op<A, E>(rf, cp1, cj.va, cj.vb);
     }
-    {
-        const LineCoef<A> cj = lc[j0 + 1], cm = lc[j0];
-        sub_op<A, E>(b1, cp1, cj.la, cj.lb);
-        sub_op<A, E>(b1, f0, cm.va, cm.vb);
-        if (has_p2) sub_op<A, E>(b1, fp2, cj.va, cj.vb);
-    }
-    A acc[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = A(0.5) * b0[e] + b1[e];
+    for (int e = 0; e < E; ++e) acc[e] = A(0.5) * rf[e];
     if (has_p2) {
-        const LineCoef<A> cj = lc[j0 + 2], cm = lc[j0 + 1];
-        sub_op<A, E>(b2, fp2, cj.la, cj.lb);
-        sub_op<A, E>(b2, cp1, cm.va, cm.vb);
-        if (has_p3) sub_op<A, E>(b2, cp3, cj.va, cj.vb);
 #pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] += A(0.5) * b2[e];
+        for (int e = 0; e < E; ++e) rf[e] = A(0);
+        const LineCoef<A> cm = lc[j0 + 1];
+        sub_op<A, E>(rf, cp1, cm.va, cm.vb);
+        if (has_p3) {
+            const LineCoef<A> cj = lc[j0 + 2];
+            sub_op<A, E>(rf, cp3, cj.va, cj.vb);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] += A(0.5) * rf[e];
     }
     gstore<T, A, E>(a.bc + r * a.crs + p * a.cps + static_cast<long long>(J) * nx, acc, nx, lane);
 }
@@ -380,8 +364,22 @@ __device__ __forceinline__ void k2_down_march_body(const Down2Args<T, A> &a, con
         for (int e = 0; e < E; ++e) d[e] = v[e];
     };
 
+    // b_c[J] = 1/2 (r_{2J} + r_{2J+2}) with the F-line residuals of one sweep
+    // from zero, r_j = -V_{j-1} x_{j-1} - V_j x_{j+1} (the C lines' are zero)
+    auto f_resid = [&](A (&rr)[E], int j, const A (&xl)[E], const A (&xr)[E]) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) rr[e] = A(0);
+        if (j > 0) {
+            const LineCoef<A> cm = lc[j - 1];
+            sub_op<A, E>(rr, xl, cm.va, cm.vb);
+        }
+        if (j + 1 < ny) {
+            const LineCoef<A> cj = lc[j];
+            sub_op<A, E>(rr, xr, cj.va, cj.vb);
+        }
+    };
     // start-up: x_{j0-2}, x_{j0-1} (first run: none), x_{j0}, x_{j0+1}, x_{j0+2}, r_{j0}
-    A xa[E], xc[E], xb[E], rp[E], b1[E], b2[E], n3[E], n4[E];
+    A xa[E], xc[E], xb[E], rp[E], n3[E], n4[E];
     {
         A fm2[E], cm1[E];
         zero(fm2);
@@ -399,47 +397,26 @@ __device__ __forceinline__ void k2_down_march_body(const Down2Args<T, A> &a, con
         if (j0 + 2 < ny) gload<T, A, E>(xb, bpl + static_cast<long long>(j0 + 2) * nx, nx, lane);
         if (j0 + 3 < ny) gload<T, A, E>(n3, bpl + static_cast<long long>(j0 + 3) * nx, nx, lane);
         if (j0 + 4 < ny) gload<T, A, E>(n4, bpl + static_cast<long long>(j0 + 4) * nx, nx, lane);
-        copy(rp, xa);
-        copy(b1, xc);
-        copy(b2, xb);
         if (has_m2) solve(fm2, j0 - 2);
         solve(xa, j0);
         if (j0 + 2 < ny) solve(xb, j0 + 2);
         if (has_m2) solve_c(cm1, j0 - 1, fm2, xa);
         solve_c(xc, j0 + 1, xa, xb);   // j0 + 1 < ny always (J0 < nyc)
-        const LineCoef<A> cj = lc[j0];
-        sub_op<A, E>(rp, xa, cj.la, cj.lb);
-        if (has_m2) {
-            const LineCoef<A> cm = lc[j0 - 1];
-            sub_op<A, E>(rp, cm1, cm.va, cm.vb);
-        }
-        sub_op<A, E>(rp, xc, cj.va, cj.vb);
+        f_resid(rp, j0, cm1, xc);
     }
     for (int J = J0; J < J1; ++J) {
-        // state: xa = x_j, xc = x_{j+1}, xb = x_{j+2}, rp = r_j, b1 = b_{j+1}, b2 = b_{j+2},
+        // state: xa = x_j, xc = x_{j+1}, xb = x_{j+2}, rp = r_j,
         // n3 = b_{j+3}, n4 = b_{j+4} (zero beyond the level)
         const int j = 2 * J;
         const bool h2 = j + 2 < ny, h3 = j + 3 < ny, h4 = j + 4 < ny;
-        A xe[E], xd[E], b3[E], b4[E];
+        A xe[E], xd[E];
         copy(xe, n3);
         copy(xd, n4);
-        copy(b3, n3);
-        copy(b4, n4);
         if (J + 1 < J1) {   // the next step's right-hand sides, one step ahead
             zero(n3);
             zero(n4);
             if (j + 5 < ny) gload<T, A, E>(n3, bpl + static_cast<long long>(j + 5) * nx, nx, lane);
             if (j + 6 < ny) gload<T, A, E>(n4, bpl + static_cast<long long>(j + 6) * nx, nx, lane);
-        }
-        // r_{j+1} (needs nothing new)
-        A acc[E];
-        {
-            const LineCoef<A> cj = lc[j + 1], cm = lc[j];
-            sub_op<A, E>(b1, xc, cj.la, cj.lb);
-            sub_op<A, E>(b1, xa, cm.va, cm.vb);
-            if (h2) sub_op<A, E>(b1, xb, cj.va, cj.vb);
-#pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] = A(0.5) * rp[e] + b1[e];
         }
         gstore<T, A, E>(xpl + static_cast<long long>(j) * nx, xa, nx, lane);
         gstore<T, A, E>(xpl + static_cast<long long>(j + 1) * nx, xc, nx, lane);
@@ -447,22 +424,18 @@ __device__ __forceinline__ void k2_down_march_body(const Down2Args<T, A> &a, con
         // x_{j+4}, x_{j+3}
         if (h4) solve(xd, j + 4);
         if (h3) solve_c(xe, j + 3, xb, xd);
-        // r_{j+2}
-        if (h2) {
-            const LineCoef<A> cj = lc[j + 2], cm = lc[j + 1];
-            sub_op<A, E>(b2, xb, cj.la, cj.lb);
-            sub_op<A, E>(b2, xc, cm.va, cm.vb);
-            if (h3) sub_op<A, E>(b2, xe, cj.va, cj.vb);
+        A acc[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] += A(0.5) * b2[e];
+        for (int e = 0; e < E; ++e) acc[e] = A(0.5) * rp[e];
+        if (h2) {
+            f_resid(rp, j + 2, xc, xe);   // r_{j+2}
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] += A(0.5) * rp[e];
         }
         gstore<T, A, E>(bcpl + static_cast<long long>(J) * nx, acc, nx, lane);
         copy(xa, xb);
         copy(xc, xe);
         copy(xb, xd);
-        copy(rp, b2);
-        copy(b1, b3);
-        copy(b2, b4);
     }
 }
 
@@ -573,6 +546,31 @@ __device__ __forceinline__ void k2_coarse_body(const Coarse2Args<T, A> &a, const
             A acc[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] = A(0);
+            if (a.ipre == 1) {
+                // after one sweep from zero the C lines' residuals are zero and
+                // an F line's is -V_{j-1} x_{j-1} - V_j x_{j+1}
+                for (int d = 0; d < 2; ++d) {
+                    const int j = 2 * J + 2 * d;
+                    if (j >= ny) break;
+                    A f[E], v[E];
+#pragma unroll
+                    for (int e = 0; e < E; ++e) f[e] = A(0);
+                    if (j > 0) {
+                        const LineCoef<A> cm = lc[j - 1];
+                        sload<A, E>(v, x + (j - 1) * nxp, lane);
+                        sub_op<A, E>(f, v, cm.va, cm.vb);
+                    }
+                    if (j + 1 < ny) {
+                        const LineCoef<A> cj = lc[j];
+                        sload<A, E>(v, x + (j + 1) * nxp, lane);
+                        sub_op<A, E>(f, v, cj.va, cj.vb);
+                    }
+#pragma unroll
+                    for (int e = 0; e < E; ++e) acc[e] += A(0.5) * f[e];
+                }
+                sstore<A, E>(bc + J * nxp, acc, lane);
+                continue;
+            }
             for (int d = 0; d < 3; ++d) {
                 const int j = 2 * J + d;
                 if (j >= ny) break;
