@@ -489,9 +489,120 @@ __device__ inline void lds_relax(A *xs, const A *bs, const LineCoef<A> *lc, cons
     }
 }
 
+// k2_coarse in down-only mode: levels l0 .. nlev-1 of the downward half of
+// the 2D cycle (one sweep from zero, no post-smoothing).  LDS holds the
+// current level's b and x only: after the C half-sweep a level's b is dead
+// (the restriction needs the C lines alone), so b_{l+1} overwrites it in
+// place.  Each solved line also goes to xl[l] for the prolongation chain,
+// which runs from the coarsest level in the next launch.
+template <typename T, typename A, int E>
+__device__ __forceinline__ void k2_coarse_down_body(const Coarse2Args<T, A> &a, const Blk &blk)
+{
+    extern __shared__ unsigned char smem_raw[];
+    A *sm = reinterpret_cast<A *>(smem_raw);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int p = blk.x % a.np, r = blk.x / a.np;
+    const int nx = a.nx, nxp = a.nxp;
+    const int k = p * a.kmul + a.koff;
+    const LineCoef<A> *lcp = plane_lines(a.pc, k, a.lc, a.lines_total);
+    const int n0 = a.ny2[a.l0];
+    int total = 0;
+    for (int l = a.l0; l < a.nlev; ++l) total += a.ny2[l];
+    A *xs = sm, *bs = sm + static_cast<size_t>(n0) * nxp;
+    LineCoef<A> *lcs = reinterpret_cast<LineCoef<A> *>(bs + static_cast<size_t>(n0) * nxp);
+    auto off = [&](int l) {
+        int o = 0;
+        for (int m = a.l0; m < l; ++m) o += a.ny2[m];
+        return o;
+    };
+    auto xrow = [&](int l, int j) {
+        const long long ps = static_cast<long long>(nx) * a.ny2[l];
+        return a.xl[l] + r * (a.P2 * ps) + p * ps + static_cast<long long>(j) * nx;
+    };
+    for (int i = threadIdx.x; i < total; i += blockDim.x) {
+        int l = a.l0, o = 0;
+        while (i >= o + a.ny2[l]) o += a.ny2[l++];
+        lcs[i] = lcp[a.lev_off[l] + (i - o)];
+    }
+    {
+        const T *bpl = a.b + r * a.brs + p * a.bps;
+        for (int j = w; j < n0; j += kW) {
+            A v[E];
+            gload<T, A, E>(v, bpl + static_cast<long long>(j) * nx, nx, lane);
+            sstore<A, E>(bs + j * nxp, v, lane);
+        }
+    }
+    __syncthreads();
+    for (int l = a.l0; l < a.nlev - 1; ++l) {
+        const int ny = a.ny2[l], nyc = a.ny2[l + 1];
+        const LineCoef<A> *lc = lcs + off(l);
+        // F lines from b alone, then C lines against them
+        for (int colour = 0; colour < 2; ++colour) {
+            const int n = colour == 0 ? (ny + 1) / 2 : ny / 2;
+            for (int t = w; t < n; t += kW) {
+                const int j = 2 * t + colour;
+                A f[E], v[E];
+                sload<A, E>(f, bs + j * nxp, lane);
+                if (colour == 1) {
+                    const LineCoef<A> cm = lc[j - 1];
+                    sload<A, E>(v, xs + (j - 1) * nxp, lane);
+                    sub_op<A, E>(f, v, cm.va, cm.vb);
+                    if (j + 1 < ny) {
+                        const LineCoef<A> cj = lc[j];
+                        sload<A, E>(v, xs + (j + 1) * nxp, lane);
+                        sub_op<A, E>(f, v, cj.va, cj.vb);
+                    }
+                }
+                thomas<A, E>(f, a.fac + static_cast<size_t>(lc[j].fac) * nxp, lane);
+                sstore<A, E>(xs + j * nxp, f, lane);
+                gstore<T, A, E>(xrow(l, j), f, nx, lane);
+            }
+            __syncthreads();
+        }
+        // b_{l+1}[J] = 1/2 (r_{2J} + r_{2J+2}), r_j = -V_{j-1} x_{j-1} - V_j x_{j+1}
+        for (int J = w; J < nyc; J += kW) {
+            A acc[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = A(0);
+            for (int d = 0; d < 2; ++d) {
+                const int j = 2 * J + 2 * d;
+                if (j >= ny) break;
+                A f[E], v[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) f[e] = A(0);
+                if (j > 0) {
+                    const LineCoef<A> cm = lc[j - 1];
+                    sload<A, E>(v, xs + (j - 1) * nxp, lane);
+                    sub_op<A, E>(f, v, cm.va, cm.vb);
+                }
+                if (j + 1 < ny) {
+                    const LineCoef<A> cj = lc[j];
+                    sload<A, E>(v, xs + (j + 1) * nxp, lane);
+                    sub_op<A, E>(f, v, cj.va, cj.vb);
+                }
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[e] += A(0.5) * f[e];
+            }
+            sstore<A, E>(bs + J * nxp, acc, lane);
+        }
+        __syncthreads();
+    }
+    if (w == 0) {   // the coarsest level: one line
+        const int l = a.nlev - 1;
+        A f[E];
+        sload<A, E>(f, bs, lane);
+        thomas<A, E>(f, a.fac + static_cast<size_t>(lcs[off(l)].fac) * nxp, lane);
+        gstore<T, A, E>(xrow(l, 0), f, nx, lane);
+    }
+}
+
 template <typename T, typename A, int E>
 __device__ __forceinline__ void k2_coarse_body(const Coarse2Args<T, A> &a, const Blk &blk)
 {
+    if (a.down_only) {
+        k2_coarse_down_body<T, A, E>(a, blk);
+        return;
+    }
     extern __shared__ unsigned char smem_raw[];
     A *sm = reinterpret_cast<A *>(smem_raw);
     const int lane = threadIdx.x & 63, w = wave_id();
@@ -729,12 +840,23 @@ __device__ inline A prolong_point(const A *vc, Win wc, int jj, int nc, int col)
     return s;
 }
 
+// Window lines (planes) per thread (4 rows of threads) of chain level l for a
+// fine run of 32: the windows hold at most 17, 9, 5 and then 3 lines (any
+// level sizes), so 5, 3, 2 and then 1 per thread.
+constexpr int kChainPre = 8;   // chain levels whose reads are issued up front
+__host__ __device__ constexpr int chain_rows(int l) { return l == 1 ? 5 : l == 2 ? 3 : l == 3 ? 2 : 1; }
+__host__ __device__ constexpr int chain_off(int l)
+{
+    int o = 0;
+    for (int m = 1; m < l; ++m) o += chain_rows(m);
+    return o;
+}
+static_assert(kChainRun == 32, "chain_rows assumes runs of 32 fine planes");
+
 template <typename T, typename A>
 __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const Blk &blk)
 {
     __shared__ A vs[2][kChainWin * kChainCols];
-    constexpr int kPreLev = 4;                  // chain levels whose reads are issued up front
-    constexpr int kRowsLev = kChainWin / 4;     // window lines per thread at a level >= 1
     constexpr int kRows0 = kChainRun / 4;       // fine lines per thread
     const int nx = a.nx;
     const int ncol = (nx + kChainCols - 1) / kChainCols;
@@ -758,17 +880,15 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
         const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
         return jj <= wl.hi && i < nx ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * nx + i)) : A(0);
     };
-    // every global read of the first kPreLev chain levels and of the fine
-    // run, issued before the first barrier (each would otherwise wait for
-    // the level above it)
-    A pre[kPreLev][kRowsLev];
+    // every global read of chain levels 1..kChainPre and of the fine run
+    // (x and the accumulated output), issued before the first barrier
+    A pre[chain_off(kChainPre + 1)];
 #pragma unroll
-    for (int q = 0; q < kPreLev; ++q) {
-        const int l = a.lc - q;
-        if (l < 1) break;
+    for (int l = 1; l <= kChainPre; ++l) {
+        if (l > a.lc) break;
         const Win wl = win(l);
 #pragma unroll
-        for (int t = 0; t < kRowsLev; ++t) pre[q][t] = level_row(l, wl, wl.lo + row0 + 4 * t);
+        for (int t = 0; t < chain_rows(l); ++t) pre[chain_off(l) + t] = level_row(l, wl, wl.lo + row0 + 4 * t);
     }
     const T *x0 = a.x0 + r * a.x0rs + p * a.x0ps;
     T *out = a.out + r * a.ors + p * a.ops;
@@ -784,36 +904,35 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
         }
     }
     int cur = 0;
-    {   // coarsest level of the chain: v = x_lc
-        const Win wl = win(a.lc);
-#pragma unroll
-        for (int t = 0; t < kRowsLev; ++t) {
-            const int jj = wl.lo + row0 + 4 * t;
-            if (jj <= wl.hi) vs[cur][(jj - wl.lo) * kChainCols + col] = pre[0][t];
+    bool first = true;   // the coarsest level is stored as it is
+    auto step = [&](int l, int nrows, auto &&xval) {
+        const Win wl = win(l);
+        if (first) {
+            for (int t = 0; t < nrows; ++t) {
+                const int jj = wl.lo + row0 + 4 * t;
+                if (jj <= wl.hi) vs[cur][(jj - wl.lo) * kChainCols + col] = xval(t, jj, wl);
+            }
+            first = false;
+        } else {
+            const Win wc = win(l + 1);
+            for (int t = 0; t < nrows; ++t) {
+                const int jj = wl.lo + row0 + 4 * t;
+                if (jj > wl.hi) break;
+                const A s = xval(t, jj, wl) + prolong_point(vs[cur], wc, jj, a.ny2[l + 1], col);
+                vs[cur ^ 1][(jj - wl.lo) * kChainCols + col] = s;
+            }
+            cur ^= 1;
         }
-        __syncthreads();
-    }
-    // v_l = x_l + P v_{l+1}
-    auto step = [&](int l, auto &&xval) {
-        const Win wl = win(l), wc = win(l + 1);
-#pragma unroll
-        for (int t = 0; t < kRowsLev; ++t) {
-            const int jj = wl.lo + row0 + 4 * t;
-            if (jj > wl.hi) break;
-            const A s = xval(t, jj, wl) + prolong_point(vs[cur], wc, jj, a.ny2[l + 1], col);
-            vs[cur ^ 1][(jj - wl.lo) * kChainCols + col] = s;
-        }
-        cur ^= 1;
         __syncthreads();
     };
+    for (int l = a.lc; l > kChainPre; --l)
+        step(l, kChainWin / 4, [&](int, int jj, const Win &wl) { return level_row(l, wl, jj); });
 #pragma unroll
-    for (int q = 1; q < kPreLev; ++q) {
-        const int l = a.lc - q;
-        if (l < 1) break;
-        step(l, [&](int t, int, const Win &) { return pre[q][t]; });
+    for (int l = kChainPre; l >= 1; --l) {
+        if (l > a.lc) continue;
+        step(l, chain_rows(l), [&](int t, int, const Win &) { return pre[chain_off(l) + t]; });
     }
-    for (int l = a.lc - kPreLev; l >= 1; --l) step(l, [&](int, int jj, const Win &wl) { return level_row(l, wl, jj); });
-    if (i >= nx) return;
+    if (i >= nx) return;   // after the last barrier
     const Win wc = win(1);
 #pragma unroll
     for (int t = 0; t < kRows0; ++t) {
@@ -840,18 +959,6 @@ __global__ __launch_bounds__(256) void k2_chain_grp(const GroupEntry *tab, int n
     k2_chain_body<T, A>(*a, blk);
 }
 
-// Window planes per thread (4 rows of threads) of 3D chain level l for a fine
-// run of 32 planes: the windows hold at most 17, 9, 5 and then 3 planes
-// (any level sizes), so 5, 3, 2 and then 1 per thread.
-constexpr int kChain3Pre = 8;   // chain levels whose reads are issued up front
-__host__ __device__ constexpr int chain3_rows(int l) { return l == 1 ? 5 : l == 2 ? 3 : l == 3 ? 2 : 1; }
-__host__ __device__ constexpr int chain3_off(int l)
-{
-    int o = 0;
-    for (int m = 1; m < l; ++m) o += chain3_rows(m);
-    return o;
-}
-static_assert(kChainRun == 32, "chain3_rows assumes runs of 32 fine planes");
 
 template <typename T, typename A>
 __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const Blk &blk)
@@ -877,13 +984,13 @@ __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const B
     };
     // every global read of chain levels 1..kChainPre and of the fine run,
     // issued before the first barrier
-    A pre[chain3_off(kChain3Pre + 1)];
+    A pre[chain_off(kChainPre + 1)];
 #pragma unroll
-    for (int l = 1; l <= kChain3Pre; ++l) {
+    for (int l = 1; l <= kChainPre; ++l) {
         if (l > a.L) break;
         const Win wl = win(l);
 #pragma unroll
-        for (int t = 0; t < chain3_rows(l); ++t) pre[chain3_off(l) + t] = level_row(l, wl, wl.lo + row0 + 4 * t);
+        for (int t = 0; t < chain_rows(l); ++t) pre[chain_off(l) + t] = level_row(l, wl, wl.lo + row0 + 4 * t);
     }
     T *x0 = a.x[0] + r * a.rs[0];
     A xf[kRows0];
@@ -914,12 +1021,12 @@ __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const B
         }
         __syncthreads();
     };
-    for (int l = a.L; l > kChain3Pre; --l)
+    for (int l = a.L; l > kChainPre; --l)
         step(l, kChainWin / 4, [&](int, int kk, const Win &wl) { return level_row(l, wl, kk); });
 #pragma unroll
-    for (int l = kChain3Pre; l >= 1; --l) {
+    for (int l = kChainPre; l >= 1; --l) {
         if (l > a.L) continue;
-        step(l, chain3_rows(l), [&](int t, int, const Win &) { return pre[chain3_off(l) + t]; });
+        step(l, chain_rows(l), [&](int t, int, const Win &) { return pre[chain_off(l) + t]; });
     }
     if (c >= pl) return;
     const Win wc = win(1);

@@ -134,7 +134,7 @@ size_t arith_size(int prec) { return prec == SMG_PREC_F64 ? 8 : 4; }
 // LDS budgets of the fused kernels (bytes per workgroup).  The coarse kernel
 // is latency-bound (one workgroup per plane), so it may take most of a CU's
 // 160 KB: every extra 2D level it absorbs removes one launch per 2D cycle.
-constexpr size_t kCoarseLds = 128 * 1024;
+constexpr size_t kCoarseLds = 160 * 1024;
 constexpr size_t kStripLds = 48 * 1024;
 // Register-only pre-smoothing: a launch with at least twice this many
 // coarse-line waves gives each wave a run of 2, 4 or 8 coarse lines (fewer
@@ -151,11 +151,15 @@ void apply_fused_schedule(smg_handle *h, size_t coarse_budget, size_t strip_budg
     const int nl = static_cast<int>(h->ny2.size());
     h->l0 = nl - 1;
     h->coarse_lds = 0;
+    // without post-smoothing the coarse kernel runs the downward half only and
+    // holds one level's b and x at a time (down-only mode, from level 1 up)
+    const bool down_only = h->ipre == 1 && h->ipost == 0 && h->o.order == 0;
     for (int l = nl - 1; l >= 0; --l) {
         size_t lines = 0;
         for (int m = l; m < nl; ++m) lines += h->ny2[m];
-        // x and b of every line, then the line rows
-        const size_t bytes = 2 * lines * line + lines * row;
+        // x and b of every line (down-only: of the first level), then the line rows
+        const size_t xb = down_only && l >= 1 ? 2 * static_cast<size_t>(h->ny2[l]) : 2 * lines;
+        const size_t bytes = xb * line + lines * row;
         if (bytes > coarse_budget) break;
         h->l0 = l;
         h->coarse_lds = bytes;
@@ -423,6 +427,16 @@ struct VCycle {
         }
     }
 
+    // lines the coarse kernel reads and writes: b and x of level l0 (plus the
+    // output read back when accumulating); down-only: b of l0, x of every level
+    double coarse_values(const Coarse2Args<T, A> &c) const
+    {
+        if (!c.down_only) return (2.0 + c.accumulate) * c.ny2[c.l0];
+        double v = c.ny2[c.l0];
+        for (int l = c.l0; l < c.nlev; ++l) v += c.ny2[l];
+        return v;
+    }
+
     bool fused2() const { return h->fused && h->o.order == 0 && h->ipre == 1 && h->ipost <= 1; }
     bool chain3() const { return h->fused && h->o.post == 0 && h->o.pre >= 1; }
 
@@ -468,23 +482,28 @@ struct VCycle {
         }
         c.ipre = h->ipre; c.ipost = h->ipost;
         c.pc = bt.pc; c.lc = LC(0); c.lines_total = h->lines_total; c.fac = h->at<Fac<A>>(h->L.fac);
+        // down-only: every level's x in the level arrays, the chain from the coarsest
+        const bool down_only = h->ipost == 0 && h->ipre == 1 && l0 >= 1;
+        c.down_only = down_only;
+        c.P2 = static_cast<int>(h->P2);
+        for (int l = l0; l < nl; ++l) c.xl[l] = h->at<T>(h->L.x2[l]);
         launch_coarse2<T, A>(c, h->coarse_lds, st,
-                             ev_for(SMG_KERNEL_COARSE2, (2.0 + c.accumulate) * h->ny2[l0] * nx * bt.np *
-                                                            static_cast<double>(nrhs)));
+                             ev_for(SMG_KERNEL_COARSE2, coarse_values(c) * nx * bt.np * static_cast<double>(nrhs)));
         if (l0 == 0) return;
         if (h->ipost == 0) {
             Chain2Args<T, A> ch{};
             ch.x0 = x0pre; ch.x0ps = x0ps; ch.x0rs = x0rs;
             ch.out = out; ch.ops = ops; ch.ors = ors; ch.accumulate = accumulate;
-            for (int l = 1; l <= l0; ++l) {
+            const int lc = down_only ? nl - 1 : l0;
+            for (int l = 1; l <= lc; ++l) {
                 ch.xc[l] = h->at<T>(h->L.x2[l]);
                 ch.cps[l] = ps2(l);
                 ch.crs[l] = rs2(l);
             }
-            for (int l = 0; l <= l0; ++l) ch.ny2[l] = h->ny2[l];
-            ch.nx = nx; ch.np = bt.np; ch.nrhs = nrhs; ch.lc = l0;
+            for (int l = 0; l <= lc; ++l) ch.ny2[l] = h->ny2[l];
+            ch.nx = nx; ch.np = bt.np; ch.nrhs = nrhs; ch.lc = lc;
             double lines = (2.0 + accumulate) * h->ny2[0];
-            for (int l = 1; l <= l0; ++l) lines += h->ny2[l];
+            for (int l = 1; l <= lc; ++l) lines += h->ny2[l];
             launch_chain2<T, A>(ch, st, ev_for(SMG_KERNEL_CHAIN2, lines * nx * bt.np * static_cast<double>(nrhs)));
             return;
         }

@@ -207,6 +207,11 @@ struct Coarse2Args {
     const LineCoef<A> *lc;      // rows of 2D level 0, plane type 0
     int lines_total;
     const Fac<A> *fac;
+    // down-only mode (one pre-smoothing sweep, no post-smoothing): the
+    // kernel leaves every level's x (l0 .. nlev-1) in xl[l] (plane stride
+    // nx*ny2[l], rhs stride P2 times that) for the prolongation chain
+    int down_only, P2;
+    T *xl[kMaxLev];
 };
 
 template <typename T, typename A>
