@@ -118,9 +118,19 @@ __device__ inline void load_fac(A (&g)[E], A (&h)[E], const Fac<A> *fac, int lan
 
 // Plan of the Thomas table fac: the products of h the lane scans multiply by.
 template <typename A, int E>
+__device__ inline void plan_products(LinePlan<A, E> &P, int lane);
+
+template <typename A, int E>
 __device__ inline void make_plan(LinePlan<A, E> &P, const Fac<A> *fac, int lane)
 {
     load_fac<A, E>(P.g, P.h, fac, lane);
+    plan_products<A, E>(P, lane);
+}
+
+// The scan multipliers of a plan whose rows P.g, P.h are in place.
+template <typename A, int E>
+__device__ inline void plan_products(LinePlan<A, E> &P, int lane)
+{
     A a0 = A(1);
 #pragma unroll
     for (int e = 0; e < E; ++e) a0 *= P.h[e];

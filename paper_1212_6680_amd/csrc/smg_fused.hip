@@ -533,6 +533,25 @@ __device__ __forceinline__ void k2_coarse_down_body(const Coarse2Args<T, A> &a, 
         }
     }
     __syncthreads();
+    // the Thomas table rows of the line this wave solves next, loaded one
+    // phase ahead (its global latency then hides behind a solve and a barrier)
+    LinePlan<A, E> P;
+    int pf = -1;
+    auto prefetch = [&](int l, int j) {
+        pf = -1;
+        if (l < a.nlev && j < a.ny2[l]) {
+            pf = __builtin_amdgcn_readfirstlane(lcs[off(l) + j].fac);
+            load_fac<A, E>(P.g, P.h, a.fac + static_cast<size_t>(pf) * nxp, lane);
+        }
+    };
+    auto solve = [&](A (&f)[E], int fi) {
+        fi = __builtin_amdgcn_readfirstlane(fi);
+        if (fi != pf) load_fac<A, E>(P.g, P.h, a.fac + static_cast<size_t>(fi) * nxp, lane);
+        plan_products<A, E>(P, lane);
+        solve_plan<A, E>(f, P, lane);
+        pf = -1;
+    };
+    prefetch(a.l0, 2 * w);
     for (int l = a.l0; l < a.nlev - 1; ++l) {
         const int ny = a.ny2[l], nyc = a.ny2[l + 1];
         const LineCoef<A> *lc = lcs + off(l);
@@ -553,10 +572,18 @@ __device__ __forceinline__ void k2_coarse_down_body(const Coarse2Args<T, A> &a, 
                         sub_op<A, E>(f, v, cj.va, cj.vb);
                     }
                 }
-                thomas<A, E>(f, a.fac + static_cast<size_t>(lc[j].fac) * nxp, lane);
+                solve(f, lc[j].fac);
                 sstore<A, E>(xs + j * nxp, f, lane);
                 gstore<T, A, E>(xrow(l, j), f, nx, lane);
             }
+            // next: this level's C line, or the next level's F line (the
+            // coarsest level's line for wave 0)
+            if (colour == 0)
+                prefetch(l, 2 * w + 1);
+            else if (l + 1 < a.nlev - 1)
+                prefetch(l + 1, 2 * w);
+            else if (w == 0)
+                prefetch(a.nlev - 1, 0);
             __syncthreads();
         }
         // b_{l+1}[J] = 1/2 (r_{2J} + r_{2J+2}), r_j = -V_{j-1} x_{j-1} - V_j x_{j+1}
@@ -591,7 +618,7 @@ __device__ __forceinline__ void k2_coarse_down_body(const Coarse2Args<T, A> &a, 
         const int l = a.nlev - 1;
         A f[E];
         sload<A, E>(f, bs, lane);
-        thomas<A, E>(f, a.fac + static_cast<size_t>(lcs[off(l)].fac) * nxp, lane);
+        solve(f, lcs[off(l)].fac);
         gstore<T, A, E>(xrow(l, 0), f, nx, lane);
     }
 }
