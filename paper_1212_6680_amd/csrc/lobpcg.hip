@@ -327,6 +327,101 @@ __global__ __launch_bounds__(256) void k_block_update(const double *U, long long
     }
 }
 
+// Y (N x mo) = U (N x k) C (k x mo) for mo <= 16 JB with every output
+// column in one block: a block owns 64 rows (wave w: rows 16w .. 16w + 15)
+// and all ceil(mo/16) 16-column blocks, so U is read once (the 64-column
+// tiles of k_block_update read it once per tile) and C comes from cache.
+// Same transposed MFMA form (Y^T = C^T U^T) and two LDS stages with the next
+// 16 rows of C and U read into registers meanwhile. Rows of C that are zero
+// for a whole 16-column block (a triangular factor, a coefficient block with
+// zeroed rows) are skipped: column block jt only takes the 16-row stages that
+// meet [lo[jt], hi[jt]), and the stage loop runs over their union.
+struct RowSpan {
+    int lo[kTriMax / 16];
+    int hi[kTriMax / 16];
+};
+
+template <int JB>
+__global__ __launch_bounds__(256) void k_block_update_wide(
+    const double *U, long long ldu, int i_begin, int i_end,
+                                                           const double *C, int mo, RowSpan span, double *Y,
+                                                           long long ldy, long long n)
+{
+    constexpr int W = 16 * JB;
+    constexpr int RC = (kK * W + 255) / 256;     // C values per thread and stage
+    __shared__ double Ct[2][kK][W + kLdsPad];
+    __shared__ double Ut[2][kK][kT + kLdsPad];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const long long n0 = static_cast<long long>(blockIdx.x) * kT;
+    const int jn = (mo + 15) / 16;
+    const int mp = jn * 16;
+    v4d acc[JB];
+#pragma unroll
+    for (int jt = 0; jt < JB; ++jt) acc[jt] = v4d{0, 0, 0, 0};
+    double ru[4], rc[RC];
+    auto fetch = [&](int i0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r;          // 16 x 64
+            const int ii = e >> 6, nn = e & 63;
+            const long long ng = n0 + nn;
+            ru[r] = (i0 + ii < i_end && ng < n) ? U[ng + (i0 + ii) * ldu] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int e = tid + 256 * r;          // 16 x W
+            const int ii = e / W, jj = e % W;
+            rc[r] = (ii < kK && i0 + ii < i_end && jj < mo) ? C[static_cast<long long>(i0 + ii) * mo + jj] : 0.0;
+        }
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r;
+            Ut[st][e >> 6][e & 63] = ru[r];
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int e = tid + 256 * r;
+            const int ii = e / W, jj = e % W;
+            if (ii < kK && jj < mp) Ct[st][ii][jj] = rc[r];
+        }
+    };
+    fetch(i_begin);
+    stash(0);
+    __syncthreads();
+    int st = 0;
+    for (int i0 = i_begin; i0 < i_end; i0 += kK) {
+        const bool more = i0 + kK < i_end;
+        if (more) fetch(i0 + kK);
+#pragma unroll
+        for (int kk = 0; kk < kK / 4; ++kk) {
+            const int kr = 4 * kk + (lane >> 4);
+            const double b = Ut[st][kr][16 * w + (lane & 15)];
+#pragma unroll
+            for (int jt = 0; jt < JB; ++jt) {
+                if (jt < jn && i0 < span.hi[jt] && i0 + kK > span.lo[jt]) {
+                    const double a = Ct[st][kr][16 * jt + (lane & 15)];
+                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
+                }
+            }
+        }
+        if (more) stash(st ^ 1);
+        __syncthreads();
+        st ^= 1;
+    }
+    const long long nn = n0 + 16 * w + (lane & 15);
+    if (nn >= n) return;
+#pragma unroll
+    for (int jt = 0; jt < JB; ++jt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = 16 * jt + 4 * r + (lane >> 4);
+            if (j < mo) Y[nn + j * ldy] = acc[jt][r];
+        }
+    }
+}
+
 // R[:, c] = AX[:, c] - theta[c] X[:, c]
 __global__ void k_block_resid(const double *AX, const double *X, const double *theta, double *R, long long ld,
                               long long n, int m)
@@ -486,9 +581,44 @@ struct Lob {
     {
         if (hipMemcpyAsync(at<double>(L.C), C.data(), C.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
-        hipLaunchKernelGGL(k_block_update, dim3(nblk(static_cast<long long>(N), kT), nblk(mo, kT)), dim3(256), 0, st,
-                           U, static_cast<long long>(N), k, at<double>(L.C), mo, Y, static_cast<long long>(N),
-                           static_cast<long long>(N));
+        // one 64-column tile reads U once already; wider outputs keep every column in a block
+        if (mo > kT && mo <= kTriMax) {
+            // rows of C that are nonzero per 16-column block; all-zero row spans are skipped
+            RowSpan sp{};
+            const int jn = (mo + 15) / 16;
+            int i_begin = k, i_end = 0;
+            for (int jt = 0; jt < jn; ++jt) {
+                int lo = k, hi = 0;
+                for (int i = 0; i < k; ++i)
+                    for (int j = 16 * jt; j < std::min(mo, 16 * jt + 16); ++j)
+                        if (C[static_cast<size_t>(i) * mo + j] != 0.0) {
+                            lo = std::min(lo, i);
+                            hi = i + 1;
+                            break;
+                        }
+                sp.lo[jt] = lo;
+                sp.hi[jt] = hi;
+                if (lo < hi) {
+                    i_begin = std::min(i_begin, lo);
+                    i_end = std::max(i_end, hi);
+                }
+            }
+            if (i_end <= i_begin) i_begin = i_end = 0;   // C == 0: the kernel writes zeros
+            i_begin -= i_begin % kK;
+            const dim3 grid(nblk(static_cast<long long>(N), kT));
+            const long long ln = static_cast<long long>(N);
+            const double *Cd = at<double>(L.C);
+            if (mo <= 128)
+                hipLaunchKernelGGL(k_block_update_wide<8>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
+                                   Y, ln, ln);
+            else
+                hipLaunchKernelGGL(k_block_update_wide<kTriMax / 16>, grid, dim3(256), 0, st, U, ln, i_begin, i_end,
+                                   Cd, mo, sp, Y, ln, ln);
+        } else {
+            hipLaunchKernelGGL(k_block_update, dim3(nblk(static_cast<long long>(N), kT), nblk(mo, kT)), dim3(256), 0,
+                               st, U, static_cast<long long>(N), k, at<double>(L.C), mo, Y, static_cast<long long>(N),
+                               static_cast<long long>(N));
+        }
         // C is reused by the next call: wait before the host buffer changes
         return hipStreamSynchronize(st) == hipSuccess && ok();
     }
@@ -522,21 +652,37 @@ struct Lob {
         return hipStreamSynchronize(st) == hipSuccess && ok();
     }
 
-    // Cholesky QR twice of S (N x k) with A S alike; S/AS and the scratch T/AT
-    // swap roles, so after two passes the result is back in S/AS.
+    // Cholesky QR twice of S (N x k). S and the scratch T swap roles, so after
+    // two passes the result is back in S; A S takes the product of the two
+    // (upper triangular) factors in one update instead of one per pass.
     int cholqr2(double *&S, double *&AS, double *&T, double *&AT, int k)
     {
-        std::vector<double> G, Ct(static_cast<size_t>(k) * k);
+        const size_t kk = static_cast<size_t>(k) * k;
+        std::vector<double> G, C1(kk), C2(kk);
         for (int pass = 0; pass < 2; ++pass) {
             if (!gram(S, k, S, k, G)) return -1;
             for (int i = 0; i < k; ++i)
                 for (int j = 0; j < i; ++j) G[i * k + j] = G[j * k + i] = 0.5 * (G[i * k + j] + G[j * k + i]);
-            if (!dense::cholesky(k, G.data())) return 0;
-            dense::inv_lower_transpose(k, G.data(), Ct.data());
-            if (!update(S, k, Ct, k, T) || !update(AS, k, Ct, k, AT)) return -1;
+            if (!dense::cholesky(k, G.data())) {
+                if (pass == 0) return 0;
+                // keep A S in step with the once-factored S
+                if (!update(AS, k, C1, k, AT)) return -1;
+                std::swap(AS, AT);
+                return 0;
+            }
+            std::vector<double> &C = pass == 0 ? C1 : C2;
+            dense::inv_lower_transpose(k, G.data(), C.data());
+            if (!update(S, k, C, k, T)) return -1;
             std::swap(S, T);
-            std::swap(AS, AT);
         }
+        std::vector<double> Cp(kk, 0.0);
+        for (int i = 0; i < k; ++i)
+            for (int l = i; l < k; ++l) {
+                const double c = C1[i * k + l];
+                for (int j = l; j < k; ++j) Cp[i * k + j] += c * C2[l * k + j];
+            }
+        if (!update(AS, k, Cp, k, AT)) return -1;
+        std::swap(AS, AT);
         return 1;
     }
 
