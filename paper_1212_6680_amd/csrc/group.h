@@ -36,6 +36,24 @@ struct Blk {
             static_cast<int>(gridDim.x), static_cast<int>(gridDim.y), static_cast<int>(gridDim.z)              \
     }
 
+// The workgroups of a launch are dealt to the 8 XCDs round-robin by flat id,
+// and each XCD has its own L2.  This renumbering gives every XCD one
+// contiguous range of the logical order (x fastest), so neighbouring tiles
+// that read each other's halo lines, or the planes next to theirs, run under
+// the same L2.  It is a bijection of the flat ids for any grid size.
+__device__ inline Blk blk_xcd()
+{
+    constexpr int kXcd = 8;
+    const int gx = static_cast<int>(gridDim.x), gy = static_cast<int>(gridDim.y), gz = static_cast<int>(gridDim.z);
+    const int nb = gx * gy * gz;
+    const int l = static_cast<int>(blockIdx.x) + gx * (static_cast<int>(blockIdx.y) + gy * static_cast<int>(blockIdx.z));
+    const int q = nb / kXcd, rem = nb % kXcd, x = l % kXcd;
+    const int lp = x * q + min(x, rem) + l / kXcd;
+    return Blk{lp % gx, (lp / gx) % gy, lp / (gx * gy), gx, gy, gz};
+}
+
+#define SMG_BLK_XCD smg::blk_xcd()
+
 constexpr int kGroupArgBytes = 528;
 
 struct alignas(16) GroupEntry {

@@ -68,8 +68,8 @@ __global__ __launch_bounds__(256) void k_matvec7(const double *x, double *y, lon
 }
 
 
-#define SMG_GROUPED_KERNEL(NAME, BOUNDS, ARGS)                                                 \
-    __global__ __launch_bounds__(BOUNDS) void NAME(ARGS a) { NAME##_body(a, SMG_BLK_HW); }     \
+#define SMG_GROUPED_KERNEL_B(NAME, BOUNDS, ARGS, BLK)                                          \
+    __global__ __launch_bounds__(BOUNDS) void NAME(ARGS a) { NAME##_body(a, BLK); }            \
     __global__ __launch_bounds__(BOUNDS) void NAME##_grp(const GroupEntry *tab, int n)         \
     {                                                                                          \
         const ARGS *a;                                                                         \
@@ -77,6 +77,10 @@ __global__ __launch_bounds__(256) void k_matvec7(const double *x, double *y, lon
         if (!group_entry(tab, n, a, blk)) return;                                              \
         NAME##_body(*a, blk);                                                                  \
     }
+
+#define SMG_GROUPED_KERNEL(NAME, BOUNDS, ARGS) SMG_GROUPED_KERNEL_B(NAME, BOUNDS, ARGS, SMG_BLK_HW)
+// plain launches of the tiled stencil passes take XCD-grouped block numbers
+#define SMG_GROUPED_KERNEL_XCD(NAME, BOUNDS, ARGS) SMG_GROUPED_KERNEL_B(NAME, BOUNDS, ARGS, SMG_BLK_XCD)
 
 // r = b - A x (or r = b when x_zero) and partial sums of r^2, b^2; grid-stride
 __device__ __forceinline__ void k_init_resid_body(const ResidArgs &a, const Blk &blk)
@@ -238,7 +242,7 @@ __device__ __forceinline__ void k_update_p_q_tiled_body(const UpdPQArgs &a, cons
     if (bid == 0)
         for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) a.partials[e] = 0.0;
 }
-SMG_GROUPED_KERNEL(k_update_p_q_tiled, kTileThreads, UpdPQArgs)
+SMG_GROUPED_KERNEL_XCD(k_update_p_q_tiled, kTileThreads, UpdPQArgs)
 
 // r = b - A x with partial sums of r^2 and b^2 (x tiled through LDS, marching
 // in z like k_update_p_q_tiled); block 0 zeroes the unused partial slots.
@@ -301,7 +305,7 @@ __device__ __forceinline__ void k_resid_tiled_body(const ResidArgs &a, const Blk
             a.partials[kRedBlocks + e] = 0.0;
         }
 }
-SMG_GROUPED_KERNEL(k_resid_tiled, kTileThreads, ResidArgs)
+SMG_GROUPED_KERNEL_XCD(k_resid_tiled, kTileThreads, ResidArgs)
 
 __device__ __forceinline__ void k_update_xr_body(const UpdXRArgs &a, const Blk &blk)
 {

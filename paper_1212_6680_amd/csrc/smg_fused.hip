@@ -974,7 +974,7 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void k2_chain(Chain2Args<T, A> a)
 {
-    k2_chain_body<T, A>(a, SMG_BLK_HW);
+    k2_chain_body<T, A>(a, SMG_BLK_XCD);
 }
 
 template <typename T, typename A>

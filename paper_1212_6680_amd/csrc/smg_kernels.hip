@@ -274,7 +274,7 @@ __device__ __forceinline__ void k_resid3_body(const Resid3Args<T, A> &a, const B
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void k_resid3(Resid3Args<T, A> a)
 {
-    k_resid3_body<T, A>(a, SMG_BLK_HW);
+    k_resid3_body<T, A>(a, SMG_BLK_XCD);
 }
 
 template <typename T, typename A>
@@ -319,7 +319,7 @@ __device__ __forceinline__ void k_restrict3_body(const Restrict3Args<T, A> &a, c
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void k_restrict3(Restrict3Args<T, A> a)
 {
-    k_restrict3_body<T, A>(a, SMG_BLK_HW);
+    k_restrict3_body<T, A>(a, SMG_BLK_XCD);
 }
 
 template <typename T, typename A>
@@ -502,7 +502,7 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
 template <typename T, typename A>
 __global__ __launch_bounds__(kRThreads) void k_restrict3_march(Restrict3Args<T, A> a)
 {
-    k_restrict3_march_body<T, A>(a, SMG_BLK_HW);
+    k_restrict3_march_body<T, A>(a, SMG_BLK_XCD);
 }
 
 template <typename T, typename A>
