@@ -64,10 +64,12 @@ inline void inv_lower_transpose(int n, const double *L, double *out)
 inline bool sym_eig(int n, const double *A, double *V, double *w)
 {
     std::vector<double> T(A, A + static_cast<size_t>(n) * n);
-    std::vector<double> Q(static_cast<size_t>(n) * n, 0.0);
-    for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+    // Q is kept transposed (row j of Qt is column j of Q), so that a rotation
+    // of two columns and a reflection both run over contiguous rows
+    std::vector<double> Qt(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Qt[i * n + i] = 1.0;
     auto t = [&](int i, int j) -> double & { return T[static_cast<size_t>(i) * n + j]; };
-    auto q = [&](int i, int j) -> double & { return Q[static_cast<size_t>(i) * n + j]; };
+    auto qrow = [&](int j) { return Qt.data() + static_cast<size_t>(j) * n; };
 
     // Phase 1: Householder reflections H_k = I - beta v v^T zero column k
     // below the subdiagonal; T <- H T H, Q <- Q H.
@@ -99,12 +101,17 @@ inline bool sym_eig(int n, const double *A, double *V, double *w)
         // T <- T - v w^T - w v^T on rows/cols >= k (v[k] = 0)
         for (int i = k; i < n; ++i)
             for (int j = k; j < n; ++j) t(i, j) -= v[i] * wv[j] + wv[i] * v[j];
-        // Q <- Q H
-        for (int i = 0; i < n; ++i) {
-            double s = 0.0;
-            for (int j = k + 1; j < n; ++j) s += q(i, j) * v[j];
-            s *= beta;
-            for (int j = k + 1; j < n; ++j) q(i, j) -= s * v[j];
+        // Q <- Q H: s_i = beta sum_j Q(i, j) v_j, then Q(i, j) -= s_i v_j
+        std::fill(p.begin(), p.end(), 0.0);
+        for (int j = k + 1; j < n; ++j) {
+            const double vj = v[j];
+            const double *qj = qrow(j);
+            for (int i = 0; i < n; ++i) p[i] += qj[i] * vj;
+        }
+        for (int j = k + 1; j < n; ++j) {
+            const double vj = v[j];
+            double *qj = qrow(j);
+            for (int i = 0; i < n; ++i) qj[i] -= beta * p[i] * vj;
         }
     }
     std::vector<double> d(n), e(n > 1 ? n - 1 : 1, 0.0);
@@ -148,10 +155,11 @@ inline bool sym_eig(int n, const double *A, double *V, double *w)
                 x = e[k];
                 z = bulge;
             }
+            double *qa = qrow(k), *qb = qrow(k + 1);
             for (int i = 0; i < n; ++i) {
-                const double qk = q(i, k), qk1 = q(i, k + 1);
-                q(i, k) = c * qk + s * qk1;
-                q(i, k + 1) = -s * qk + c * qk1;
+                const double qk = qa[i], qk1 = qb[i];
+                qa[i] = c * qk + s * qk1;
+                qb[i] = -s * qk + c * qk1;
             }
         }
     }
@@ -160,7 +168,8 @@ inline bool sym_eig(int n, const double *A, double *V, double *w)
     std::sort(ord.begin(), ord.end(), [&](int i, int j) { return d[i] < d[j]; });
     for (int jj = 0; jj < n; ++jj) {
         w[jj] = d[ord[jj]];
-        for (int i = 0; i < n; ++i) V[static_cast<size_t>(i) * n + jj] = q(i, ord[jj]);
+        const double *qj = qrow(ord[jj]);
+        for (int i = 0; i < n; ++i) V[static_cast<size_t>(i) * n + jj] = qj[i];
     }
     return true;
 }
