@@ -755,6 +755,17 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         return status;
     };
     auto sync = [&]() { return hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess; };
+    // End of an iteration's work on the stream (its scalars are in hs once it
+    // completes), so that the next iteration's V-cycle can be queued before
+    // the host waits; see the loop.
+    struct Event {
+        hipEvent_t e = nullptr;
+        ~Event()
+        {
+            if (e) (void)hipEventDestroy(e);
+        }
+    } done;
+    if (hipEventCreateWithFlags(&done.e, hipEventDisableTiming) != hipSuccess) return finish(SMG_EHIP);
     auto fall_back = [&](int k, int reason) {
         hook->active = 0;
         hook->fallback_iter = k;
@@ -773,8 +784,11 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     if (o->history) o->history[0] = rel;
     double c0 = 0.0;
     int k = 0, status = SMG_NOT_CONVERGED;
+    bool queued = false;   // this iteration's V-cycle is already on the stream
     for (; k < o->max_iter && rel > o->rtol; ++k) {
-        if (o->precond == SMG_PRECOND_SMG)
+        if (queued)
+            queued = false;
+        else if (o->precond == SMG_PRECOND_SMG)
             vcycle(h, r, s, 1, static_cast<long long>(n), st);
         else
             launch_copy(r, s, n, st);
@@ -804,7 +818,23 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         launch_finalize(2, method, k, part, sc, nullptr, st);
         launch_update_xr(x, r, pb, q, sc, n, part, st);
         launch_finalize(3, method, k, part, sc, hs, st);
-        if (!sync()) return finish(SMG_EHIP);
+        // When the residual history says the next iteration will run (the
+        // rate of the last two steps, with a margin of 4 over rtol), its
+        // V-cycle s = B r_{k+1} goes on the stream before the host waits for
+        // this iteration's scalars, so the GPU does not idle meanwhile.  The
+        // V-cycle writes s only, which nothing reads after a stop.
+        const double pred = k == 0 ? 0.5 * rels[0] : rels[k] * (rels[k] / rels[k - 1]);
+        const bool ahead = o->precond == SMG_PRECOND_SMG && !(hook && hook->active) && k + 1 < o->max_iter &&
+                           pred > 4.0 * o->rtol;
+        if (ahead) {
+            if (hipEventRecord(done.e, st) != hipSuccess) return finish(SMG_EHIP);
+            vcycle(h, r, s, 1, static_cast<long long>(n), st);
+            queued = true;
+            if (hipEventSynchronize(done.e) != hipSuccess || hipGetLastError() != hipSuccess)
+                return finish(SMG_EHIP);
+        } else if (!sync()) {
+            return finish(SMG_EHIP);
+        }
         std::swap(pa, pb);
         if (hs->breakdown) {
             inf.iters = k;
