@@ -393,7 +393,7 @@ __global__ void k_convert_out(const T *src, long long lds, double *dst, long lon
     dst[r * ldd + i] = static_cast<double>(ldv(src + r * lds + i));
 }
 
-// Residual + restriction marching in z.  A block owns a 64 x 8 (i, j) tile and
+// Residual + restriction marching in z.  A block owns a 64 x 4 (i, j) tile and
 // a run of coarse planes [K0, K1).  Every fine x plane is staged once in an
 // LDS tile with a one-point halo, its in-plane product T2 x is formed once,
 // and a window of three planes (x and T2 x) in registers feeds the 15-point
@@ -401,7 +401,8 @@ __global__ void k_convert_out(const T *src, long long lds, double *dst, long lon
 // combined into b_c[K] = 1/2 r_{2K} + r_{2K+1} + 1/2 r_{2K+2} as the march
 // passes.  x and b are read about once, a few planes ahead of their use; two
 // LDS tiles alternate, so each plane takes one barrier.
-constexpr int kRTX = 64, kRTY = 8, kRThreads = kRTX * kRTY;
+constexpr int kRTX = 64, kRTY = 4, kRThreads = kRTX * kRTY;
+static_assert(2 * (kRTX + kRTY) <= kRThreads, "every halo point needs a thread");
 
 template <typename T, typename A>
 __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A> &a, const Blk &blk)
@@ -434,8 +435,9 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
     const int kx_last = min(nz - 1, 2 * K1 + 1), kb_last = min(nz - 1, 2 * K1);
     // the next kPre planes of x (centre and halo point) and of b are loaded
     // ahead into small register rings, so that a step waits on a load issued
-    // kPre steps before rather than on its own
-    constexpr int kPre = 4;
+    // kPre steps before rather than on its own (two: a deeper ring costs
+    // registers, and eight waves per SIMD hide more than the ring does)
+    constexpr int kPre = 2;
     auto load_x = [&](int k, A &xc, A &xh) {
         const bool live = k >= 0 && k <= kx_last && !a.x_zero;
         xc = (in && live) ? static_cast<A>(ldv(x + k * pl + c2)) : A(0);
