@@ -132,7 +132,7 @@ def test_vcycle_parity_full_size(n):
 
 
 FUSED_SHAPES = [(1, 1, 1), (9, 1, 1), (5, 4, 3), (16, 16, 16), (33, 17, 9), (64, 64, 2), (130, 6, 7),
-                (17, 40, 33), (100, 70, 45), (256, 256, 4), (300, 11, 3), (64, 200, 5), (512, 3, 4)]
+                (17, 40, 33), (100, 70, 45), (256, 256, 4), (300, 11, 3), (64, 200, 5), (384, 30, 4), (512, 3, 4)]
 
 
 @pytest.mark.parametrize("shape", FUSED_SHAPES)
@@ -177,7 +177,8 @@ def test_autotuned_schedule_matches_oracle(shape):
 
 
 @pytest.mark.parametrize("shape,nrhs", [((33, 45, 17), 1), ((70, 129, 9), 1), ((200, 31, 12), 1),
-                                        ((256, 64, 8), 1), ((96, 57, 6), 3)])
+                                        ((256, 64, 8), 1), ((96, 57, 6), 3), ((300, 37, 6), 1),
+                                        ((384, 48, 5), 2)])
 @pytest.mark.parametrize("pp", [(1, 0), (1, 1)])
 def test_marching_pre_smoothing(shape, nrhs, pp):
     """Pre-smoothing kernels that march runs of 2, 4 or 8 coarse lines per wave
@@ -185,7 +186,8 @@ def test_marching_pre_smoothing(shape, nrhs, pp):
     by a threshold of 5) give the V-cycle of single-line waves up to rounding
     (the same operations; the compiler may fuse a multiply-add differently),
     and the oracle's to 1e-12: odd and even line counts, runs cut by the end
-    of a level, line widths of 1 to 4 points per lane, several right-hand sides."""
+    of a level, line widths of 1 to 4 points per lane (wider lines, 5 and 6
+    points, take the LDS strip kernel either way), several right-hand sides."""
     c = tuple((v + 1.0) ** 2 for v in shape)
     n = int(np.prod(shape))
     r = np.stack([synth.rhs(*shape, seed=90 + i).reshape(-1) for i in range(nrhs)])
