@@ -212,6 +212,48 @@ def test_correction_bf16():
     assert np.linalg.norm(corr - y) <= 2e-3 * np.linalg.norm(y)
 
 
+def test_correction_bf16_full_size_sampled():
+    """The bf16 correction at 256^3 (the size the learned post-smoother is applied
+    at, c = 257^2) against the oracle at sampled points: corners, edges, faces
+    and the interior.  An output point depends on the input within distance 4
+    (four 3x3x3 layers), so the oracle runs the network on the 9^3 patch around
+    each sample, cut at the domain boundary where the zero padding is the same
+    as on the whole grid.  sigma is a global mean, compared in full."""
+    n = 256
+    shape = (n, n, n)
+    c = ((n + 1.0) ** 2,) * 3
+    params = L.init_params(11)
+    r = synth.rhs(n, n, n, 35)
+    s = 0.1 * synth.rhs(n, n, n, 36) / c[0]
+    rp = r - O.matvec(s, shape, c)
+    cbar = sum(c) / 3
+    sigma = np.sqrt(np.mean((rp / cbar) ** 2))
+    G = _smg(shape, c, 1, 0)
+    net = _net(G.n, "bf16", train=False)
+    net.set_params(L.flatten(params))
+    out, sig = net.correct(G, _dev(r), _dev(s))
+    corr = ((out.cpu().numpy() - s) / sig).reshape(n, n, n)
+    assert abs(sig - sigma) <= 1e-12 * sigma
+    x = (rp / (cbar * sigma)).reshape(n, n, n)
+    pq = [(W, b.astype(np.float32).astype(np.float64)) for W, b in params]
+    g = np.random.default_rng(5)
+    ends = [0, 1, 4, n - 5, n - 2, n - 1]
+    pts = [(k, j, i) for k in (0, n - 1) for j in (0, n - 1) for i in (0, n - 1)]
+    pts += [tuple(int(v) for v in g.choice(ends, 3)) for _ in range(16)]
+    pts += [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(24)]
+    got, want = [], []
+    for k, j, i in pts:
+        lo = [max(0, v - 4) for v in (k, j, i)]
+        hi = [min(n, v + 5) for v in (k, j, i)]
+        patch = x[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        y = L.forward(pq, patch, quantize=L.round_bf16)
+        want.append(y[k - lo[0], j - lo[1], i - lo[2]])
+        got.append(corr[k, j, i])
+    got, want = np.array(got), np.array(want)
+    assert np.linalg.norm(got - want) <= 5e-3 * np.linalg.norm(want)
+    assert np.max(np.abs(got - want)) <= 2e-2 * np.sqrt(np.mean(want ** 2))
+
+
 def test_pairs_match_oracle_f64():
     shape = (20, 18, 16)
     nx, ny, nz = shape
