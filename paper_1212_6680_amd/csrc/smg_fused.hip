@@ -880,7 +880,7 @@ __host__ __device__ constexpr int chain_off(int l)
 }
 static_assert(kChainRun == 32, "chain_rows assumes runs of 32 fine planes");
 
-template <typename T, typename A>
+template <typename T, typename A, bool ACC>
 __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const Blk &blk)
 {
     __shared__ A vs[2][kChainWin * kChainCols];
@@ -927,7 +927,7 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
         if (jj <= w0.hi && i < nx) {
             const long long o = static_cast<long long>(jj) * nx + i;
             xf[t] = static_cast<A>(ldv(x0 + o));
-            if (a.accumulate) of[t] = static_cast<A>(ldv(out + o));
+            if constexpr (ACC) of[t] = static_cast<A>(ldv(out + o));
         }
     }
     int cur = 0;
@@ -966,24 +966,26 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
         const int jj = w0.lo + row0 + 4 * t;
         if (jj > w0.hi) break;
         A s = xf[t] + prolong_point(vs[cur], wc, jj, a.ny2[1], col);
-        if (a.accumulate) s += of[t];
+        if constexpr (ACC) s += of[t];
         stv(out + static_cast<long long>(jj) * nx + i, s);
     }
 }
 
-template <typename T, typename A>
+// ACC: the output is accumulated into (read back) rather than assigned; the
+// assigning kernel keeps no registers for the read-back
+template <typename T, typename A, bool ACC>
 __global__ __launch_bounds__(256) void k2_chain(Chain2Args<T, A> a)
 {
-    k2_chain_body<T, A>(a, SMG_BLK_XCD);
+    k2_chain_body<T, A, ACC>(a, SMG_BLK_XCD);
 }
 
-template <typename T, typename A>
+template <typename T, typename A, bool ACC>
 __global__ __launch_bounds__(256) void k2_chain_grp(const GroupEntry *tab, int n)
 {
     const Chain2Args<T, A> *a;
     Blk blk;
     if (!group_entry(tab, n, a, blk)) return;
-    k2_chain_body<T, A>(*a, blk);
+    k2_chain_body<T, A, ACC>(*a, blk);
 }
 
 
@@ -1293,7 +1295,12 @@ void launch_chain2(const Chain2Args<T, A> &a, hipStream_t st, const LaunchEv &ev
     const long long nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
     const long long nblk = ncol * nrun * a.np * a.nrhs;
     if (nblk == 0) return;
-    SMG_LAUNCH_G(ev, (k2_chain<T, A>), (k2_chain_grp<T, A>), dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, a);
+    if (a.accumulate)
+        SMG_LAUNCH_G(ev, (k2_chain<T, A, true>), (k2_chain_grp<T, A, true>), dim3(static_cast<unsigned>(nblk)),
+                     dim3(256), 0, st, a);
+    else
+        SMG_LAUNCH_G(ev, (k2_chain<T, A, false>), (k2_chain_grp<T, A, false>), dim3(static_cast<unsigned>(nblk)),
+                     dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
