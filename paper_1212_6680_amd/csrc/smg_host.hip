@@ -822,7 +822,8 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         // rate of the last two steps, with a margin of 4 over rtol), its
         // V-cycle s = B r_{k+1} goes on the stream before the host waits for
         // this iteration's scalars, so the GPU does not idle meanwhile.  The
-        // V-cycle writes s only, which nothing reads after a stop.
+        // V-cycle writes s and its own level buffers only, which nothing reads
+        // after a stop (the true residual below uses s as scratch).
         const double pred = k == 0 ? 0.5 * rels[0] : rels[k] * (rels[k] / rels[k - 1]);
         const bool ahead = o->precond == SMG_PRECOND_SMG && !(hook && hook->active) && k + 1 < o->max_iter &&
                            pred > 4.0 * o->rtol;
