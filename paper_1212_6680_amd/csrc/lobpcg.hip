@@ -611,6 +611,12 @@ struct Lob {
             if (mo <= 128)
                 hipLaunchKernelGGL(k_block_update_wide<8>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
                                    Y, ln, ln);
+            else if (mo <= 144)
+                hipLaunchKernelGGL(k_block_update_wide<9>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
+                                   Y, ln, ln);
+            else if (mo <= 208)
+                hipLaunchKernelGGL(k_block_update_wide<13>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
+                                   Y, ln, ln);
             else
                 hipLaunchKernelGGL(k_block_update_wide<kTriMax / 16>, grid, dim3(256), 0, st, U, ln, i_begin, i_end,
                                    Cd, mo, sp, Y, ln, ln);
