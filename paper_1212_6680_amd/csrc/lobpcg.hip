@@ -581,8 +581,9 @@ struct Lob {
     {
         if (hipMemcpyAsync(at<double>(L.C), C.data(), C.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
-        // one 64-column tile reads U once already; wider outputs keep every column in a block
-        if (mo > kT && mo <= kTriMax) {
+        // one 64-column tile of k_block_update reads U once already; it is
+        // kept for 49..64 columns, where the 4-block instance needs 195 VGPRs
+        if (mo <= kTriMax && (mo <= 48 || mo > kT)) {
             // rows of C that are nonzero per 16-column block; all-zero row spans are skipped
             RowSpan sp{};
             const int jn = (mo + 15) / 16;
@@ -608,7 +609,13 @@ struct Lob {
             const dim3 grid(nblk(static_cast<long long>(N), kT));
             const long long ln = static_cast<long long>(N);
             const double *Cd = at<double>(L.C);
-            if (mo <= 128)
+            if (mo <= 32)
+                hipLaunchKernelGGL(k_block_update_wide<2>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
+                                   Y, ln, ln);
+            else if (mo <= 48)
+                hipLaunchKernelGGL(k_block_update_wide<3>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
+                                   Y, ln, ln);
+            else if (mo <= 128)
                 hipLaunchKernelGGL(k_block_update_wide<8>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
                                    Y, ln, ln);
             else if (mo <= 144)
