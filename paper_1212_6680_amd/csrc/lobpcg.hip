@@ -143,31 +143,31 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double *U, long long
 // padding beyond the last 16-block.  Slices of 16 rows (8 when U != V, to keep
 // both operands in the same LDS) are staged in two LDS stages with the next
 // slice read into registers meanwhile.  Writes part[z][i][j] for the upper
-// blocks only (the reduction mirrors).
+// blocks only (the reduction mirrors).  An instance takes k <= 16 NB: its
+// accumulators and LDS scale with NB, so narrow products run more blocks per CU.
 constexpr int kTriMax = 224;                  // 14 blocks of 16
-constexpr int kTriBlocks = 14 * 15 / 2;       // 105 output blocks at most
 constexpr int kTriWaves = 8;                  // waves per block (two per SIMD)
-constexpr int kTriPerWave = (kTriBlocks + kTriWaves - 1) / kTriWaves;
-constexpr int kTriLd = kTriMax + kLdsPad;
 
-template <bool SAME>
+template <bool SAME, int NB>
 __global__ __launch_bounds__(64 * kTriWaves) void k_gram_tri(const double *U, const double *V, long long ld, int k, long long n,
                                                   long long slice, double *part)
 {
     constexpr int KS = SAME ? 16 : 8;                    // rows per stage
     constexpr int NT = 64 * kTriWaves;
-    constexpr int R = (KS * kTriMax + NT - 1) / NT;      // staged values per thread and operand
+    constexpr int TM = 16 * NB;                          // widest k of this instance
+    constexpr int PW = (NB * (NB + 1) / 2 + kTriWaves - 1) / kTriWaves;   // output blocks per wave
+    constexpr int R = (KS * TM + NT - 1) / NT;           // staged values per thread and operand
     // stages: U in Ls[0], Ls[1]; V (when it differs) in Ls[2], Ls[3]
-    __shared__ double Ls[SAME ? 2 : 4][KS][kTriLd];
+    __shared__ double Ls[SAME ? 2 : 4][KS][TM + kLdsPad];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nb = (k + 15) / 16, T = nb * (nb + 1) / 2;
     const long long n_beg = static_cast<long long>(blockIdx.x) * slice;
     const long long n_end = n_beg + slice < n ? n_beg + slice : n;
     // this wave's output blocks: t = w, w + 8, ... in row-major order of the
     // upper triangle (uniform values)
-    int bi[kTriPerWave], bj[kTriPerWave];
+    int bi[PW], bj[PW];
 #pragma unroll
-    for (int b = 0; b < kTriPerWave; ++b) {
+    for (int b = 0; b < PW; ++b) {
         const int t = w + kTriWaves * b;
         int i = 0, rem = t;
         while (i < nb && rem >= nb - i) {
@@ -177,9 +177,9 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_gram_tri(const double *U, co
         bi[b] = t < T ? i : -1;
         bj[b] = t < T ? i + rem : -1;
     }
-    v4d acc[kTriPerWave];
+    v4d acc[PW];
 #pragma unroll
-    for (int b = 0; b < kTriPerWave; ++b) acc[b] = v4d{0, 0, 0, 0};
+    for (int b = 0; b < PW; ++b) acc[b] = v4d{0, 0, 0, 0};
     const int kp = nb * 16;   // staged columns (zero past k)
     double ru[R], rv[SAME ? 1 : R];
     auto fetch = [&](long long n0) {
@@ -213,13 +213,13 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_gram_tri(const double *U, co
     for (long long n0 = n_beg; n0 < n_end; n0 += KS) {
         const bool more = n0 + KS < n_end;
         if (more) fetch(n0 + KS);
-        const double(*Ua)[kTriLd] = Ls[st];
-        const double(*Vb)[kTriLd] = Ls[SAME ? st : 2 + st];
+        const double(*Ua)[TM + kLdsPad] = Ls[st];
+        const double(*Vb)[TM + kLdsPad] = Ls[SAME ? st : 2 + st];
 #pragma unroll
         for (int kk = 0; kk < KS / 4; ++kk) {
             const int kr = 4 * kk + (lane >> 4);
 #pragma unroll
-            for (int b = 0; b < kTriPerWave; ++b) {
+            for (int b = 0; b < PW; ++b) {
                 if (bi[b] < 0) break;
                 const double a = Ua[kr][16 * bi[b] + (lane & 15)];
                 const double v = Vb[kr][16 * bj[b] + (lane & 15)];
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_gram_tri(const double *U, co
     }
     double *out = part + static_cast<long long>(blockIdx.x) * k * k;
 #pragma unroll
-    for (int b = 0; b < kTriPerWave; ++b) {
+    for (int b = 0; b < PW; ++b) {
         if (bi[b] < 0) break;
         const int j = 16 * bj[b] + (lane & 15);
 #pragma unroll
@@ -538,16 +538,33 @@ struct Lob {
     {
         const int s = sym && p == q ? 1 : 0;
         if (s && p <= kTriMax) {   // narrow: all upper 16-blocks per block, slices of N
-            const long long want = std::min<long long>(256, L.nslices_gram);   // one block per CU
+            // one block per CU; two for the 8-block instance (the 4-block one
+            // would fit four, but more slices cost more in the reduction than
+            // they save)
+            const int nbk = (p + 15) / 16;
+            const long long want = std::min<long long>(nbk > 4 && nbk <= 8 ? 512 : 256, L.nslices_gram);
             const long long slice = (static_cast<long long>(N) + want - 1) / want;
             const long long sl = (slice + 15) / 16 * 16;
             const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
-            if (U == V)
-                hipLaunchKernelGGL(k_gram_tri<true>, dim3(nz), dim3(64 * kTriWaves), 0, st, U, V, static_cast<long long>(N), p,
-                                   static_cast<long long>(N), sl, at<double>(L.part));
-            else
-                hipLaunchKernelGGL(k_gram_tri<false>, dim3(nz), dim3(64 * kTriWaves), 0, st, U, V, static_cast<long long>(N), p,
-                                   static_cast<long long>(N), sl, at<double>(L.part));
+            // instances by the widest k they take (registers and LDS scale with it)
+            const long long ln = static_cast<long long>(N);
+            double *pt = at<double>(L.part);
+            const dim3 g(nz), b(64 * kTriWaves);
+            if (U == V) {
+                if (nbk <= 4)
+                    hipLaunchKernelGGL((k_gram_tri<true, 4>), g, b, 0, st, U, V, ln, p, ln, sl, pt);
+                else if (nbk <= 8)
+                    hipLaunchKernelGGL((k_gram_tri<true, 8>), g, b, 0, st, U, V, ln, p, ln, sl, pt);
+                else
+                    hipLaunchKernelGGL((k_gram_tri<true, kTriMax / 16>), g, b, 0, st, U, V, ln, p, ln, sl, pt);
+            } else {
+                if (nbk <= 4)
+                    hipLaunchKernelGGL((k_gram_tri<false, 4>), g, b, 0, st, U, V, ln, p, ln, sl, pt);
+                else if (nbk <= 8)
+                    hipLaunchKernelGGL((k_gram_tri<false, 8>), g, b, 0, st, U, V, ln, p, ln, sl, pt);
+                else
+                    hipLaunchKernelGGL((k_gram_tri<false, kTriMax / 16>), g, b, 0, st, U, V, ln, p, ln, sl, pt);
+            }
             hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 256)), dim3(256), 0, st,
                                at<double>(L.part), nz, p, q, 16, 1, at<double>(L.G));
             return;
