@@ -244,16 +244,31 @@ __global__ __launch_bounds__(64 * kTriWaves) void k_gram_tri(const double *U, co
 }
 
 // G[i][j] = sum_z part[z][i][j] in a fixed order (deterministic); with sym,
-// entries of tiles below the diagonal come from the mirrored entry.
-__global__ void k_gram_reduce(const double *part, int nz, int p, int q, int tile, int sym, double *G)
+// entries of tiles below the diagonal come from the mirrored entry.  A block
+// takes 64 entries; its 4 waves sum the slices z = w, w + 4, ... and wave 0
+// adds the four sums in order.
+constexpr int kRedGroups = 4;
+
+__global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const double *part, int nz, int p, int q, int tile,
+                                                                 int sym, double *G)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= p * q) return;
-    const int i = e / q, j = e % q;
-    const int src = sym && i / tile > j / tile ? j * q + i : e;
+    __shared__ double sums[kRedGroups][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int z = 0; z < nz; ++z) s += part[static_cast<long long>(z) * p * q + src];
-    G[e] = s;
+    if (e < p * q) {
+        const int i = e / q, j = e % q;
+        const int src = sym && i / tile > j / tile ? j * q + i : e;
+        for (int z = w; z < nz; z += kRedGroups) s += part[static_cast<long long>(z) * p * q + src];
+    }
+    sums[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && e < p * q) {
+        double t = sums[0][lane];
+#pragma unroll
+        for (int g = 1; g < kRedGroups; ++g) t += sums[g][lane];
+        G[e] = t;
+    }
 }
 
 // Y[n + j*ldy] = sum_{i<k} U[n + i*ldu] * C[i*mo + j]  for j < mo (C row-major k x mo).
@@ -565,7 +580,7 @@ struct Lob {
                 else
                     hipLaunchKernelGGL((k_gram_tri<false, kTriMax / 16>), g, b, 0, st, U, V, ln, p, ln, sl, pt);
             }
-            hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 256)), dim3(256), 0, st,
+            hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 64)), dim3(64 * kRedGroups), 0, st,
                                at<double>(L.part), nz, p, q, 16, 1, at<double>(L.G));
             return;
         }
@@ -578,7 +593,7 @@ struct Lob {
         const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
         hipLaunchKernelGGL(k_gram_partial, dim3(tp, tq, nz), dim3(256), 0, st, U, static_cast<long long>(N), p, V,
                            static_cast<long long>(N), q, static_cast<long long>(N), sl, at<double>(L.part), s);
-        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 64)), dim3(64 * kRedGroups), 0, st,
                            at<double>(L.part), nz, p, q, kGT, s, at<double>(L.G));
     }
 
