@@ -553,11 +553,10 @@ struct Lob {
     {
         const int s = sym && p == q ? 1 : 0;
         if (s && p <= kTriMax) {   // narrow: all upper 16-blocks per block, slices of N
-            // one block per CU; two for the 8-block instance (the 4-block one
-            // would fit four, but more slices cost more in the reduction than
-            // they save)
+            // one block per CU for the widest instance; the narrower ones fit
+            // two and four per CU
             const int nbk = (p + 15) / 16;
-            const long long want = std::min<long long>(nbk > 4 && nbk <= 8 ? 512 : 256, L.nslices_gram);
+            const long long want = std::min<long long>(nbk <= 4 ? 1024 : nbk <= 8 ? 512 : 256, L.nslices_gram);
             const long long slice = (static_cast<long long>(N) + want - 1) / want;
             const long long sl = (slice + 15) / 16 * 16;
             const int nz = static_cast<int>((static_cast<long long>(N) + sl - 1) / sl);
