@@ -276,7 +276,7 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const double *p
 // is a contiguous run of 16 n: wave w owns n in [16w, 16w+16) of the tile;
 // 16-column blocks past mo are skipped.
 __global__ __launch_bounds__(256) void k_block_update(const double *U, long long ldu, int k, const double *C, int mo,
-                                                      double *Y, long long ldy, long long n)
+                                                      double *Y, long long ldy, long long n, double *Y2, int jsplit)
 {
     // two LDS stages: the next 16 rows of C and U are read into registers
     // while the MFMAs run on these (one barrier per step)
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_block_update(const double *U, long long
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = j0 + 16 * jt + 4 * r + (lane >> 4);
-            if (j < mo) Y[nn + j * ldy] = acc[jt][r];
+            if (j < mo) (j < jsplit ? Y + j * ldy : Y2 + (j - jsplit) * ldy)[nn] = acc[jt][r];
         }
     }
 }
@@ -360,7 +360,7 @@ template <int JB>
 __global__ __launch_bounds__(256) void k_block_update_wide(
     const double *U, long long ldu, int i_begin, int i_end,
                                                            const double *C, int mo, RowSpan span, double *Y,
-                                                           long long ldy, long long n)
+                                                           long long ldy, long long n, double *Y2, int jsplit)
 {
     constexpr int W = 16 * JB;
     constexpr int RC = (kK * W + 255) / 256;     // C values per thread and stage
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void k_block_update_wide(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = 16 * jt + 4 * r + (lane >> 4);
-            if (j < mo) Y[nn + j * ldy] = acc[jt][r];
+            if (j < mo) (j < jsplit ? Y + j * ldy : Y2 + (j - jsplit) * ldy)[nn] = acc[jt][r];
         }
     }
 }
@@ -607,9 +607,12 @@ struct Lob {
         return hipStreamSynchronize(st) == hipSuccess && ok();
     }
 
-    // Y (N x mo) = U (N x k) C (k x mo, host row-major)
-    bool update(const double *U, int k, const std::vector<double> &C, int mo, double *Y)
+    // Y (N x mo) = U (N x k) C (k x mo, host row-major); with Y2, columns
+    // from jsplit on go to Y2 instead (column jsplit + c to Y2[:, c])
+    bool update(const double *U, int k, const std::vector<double> &C, int mo, double *Y, double *Y2 = nullptr,
+                int jsplit = -1)
     {
+        if (!Y2) jsplit = mo;
         if (hipMemcpyAsync(at<double>(L.C), C.data(), C.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
         // one 64-column tile of k_block_update reads U once already; it is
@@ -642,26 +645,26 @@ struct Lob {
             const double *Cd = at<double>(L.C);
             if (mo <= 32)
                 hipLaunchKernelGGL(k_block_update_wide<2>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln);
+                                   Y, ln, ln, Y2, jsplit);
             else if (mo <= 48)
                 hipLaunchKernelGGL(k_block_update_wide<3>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln);
+                                   Y, ln, ln, Y2, jsplit);
             else if (mo <= 128)
                 hipLaunchKernelGGL(k_block_update_wide<8>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln);
+                                   Y, ln, ln, Y2, jsplit);
             else if (mo <= 144)
                 hipLaunchKernelGGL(k_block_update_wide<9>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln);
+                                   Y, ln, ln, Y2, jsplit);
             else if (mo <= 208)
                 hipLaunchKernelGGL(k_block_update_wide<13>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln);
+                                   Y, ln, ln, Y2, jsplit);
             else
                 hipLaunchKernelGGL(k_block_update_wide<kTriMax / 16>, grid, dim3(256), 0, st, U, ln, i_begin, i_end,
-                                   Cd, mo, sp, Y, ln, ln);
+                                   Cd, mo, sp, Y, ln, ln, Y2, jsplit);
         } else {
             hipLaunchKernelGGL(k_block_update, dim3(nblk(static_cast<long long>(N), kT), nblk(mo, kT)), dim3(256), 0,
                                st, U, static_cast<long long>(N), k, at<double>(L.C), mo, Y, static_cast<long long>(N),
-                               static_cast<long long>(N));
+                               static_cast<long long>(N), Y2, jsplit);
         }
         // C is reused by the next call: wait before the host buffer changes
         return hipStreamSynchronize(st) == hipSuccess && ok();
@@ -934,14 +937,12 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
                 Ce[static_cast<size_t>(i) * 2 * m + j] = V[static_cast<size_t>(i) * k + j];
                 if (i >= m) Ce[static_cast<size_t>(i) * 2 * m + m + j] = V[static_cast<size_t>(i) * k + j];
             }
-        if (!lb.update(S, k, Ce, 2 * m, T) || !lb.update(AS, k, Ce, 2 * m, AT)) return finish(SMG_EHIP);
+        // X and AX into the scratch pair (then swapped in), P and AP straight
+        // into their own buffers (the gathered copies in S are what is read)
+        if (!lb.update(S, k, Ce, 2 * m, T, P, m) || !lb.update(AS, k, Ce, 2 * m, AT, AP, m))
+            return finish(SMG_EHIP);
         std::swap(S, T);
         std::swap(AS, AT);
-        if (hipMemcpyAsync(P, S + static_cast<size_t>(m) * N, N * m * 8, hipMemcpyDeviceToDevice, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(AP, AS + static_cast<size_t>(m) * N, N * m * 8, hipMemcpyDeviceToDevice, st) !=
-                hipSuccess)
-            return finish(SMG_EHIP);
         have_p = true;
     }
     if (hipMemcpyAsync(X, S, N * m * 8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
