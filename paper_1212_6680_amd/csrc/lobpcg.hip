@@ -437,16 +437,6 @@ __global__ __launch_bounds__(256) void k_block_update_wide(
     }
 }
 
-// R[:, c] = AX[:, c] - theta[c] X[:, c]
-__global__ void k_block_resid(const double *AX, const double *X, const double *theta, double *R, long long ld,
-                              long long n, int m)
-{
-    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (e >= n || c >= m) return;
-    R[e + c * ld] = AX[e + c * ld] - theta[c] * X[e + c * ld];
-}
-
 // part[c][z] = sum over slice z of U[:, c] .* V[:, c]
 __global__ __launch_bounds__(256) void k_coldot_partial(const double *U, const double *V, long long ld, long long n,
                                                         long long slice, double *part, int nslices)
@@ -462,6 +452,42 @@ __global__ __launch_bounds__(256) void k_coldot_partial(const double *U, const d
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) part[c * nslices + z] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+// R = AX - X diag(theta) with the column sums of R^2 and X^2 in one pass
+// (the slicing and summation order of k_coldot_partial): part[c][z] for R,
+// part[m + c][z] for X.
+__global__ __launch_bounds__(256) void k_block_resid_dots(const double *AX, const double *X, const double *theta,
+                                                          double *R, long long ld, long long n, long long slice,
+                                                          double *part, int nslices, int m)
+{
+    __shared__ double lds[2][4];
+    const int c = blockIdx.y, z = blockIdx.x;
+    const long long beg = static_cast<long long>(z) * slice;
+    const long long end = beg + slice < n ? beg + slice : n;
+    const double th = theta[c];
+    double sr = 0.0, sx = 0.0;
+    for (long long e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        const double xv = X[e + c * ld];
+        const double rv = AX[e + c * ld] - th * xv;
+        R[e + c * ld] = rv;
+        sr += rv * rv;
+        sx += xv * xv;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_down(sr, off, 64);
+        sx += __shfl_down(sx, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = sr;
+        lds[1][threadIdx.x >> 6] = sx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[c * nslices + z] = lds[0][0] + lds[0][1] + lds[0][2] + lds[0][3];
+        part[(m + c) * nslices + z] = lds[1][0] + lds[1][1] + lds[1][2] + lds[1][3];
+    }
 }
 
 __global__ void k_coldot_reduce(const double *part, int nslices, int m, double *out)
@@ -868,10 +894,16 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
         // residuals and their relative norms
         if (hipMemcpyAsync(theta_d, theta.data(), m * 8, hipMemcpyHostToDevice, st) != hipSuccess)
             return finish(SMG_EHIP);
-        hipLaunchKernelGGL(k_block_resid, dim3(nblk(ld, 256), m), dim3(256), 0, st, AS, S, theta_d, R, ld, ld, m);
         double *cout = lb.at<double>(lb.L.cout);
-        lb.coldots(R, R, m, cout, lb.at<double>(lb.L.cpart));
-        lb.coldots(S, S, m, cout + m, lb.at<double>(lb.L.cpart) + static_cast<size_t>(m) * lb.L.nslices_col);
+        {
+            // R and the column norms of R and X in one pass
+            const int ns = lb.L.nslices_col;
+            const long long slice = (ld + ns - 1) / ns;
+            double *cp = lb.at<double>(lb.L.cpart);
+            hipLaunchKernelGGL(k_block_resid_dots, dim3(ns, m), dim3(256), 0, st, AS, S, theta_d, R, ld, ld, slice, cp,
+                               ns, m);
+            hipLaunchKernelGGL(k_coldot_reduce, dim3(nblk(2 * m, 64)), dim3(64), 0, st, cp, ns, 2 * m, cout);
+        }
         std::vector<double> nr(2 * m);
         if (hipMemcpyAsync(nr.data(), cout, 2 * m * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess || !lb.ok())
