@@ -511,18 +511,21 @@ __global__ void k_scale_cols(double *X, double *AX, const double *nrm2, long lon
 }
 
 // dst[:, c] = src[:, idx[c]]
-__global__ void k_gather_cols(const double *src, double *dst, const int *idx, long long ld, long long n, int m)
+// dst[:, c] = src[:, idx[c]] (times scale[c] when scale is given)
+__global__ void k_gather_cols(const double *src, double *dst, const int *idx, const double *scale, long long ld,
+                              long long n, int m)
 {
     const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (e >= n || c >= m) return;
-    dst[e + c * ld] = src[e + static_cast<long long>(idx[c]) * ld];
+    const double v = src[e + static_cast<long long>(idx[c]) * ld];
+    dst[e + c * ld] = scale ? scale[c] * v : v;
 }
 
 inline unsigned nblk(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
 
 struct LobLayout {
-    size_t S, AS, T, AT, P, AP, R, part, G, C, theta, cpart, cout, idx, total;
+    size_t S, AS, T, AT, P, AP, R, part, G, C, theta, cpart, cout, idx, gscale, total;
     int nslices_gram, nslices_col;
 };
 
@@ -559,6 +562,7 @@ LobLayout lob_layout(size_t N, int m)
     L.cpart = take(k3 * L.nslices_col * 8 * 2);
     L.cout = take(k3 * 8 * 2);
     L.idx = take(k3 * 4);
+    L.gscale = take(k3 * 8);
     L.total = off;
     return L;
 }
@@ -714,14 +718,18 @@ struct Lob {
                            nrm, static_cast<long long>(N), static_cast<long long>(N), mcols);
     }
 
-    bool gather(const double *src, double *dst, const std::vector<int> &idx)
+    // dst[:, t] = src[:, idx[t]], times scale[t] (host) when given
+    bool gather(const double *src, double *dst, const std::vector<int> &idx, const double *scale = nullptr)
     {
         if (idx.empty()) return true;
         if (hipMemcpyAsync(at<int>(L.idx), idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
+        if (scale && hipMemcpyAsync(at<double>(L.gscale), scale, idx.size() * 8, hipMemcpyHostToDevice, st) !=
+                         hipSuccess)
+            return false;
         hipLaunchKernelGGL(k_gather_cols, dim3(nblk(static_cast<long long>(N), 256), static_cast<int>(idx.size())),
-                           dim3(256), 0, st, src, dst, at<int>(L.idx), static_cast<long long>(N),
-                           static_cast<long long>(N), static_cast<int>(idx.size()));
+                           dim3(256), 0, st, src, dst, at<int>(L.idx), scale ? at<double>(L.gscale) : nullptr,
+                           static_cast<long long>(N), static_cast<long long>(N), static_cast<int>(idx.size()));
         return hipStreamSynchronize(st) == hipSuccess && ok();
     }
 
@@ -885,7 +893,7 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
     for (int i = 0; i < m; ++i) theta[i] = w[i];
 
     bool have_p = false;
-    std::vector<double> rr(m), xx(m), res(m);
+    std::vector<double> rr(m), xx(m), res(m), pinv(m, 1.0);
     std::vector<int> active, all(m);
     for (int i = 0; i < m; ++i) all[i] = i;
     int it = 0;
@@ -937,9 +945,14 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
         if (smg_matvec(h, W, AW, nj, ld, stream) != SMG_OK) return finish(SMG_EHIP);
         int k = m + nj;
         if (have_p) {
+            // P's columns come out of the last Rayleigh-Ritz step with norms
+            // known from its coefficients (S was orthonormal), so the gather
+            // normalises them itself
             double *Pj = S + static_cast<size_t>(k) * N, *APj = AS + static_cast<size_t>(k) * N;
-            if (!lb.gather(P, Pj, active) || !lb.gather(AP, APj, active)) return finish(SMG_EHIP);
-            lb.normalize(Pj, APj, nj);
+            std::vector<double> sc(nj);
+            for (int t = 0; t < nj; ++t) sc[t] = pinv[active[t]];
+            if (!lb.gather(P, Pj, active, sc.data()) || !lb.gather(AP, APj, active, sc.data()))
+                return finish(SMG_EHIP);
             k += nj;
         }
         int rc = lb.cholqr2(S, AS, T, AT, k);
@@ -969,6 +982,15 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
                 Ce[static_cast<size_t>(i) * 2 * m + j] = V[static_cast<size_t>(i) * k + j];
                 if (i >= m) Ce[static_cast<size_t>(i) * 2 * m + m + j] = V[static_cast<size_t>(i) * k + j];
             }
+        // 1 / ||P_new[:, j]|| = 1 / ||C_P[:, j]|| for orthonormal S (1 for a zero column)
+        for (int j = 0; j < m; ++j) {
+            double q = 0.0;
+            for (int i = m; i < k; ++i) {
+                const double c = Ce[static_cast<size_t>(i) * 2 * m + m + j];
+                q += c * c;
+            }
+            pinv[j] = q > 0.0 ? 1.0 / std::sqrt(q) : 1.0;
+        }
         // X and AX into the scratch pair (then swapped in), P and AP straight
         // into their own buffers (the gathered copies in S are what is read)
         if (!lb.update(S, k, Ce, 2 * m, T, P, m) || !lb.update(AS, k, Ce, 2 * m, AT, AP, m))
