@@ -733,9 +733,26 @@ struct Lob {
         return hipStreamSynchronize(st) == hipSuccess && ok();
     }
 
+    // Y = A X for cols columns (the grid operator; stream-ordered)
+    bool apply_a(const double *X, double *Y, int cols)
+    {
+        return cols == 0 || smg_matvec(h, X, Y, cols, static_cast<int64_t>(N), st) == SMG_OK;
+    }
+
+    // A S after S <- S C (C k x mo): from the operator when the basis is wide
+    // (a stencil pass over the mo new columns moves 16 N mo bytes, while the
+    // k x mo update is bound by its N k mo MFMA flops), else by the same update
+    // of A S.  Y receives the new A S; AS itself is only read.
+    static constexpr int kStencilK = 96;
+    bool new_as(const double *AS, int k, const std::vector<double> &C, int mo, const double *Snew, double *Y)
+    {
+        return k >= kStencilK ? apply_a(Snew, Y, mo) : update(AS, k, C, mo, Y);
+    }
+
     // Cholesky QR twice of S (N x k). S and the scratch T swap roles, so after
-    // two passes the result is back in S; A S takes the product of the two
-    // (upper triangular) factors in one update instead of one per pass.
+    // two passes the result is back in S; A S follows the two (upper
+    // triangular) factors at once: by their product, or for a wide basis by
+    // the operator.
     int cholqr2(double *&S, double *&AS, double *&T, double *&AT, int k)
     {
         const size_t kk = static_cast<size_t>(k) * k;
@@ -747,7 +764,7 @@ struct Lob {
             if (!dense::cholesky(k, G.data())) {
                 if (pass == 0) return 0;
                 // keep A S in step with the once-factored S
-                if (!update(AS, k, C1, k, AT)) return -1;
+                if (!new_as(AS, k, C1, k, S, AT)) return -1;
                 std::swap(AS, AT);
                 return 0;
             }
@@ -756,13 +773,16 @@ struct Lob {
             if (!update(S, k, C, k, T)) return -1;
             std::swap(S, T);
         }
-        std::vector<double> Cp(kk, 0.0);
-        for (int i = 0; i < k; ++i)
-            for (int l = i; l < k; ++l) {
-                const double c = C1[i * k + l];
-                for (int j = l; j < k; ++j) Cp[i * k + j] += c * C2[l * k + j];
-            }
-        if (!update(AS, k, Cp, k, AT)) return -1;
+        std::vector<double> Cp;
+        if (k < kStencilK) {
+            Cp.assign(kk, 0.0);
+            for (int i = 0; i < k; ++i)
+                for (int l = i; l < k; ++l) {
+                    const double c = C1[i * k + l];
+                    for (int j = l; j < k; ++j) Cp[i * k + j] += c * C2[l * k + j];
+                }
+        }
+        if (!new_as(AS, k, Cp, k, S, AT)) return -1;
         std::swap(AS, AT);
         return 1;
     }
@@ -790,7 +810,7 @@ struct Lob {
         for (int i = 0; i < k; ++i)
             for (int jj = 0; jj < kk; ++jj)
                 Cm[i * kk + jj] = dinv[i] * V[i * k + keep[jj]] / std::sqrt(w[keep[jj]]);
-        if (!update(S, k, Cm, kk, T) || !update(AS, k, Cm, kk, AT)) return -1;
+        if (!update(S, k, Cm, kk, T) || !new_as(AS, k, Cm, kk, T, AT)) return -1;
         std::swap(S, T);
         std::swap(AS, AT);
         return kk;
@@ -887,7 +907,7 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
     V.resize(static_cast<size_t>(m) * m);
     w.resize(m);
     if (!dense::sym_eig(m, G.data(), V.data(), w.data())) return finish(SMG_EBREAKDOWN);
-    if (!lb.update(S, m, V, m, T) || !lb.update(AS, m, V, m, AT)) return finish(SMG_EHIP);
+    if (!lb.update(S, m, V, m, T) || !lb.new_as(AS, m, V, m, T, AT)) return finish(SMG_EHIP);
     std::swap(S, T);
     std::swap(AS, AT);
     for (int i = 0; i < m; ++i) theta[i] = w[i];
@@ -991,10 +1011,13 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
             }
             pinv[j] = q > 0.0 ? 1.0 / std::sqrt(q) : 1.0;
         }
-        // X and AX into the scratch pair (then swapped in), P and AP straight
-        // into their own buffers (the gathered copies in S are what is read)
-        if (!lb.update(S, k, Ce, 2 * m, T, P, m) || !lb.update(AS, k, Ce, 2 * m, AT, AP, m))
-            return finish(SMG_EHIP);
+        // X into the scratch (then swapped in), P straight into its own buffer
+        // (the gathered copy in S is what is read); AX and AP likewise, by the
+        // operator for a wide basis
+        if (!lb.update(S, k, Ce, 2 * m, T, P, m)) return finish(SMG_EHIP);
+        const bool ok_as = k >= Lob::kStencilK ? lb.apply_a(T, AT, m) && lb.apply_a(P, AP, m)
+                                               : lb.update(AS, k, Ce, 2 * m, AT, AP, m);
+        if (!ok_as) return finish(SMG_EHIP);
         std::swap(S, T);
         std::swap(AS, AT);
         have_p = true;
