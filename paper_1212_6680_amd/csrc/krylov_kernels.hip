@@ -307,6 +307,53 @@ __device__ __forceinline__ void k_resid_tiled_body(const ResidArgs &a, const Blk
 }
 SMG_GROUPED_KERNEL_XCD(k_resid_tiled, kTileThreads, ResidArgs)
 
+// y = A x for nrhs columns, marching in z like k_update_p_q_tiled: a block
+// owns a kTX x kTY tile, a run of kchunk planes and one column; x at k-1, k,
+// k+1 stays in registers and the in-plane neighbours come from an LDS tile
+// with a one-point halo, so x is read about once.
+__global__ __launch_bounds__(kTileThreads) void k_matvec7_tiled(const double *x, double *y, long long ld, int nx,
+                                                                int ny, int nz, double cx, double cy, double cz,
+                                                                int kchunk, int nzb)
+{
+    __shared__ double tile[(kTY + 2) * (kTX + 2)];
+    const Blk blk = blk_xcd();
+    const int r = blk.z / nzb, zb = blk.z % nzb;
+    const double *xr = x + r * ld;
+    double *yr = y + r * ld;
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+    const int i = blk.x * kTX + tx, j = blk.y * kTY + ty;
+    const bool in = i < nx && j < ny;
+    const long long pl = static_cast<long long>(nx) * ny;
+    const long long c2 = static_cast<long long>(j) * nx + i;
+    const int k0 = zb * kchunk, k1 = min(nz, k0 + kchunk);
+    int hy, hx;
+    tile_halo(threadIdx.x, hy, hx);
+    int hi = -1, hj = -1;
+    if (hy >= 0) {
+        hi = blk.x * kTX + hx - 1;
+        hj = blk.y * kTY + hy - 1;
+    }
+    const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const long long hc2 = static_cast<long long>(hj) * nx + hi;
+    const double diag = 2.0 * (cx + cy + cz);
+    double xm = (in && k0 > 0 && k0 < nz) ? xr[(k0 - 1) * pl + c2] : 0.0;
+    double xc = (in && k0 < nz) ? xr[k0 * pl + c2] : 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const double xn = (in && k + 1 < nz) ? xr[(k + 1) * pl + c2] : 0.0;
+        tile[(ty + 1) * (kTX + 2) + tx + 1] = xc;
+        if (hy >= 0) tile[hy * (kTX + 2) + hx] = hin ? xr[k * pl + hc2] : 0.0;
+        __syncthreads();
+        if (in) {
+            const int cc = (ty + 1) * (kTX + 2) + tx + 1;
+            yr[k * pl + c2] = diag * xc - cx * (tile[cc - 1] + tile[cc + 1]) -
+                              cy * (tile[cc - (kTX + 2)] + tile[cc + (kTX + 2)]) - cz * (xm + xn);
+        }
+        __syncthreads();
+        xm = xc;
+        xc = xn;
+    }
+}
+
 __device__ __forceinline__ void k_update_xr_body(const UpdXRArgs &a, const Blk &blk)
 {
     __shared__ double lds[kRB / 64];
@@ -422,6 +469,18 @@ void launch_fill(double *dst, double v, size_t n, hipStream_t st)
 void launch_matvec7(const double *x, double *y, long long ld, int nrhs, int nx, int ny, int nz, double cx, double cy,
                     double cz, hipStream_t st)
 {
+    // enough blocks to fill the chip; each marches kchunk planes of one column
+    const long long gx = (nx + kTX - 1) / kTX, gy = (ny + kTY - 1) / kTY;
+    long long nzb = 2048 / (gx * gy * nrhs);
+    nzb = nzb < 1 ? 1 : (nzb > nz ? nz : nzb);
+    const int kchunk = static_cast<int>((nz + nzb - 1) / nzb);
+    nzb = (nz + kchunk - 1) / kchunk;
+    if (gx * gy <= 65535 && nzb * nrhs <= 65535) {
+        hipLaunchKernelGGL(k_matvec7_tiled, dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy),
+                                                 static_cast<unsigned>(nzb * nrhs)),
+                           dim3(kTileThreads), 0, st, x, y, ld, nx, ny, nz, cx, cy, cz, kchunk, static_cast<int>(nzb));
+        return;
+    }
     const dim3 grid((nx * ny + 255) / 256, nz, nrhs);
     hipLaunchKernelGGL(k_matvec7, grid, dim3(256), 0, st, x, y, ld, nx, ny, nz, cx, cy, cz);
 }
