@@ -955,10 +955,15 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
         const int nj = static_cast<int>(active.size());
         // W = T R_J into S[:, m : m+nj]
         double *W = S + static_cast<size_t>(m) * N, *AW = AS + static_cast<size_t>(m) * N;
-        if (!lb.gather(R, T, active)) return finish(SMG_EHIP);
+        // R_J: R itself while every column is active, else gathered into T
+        const double *RJ = R;
+        if (nj < m) {
+            if (!lb.gather(R, T, active)) return finish(SMG_EHIP);
+            RJ = T;
+        }
         if (o->precond == SMG_PRECOND_SMG) {
-            if (smg_apply(h, T, W, nj, ld, stream) != SMG_OK) return finish(SMG_EHIP);
-        } else if (hipMemcpyAsync(W, T, N * nj * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+            if (smg_apply(h, RJ, W, nj, ld, stream) != SMG_OK) return finish(SMG_EHIP);
+        } else if (hipMemcpyAsync(W, RJ, N * nj * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
             return finish(SMG_EHIP);
         }
         lb.normalize(W, nullptr, nj);
