@@ -181,3 +181,72 @@ def unflatten(flat: np.ndarray):
 
 
 NPARAMS = sum(27 * ci * co + co for ci, co in zip(CHANNELS[:-1], CHANNELS[1:]))
+
+
+# ---------------------------------------------------------------------------
+# Flexible PCG with the learned post-smoother (the form beside the paper).
+# ---------------------------------------------------------------------------
+FALLBACK_NONE, FALLBACK_SR, FALLBACK_NONFINITE, FALLBACK_STAGNATION = "none", "sr", "nonfinite", "stagnation"
+
+
+def correction(params, r, s, shape, c, quantize=None):
+    """s + sigma N(r' / (cbar sigma)) with r' = r - A s, cbar = (cx + cy + cz)/3 and
+    sigma = rms(r' / cbar): the preconditioned residual after one V-cycle without
+    post-smoothing, corrected by the network on the normalised remaining residual."""
+    from oracle import oracle as O
+    nx, ny, nz = shape
+    rp = r - O.matvec(s, shape, c)
+    cbar = (c[0] + c[1] + c[2]) / 3.0
+    sigma = float(np.sqrt(np.mean((rp / cbar) ** 2)))
+    with np.errstate(over="ignore", invalid="ignore"):      # a corrupted network may overflow
+        y = forward(params, (rp / (cbar * sigma)).reshape(nz, ny, nx), quantize=quantize).ravel()
+        return s + sigma * y, sigma
+
+
+def fpcg_learned(b, shape, c, smg, params, rtol=1e-8, max_iter=500, x0=None, quantize=None):
+    """Algorithm 1 of Section 2 with beta from equation (2), whose flexibility
+    admits a nonlinear preconditioner: s_k = correction(T r_k) with T = smg (one
+    V-cycle, normally without post-smoothing).  The network is dropped for the
+    rest of the solve (s_k = T r_k from then on) when
+      * the corrected s_k has a non-finite entry          -> "nonfinite" at iteration k,
+      * (s_k, r_k) <= 0 for the corrected s_k              -> "sr" at iteration k,
+      * ||r_{k+1}|| > 0.9 ||r_{k-1}|| (k >= 1)             -> "stagnation" from iteration k+1.
+    beta_k = (s_k, r_k - r_{k-1}) / (s_{k-1}, r_{k-1}), with r_{k-1} stored.
+    Returns (x, iterations, relative residual history, fallback iteration, reason)."""
+    from oracle import oracle as O
+    b = np.asarray(b, dtype=np.float64).ravel()
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64).ravel()
+    r = b - O.matvec(x, shape, c)
+    bden = np.linalg.norm(b) or 1.0
+    rels = [np.linalg.norm(r) / bden]
+    active, fb_iter, fb_reason = True, -1, FALLBACK_NONE
+    p = r_prev = None
+    sr_prev = 0.0
+    k = 0
+    while k < max_iter and rels[-1] > rtol:
+        s = smg.apply(r)
+        if active:
+            sl, _ = correction(params, r, s, shape, c, quantize)
+            if not np.all(np.isfinite(sl)):
+                active, fb_iter, fb_reason = False, k, FALLBACK_NONFINITE
+            elif not float(sl @ r) > 0.0:
+                active, fb_iter, fb_reason = False, k, FALLBACK_SR
+            else:
+                s = sl
+        sr = float(s @ r)
+        if k == 0:
+            p = s.copy()
+        else:
+            beta = (sr - float(s @ r_prev)) / sr_prev
+            p = s + beta * p
+        q = O.matvec(p, shape, c)
+        alpha = sr / float(p @ q)
+        r_prev = r.copy()
+        x = x + alpha * p
+        r = r - alpha * q
+        sr_prev = sr
+        rels.append(np.linalg.norm(r) / bden)
+        if active and k >= 1 and rels[k + 1] > 0.9 * rels[k - 1]:
+            active, fb_iter, fb_reason = False, k + 1, FALLBACK_STAGNATION
+        k += 1
+    return x, k, np.array(rels), fb_iter, fb_reason

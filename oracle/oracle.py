@@ -53,7 +53,7 @@ def lib():
         L.oracle_smg_plane_level_ny.argtypes = [p, i, i, i]
         L.oracle_smg_line_coef.argtypes = [p, i, i, i, i, p]
         L.oracle_smg_plane_solve.argtypes = [p, i, i, p, p]
-        L.oracle_krylov.argtypes = [p, i, i, i, i, d, d, d, p, p, d, i, p, p,
+        L.oracle_krylov.argtypes = [p, i, i, i, i, d, d, d, p, p, d, i, i, p, p,
                                     C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_krylov.restype = i
         L.oracle_num_threads.restype = i
@@ -157,19 +157,22 @@ class KrylovResult:
 
 
 def krylov(method: int, b: np.ndarray, shape, c=(1.0, 1.0, 1.0), smg: SMG | None = None,
-           x0: np.ndarray | None = None, rtol=1e-8, max_iter=500, history=True) -> KrylovResult:
-    """Algorithm 1 with beta from (1) [PCG], (2) [FPCG] or 0 [PSD]; T = smg or identity."""
+           x0: np.ndarray | None = None, rtol=1e-8, max_iter=500, history=True, stop="2") -> KrylovResult:
+    """Algorithm 1 with beta from (1) [PCG], (2) [FPCG] or 0 [PSD]; T = smg or identity.
+    stop "2": ||r_k||_2 <= rtol ||b||_2; stop "c": sqrt|(T r_k, r_k)| <= rtol sqrt|(T b, b)|."""
     nx, ny, nz = shape
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64).reshape(-1)
     hist = np.full(max_iter + 1, np.nan) if history else None
-    histC = np.full(max(max_iter, 1), np.nan) if history else None
+    histC = np.full(max_iter + 1, np.nan) if history else None
     it, rel, trel = C.c_int(0), C.c_double(0), C.c_double(0)
+    stop_c = 1 if stop == "c" else 0
     st = lib().oracle_krylov(smg.h if smg is not None else None, method, nx, ny, nz,
-                             c[0], c[1], c[2], _ptr(b), _ptr(x), rtol, max_iter,
+                             c[0], c[1], c[2], _ptr(b), _ptr(x), rtol, stop_c, max_iter,
                              _ptr(hist) if history else None, _ptr(histC) if history else None,
                              C.byref(it), C.byref(rel), C.byref(trel))
     k = it.value
+    nc = k + (1 if stop_c and st == 0 else 0)
     return KrylovResult(st, k, rel.value, trel.value,
                         hist[:k + 1] if history else None,
-                        histC[:k] if history else None, x)
+                        histC[:nc] if history else None, x)

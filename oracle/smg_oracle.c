@@ -506,34 +506,38 @@ static double dot(size_t n, const double *a, const double *b)
 enum { ORACLE_PCG = 0, ORACLE_FPCG = 1, ORACLE_PSD = 2 };
 
 /* Returns 0 converged, 1 max_iter reached, -4 breakdown (non-finite scalar).
+ * Stopping test: ||r_k||_2 <= rtol ||b||_2 on the recursive residual, or,
+ * with stop_c, sqrt|(s_k, r_k)| <= rtol sqrt|(T b, b)| (the C-norm ratio
+ * plotted in Figs. 2 and 5), tested as soon as s_k = T r_k is formed.
  * hist (nullable, max_iter+1 entries) receives ||r_k||_2/||b||_2 for
- * k = 0..iters; histC (nullable, max_iter entries) receives
+ * k = 0..iters; histC (nullable, max_iter+1 entries) receives
  * sqrt|(s_k, r_k)| / sqrt|(T b, b)| for every k at which s_k was formed. */
 int oracle_krylov(oracle_smg *S, int method, int nx, int ny, int nz, double cx, double cy,
-                  double cz, const double *b, double *x, double rtol, int max_iter,
+                  double cz, const double *b, double *x, double rtol, int stop_c, int max_iter,
                   double *hist, double *histC, int *iters_out, double *rel_out,
                   double *true_rel_out)
 {
     const size_t n = (size_t)nx * ny * nz;
     double *r = zalloc(n), *s = zalloc(n), *p = zalloc(n), *q = zalloc(n), *rp = zalloc(n);
-    int status = 1, k = 0;
+    int status = 1, k = 0, cconv = 0;
     oracle_matvec(nx, ny, nz, cx, cy, cz, x, q);
     for (size_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     const double bnorm = sqrt(dot(n, b, b));
     const double bden = bnorm > 0.0 ? bnorm : 1.0;
     double rel = sqrt(dot(n, r, r)) / bden;
     double cden = 0.0;
-    if (histC) {                                  /* (T b, b) for the C-norm */
+    if (histC || stop_c) {                        /* (T b, b) for the C-norm */
         if (S) oracle_smg_apply(S, b, s); else memcpy(s, b, n * sizeof(double));
         cden = sqrt(fabs(dot(n, s, b)));
         if (cden == 0.0) cden = 1.0;
     }
     if (hist) hist[0] = rel;
     double sr_prev = 0.0;
-    for (k = 0; k < max_iter && rel > rtol; ++k) {
+    for (k = 0; k < max_iter && (stop_c || rel > rtol); ++k) {
         if (S) oracle_smg_apply(S, r, s); else memcpy(s, r, n * sizeof(double));
         const double sr = dot(n, s, r);
         if (histC) histC[k] = sqrt(fabs(sr)) / cden;
+        if (stop_c && !(sqrt(fabs(sr)) / cden > rtol)) { cconv = 1; break; }
         double beta = 0.0;
         if (k > 0 && method == ORACLE_PCG) beta = sr / sr_prev;                       /* (1) */
         if (k > 0 && method == ORACLE_FPCG) beta = (sr - dot(n, s, rp)) / sr_prev;    /* (2) */
@@ -553,7 +557,7 @@ int oracle_krylov(oracle_smg *S, int method, int nx, int ny, int nz, double cx, 
         rel = sqrt(dot(n, r, r)) / bden;
         if (hist) hist[k + 1] = rel;
     }
-    if (status == 1 && rel <= rtol) status = 0;
+    if (status == 1 && (stop_c ? cconv : rel <= rtol)) status = 0;
     oracle_matvec(nx, ny, nz, cx, cy, cz, x, q);
     for (size_t i = 0; i < n; ++i) q[i] = b[i] - q[i];
     if (true_rel_out) *true_rel_out = sqrt(dot(n, q, q)) / bden;

@@ -139,3 +139,24 @@ def test_history_c_norm_starts_at_one_for_zero_guess():
     r = O.krylov(O.FPCG, b, shape, c, O.SMG(shape, c, 1, 0))
     assert abs(r.histC[0] - 1.0) < 1e-14
     assert r.hist[0] == pytest.approx(1.0, abs=1e-15)
+
+
+def test_cnorm_stopping_without_preconditioner_is_2norm_stopping():
+    """With T = I the C-norm ratio sqrt|(T r, r)| / sqrt|(T b, b)| is the
+    2-norm ratio, so both stopping rules end at the same step; with SMG the
+    C-norm history starts at sqrt|(T r_0, r_0)| / sqrt|(T b, b)| (= 1 for x0 = 0)."""
+    shape, c, b = _problem(12, seed=6)
+    r2 = O.krylov(O.PCG, b, shape, c, None, rtol=1e-7, max_iter=200)
+    rc = O.krylov(O.PCG, b, shape, c, None, rtol=1e-7, max_iter=200, stop="c")
+    assert r2.status == 0 and rc.status == 0 and r2.iters == rc.iters
+    assert np.allclose(rc.histC, r2.hist[:len(rc.histC)], rtol=1e-12, atol=0)
+    S = O.SMG(shape, c, 1, 0)
+    f = O.krylov(O.FPCG, b, shape, c, S, rtol=1e-7, stop="c")
+    assert f.status == 0 and f.histC[0] == pytest.approx(1.0, rel=1e-14)
+    assert f.histC[-1] <= 1e-7 < f.histC[-2]
+    # a random x0: the first ratio is |(T r0, r0)|^(1/2) / |(T b, b)|^(1/2)
+    x0 = synth.uniform_pm1(8, b.size)
+    g = O.krylov(O.FPCG, b, shape, c, S, x0=x0, rtol=1e-7, stop="c")
+    r0 = b - O.matvec(x0, shape, c)
+    want = np.sqrt(abs(S.apply(r0) @ r0) / abs(S.apply(b) @ b))
+    assert g.histC[0] == pytest.approx(want, rel=1e-12)

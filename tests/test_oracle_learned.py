@@ -133,3 +133,73 @@ def test_quantized_loss_without_rounding_equals_plain():
     b = L.loss_and_grads(params, x, t, quantize=lambda v: v)
     assert a[0] == b[0]
     assert np.array_equal(L.flatten(a[1]), L.flatten(b[1]))
+
+
+# --- the flexible-PCG loop with the learned correction ----------------------
+
+def _loop_problem(n=12, seed=1):
+    import synth
+    from oracle import oracle as O
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    return shape, c, synth.rhs(n, n, n, seed), O.SMG(shape, c, 1, 0)
+
+
+def test_learned_loop_with_zero_network_is_the_c_oracles_fpcg():
+    """A network with all-zero parameters adds nothing: the NumPy loop must be
+    the C oracle's flexible PCG (an independent implementation of equation
+    (2)), iteration for iteration."""
+    from oracle import oracle as O
+    shape, c, b, S = _loop_problem()
+    zero = [(W * 0, bb * 0) for W, bb in L.init_params(0)]
+    x, k, rels, fb_iter, fb_reason = L.fpcg_learned(b, shape, c, S, zero)
+    ref = O.krylov(O.FPCG, b, shape, c, S)
+    assert fb_reason == "none" and fb_iter == -1
+    assert k == ref.iters
+    assert np.allclose(rels, ref.hist, rtol=1e-9, atol=1e-15)
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_learned_loop_fallbacks():
+    """Each fallback rule fires where its condition first holds, and the solve
+    continues as plain flexible PCG (so it still converges)."""
+    from oracle import oracle as O
+    shape, c, b, S = _loop_problem()
+    plain = O.krylov(O.FPCG, b, shape, c, S)
+    # overflow: non-finite at once, then exactly plain FPCG
+    huge = L.unflatten(np.full(L.NPARAMS, 1e150))
+    x, k, rels, fi, fr = L.fpcg_learned(b, shape, c, S, huge)
+    assert (fr, fi) == ("nonfinite", 0) and k == plain.iters
+    assert np.allclose(rels, plain.hist, rtol=1e-9, atol=1e-15)
+    # a constant output of the sign that makes (s, r) negative
+    s0 = S.apply(b)
+    rp = b - O.matvec(s0, shape, c)
+    sigma = np.sqrt(np.mean((rp / c[0]) ** 2))
+    v = -10.0 * abs(float(s0 @ b)) / (sigma * abs(b.sum())) * np.sign(b.sum())
+    p = np.zeros(L.NPARAMS)
+    p[-1] = v
+    x, k, rels, fi, fr = L.fpcg_learned(b, shape, c, S, L.unflatten(p))
+    assert (fr, fi) == ("sr", 0) and k == plain.iters
+    # a constant output of the other sign keeps (s, r) > 0 but spoils the
+    # preconditioner: the residual stops falling and the network is dropped
+    p[-1] = -v
+    x, k, rels, fi, fr = L.fpcg_learned(b, shape, c, S, L.unflatten(p))
+    assert fr == "stagnation" and fi >= 2
+    assert rels[fi] > 0.9 * rels[fi - 2]
+    assert np.all(rels[2:fi] <= 0.9 * rels[:fi - 2])      # the first step where the rule holds
+    assert rels[-1] <= 1e-8
+    assert np.linalg.norm(b - O.matvec(x, shape, c)) <= 1.5e-8 * np.linalg.norm(b)
+
+
+def test_learned_correction_definition():
+    """correction() forms r' = r - A s, sigma = rms(r'/cbar) and adds sigma times
+    the network of r'/(cbar sigma): with a network whose only nonzero parameter
+    is the output bias beta, the result is s + sigma beta everywhere."""
+    from oracle import oracle as O
+    shape, c, b, S = _loop_problem(8)
+    s = S.apply(b)
+    p = np.zeros(L.NPARAMS)
+    p[-1] = 0.37
+    out, sigma = L.correction(L.unflatten(p), b, s, shape, c)
+    rp = b - O.matvec(s, shape, c)
+    assert np.isclose(sigma, np.linalg.norm(rp / c[0]) / np.sqrt(rp.size), rtol=1e-14)
+    assert np.allclose(out - s, 0.37 * sigma, rtol=1e-13, atol=0)
