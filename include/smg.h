@@ -85,14 +85,32 @@ typedef struct smg_opts {
                                        1: one launch per stage (reference schedule) */
 } smg_opts;
 
+enum { SMG_STOP_2NORM = 0, SMG_STOP_CNORM = 1 };
+
 typedef struct krylov_opts {
-    double rtol;            /* stop when ||r_k||_2 <= rtol*||b||_2 (recursive r) */
+    double rtol;            /* stopping threshold, see stop_norm */
     int32_t max_iter;       /* >= 0 */
     int32_t precond;        /* SMG_PRECOND_SMG or SMG_PRECOND_NONE (T = I) */
     int32_t x0_zero;        /* 1: ignore the contents of x and start from 0 */
-    int32_t reserved;
-    double *history;        /* HOST, nullable, max_iter+1 entries: ||r_k||/||b|| */
-    double *history_c;      /* HOST, nullable, max_iter entries: sqrt|(s_k,r_k)| / sqrt|(s_0,r_0)| */
+    int32_t stop_norm;      /* SMG_STOP_2NORM: stop when ||r_k||_2 <= rtol ||b||_2 (recursive r_k);
+                               SMG_STOP_CNORM: stop when sqrt|(T r_k, r_k)| <= rtol sqrt|(T b, b)|, the
+                               ratio the paper plots (Figs. 2 and 5), tested once s_k = T r_k is formed */
+    double *history;        /* HOST, nullable, max_iter+1 entries: ||r_k||_2/||b||_2 */
+    double *history_c;      /* HOST, nullable, max_iter entries: sqrt|(s_k,r_k)| / sqrt|(T b, b)| */
+    /* Per-step diagnostics of Section 5 (all nullable; they cost two extra
+     * stencil passes and a host round trip per iteration):
+     *   xstar      DEVICE, the exact solution A^{-1} b (e.g. from a tighter solve);
+     *   diag_work  DEVICE, 2*nx*ny*nz doubles of scratch, required with xstar;
+     *   err_a      HOST, max_iter+1 entries: ||x* - x_k||_A / ||x* - x_0||_A, which
+     *              equals ||r_k||_{A^{-1}} / ||r_0||_{A^{-1}} (needs xstar);
+     *   sin_angle  HOST, max_iter entries: sin of the A^{-1}-angle between r_k and
+     *              A T r_k, cos = |(r_k, T r_k)| / (||r_k||_{A^{-1}} ||A T r_k||_{A^{-1}})
+     *              (Theorem 1: for PSD err_a[k+1]/err_a[k] equals it; flexible PCG,
+     *              being locally optimal, is never slower) (needs xstar). */
+    const double *xstar;
+    double *diag_work;
+    double *err_a;
+    double *sin_angle;
 } krylov_opts;
 
 typedef struct krylov_info {
@@ -101,6 +119,8 @@ typedef struct krylov_info {
     double rel_res;         /* ||r||_2/||b||_2 of the recursive residual */
     double true_rel_res;    /* ||b - A x||_2/||b||_2 recomputed at exit */
     double solve_seconds;   /* wall time of the iteration, host clock */
+    double rel_res_c;       /* sqrt|(T r, r)| / sqrt|(T b, b)| of the last residual T was applied to
+                               (the final one with SMG_STOP_CNORM); NaN when T was never applied */
 } krylov_info;
 
 typedef struct smg_handle smg_handle;
@@ -187,8 +207,9 @@ typedef struct smg_batch smg_batch;
 int smg_batch_workspace_bytes(smg_handle *const *hs, int32_t nbox, size_t *bytes);
 int smg_batch_create(smg_handle *const *hs, int32_t nbox, const double *const *b, double *const *x, void *ws,
                      size_t ws_bytes, int32_t use_graph, void *stream, smg_batch **out);
-/* One batched solve with options o (history pointers must be NULL, precond
- * SMG_PRECOND_SMG); infos: host, nbox entries.  Returns SMG_OK when every box
+/* One batched solve with options o (history and diagnostic pointers must be
+ * NULL, precond SMG_PRECOND_SMG, stop_norm SMG_STOP_2NORM); infos: host, nbox
+ * entries (rel_res_c is NaN).  Returns SMG_OK when every box
  * converged, else the most severe status among the boxes. */
 int smg_batch_fpcg(smg_batch *bt, const krylov_opts *o, krylov_info *infos, void *stream);
 /* Grouped launches per iteration (steps) and the per-box launches they

@@ -11,6 +11,7 @@
 // buffers alternate between iterations) and replayed.  Per box, the kernels,
 // their arguments and their order are those of fpcg_solve, so each box's
 // iterates are bitwise those of its own single-box solve.
+#include <limits>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -338,7 +339,8 @@ int smg_batch_create(smg_handle *const *hs, int32_t nbox, const double *const *b
 int smg_batch_fpcg(smg_batch *bt, const krylov_opts *o, krylov_info *infos, void *stream)
 {
     if (!bt || !o || !infos) return SMG_EINVAL;
-    if (o->max_iter < 0 || !(o->rtol >= 0.0) || o->precond != SMG_PRECOND_SMG || o->history || o->history_c)
+    if (o->max_iter < 0 || !(o->rtol >= 0.0) || o->precond != SMG_PRECOND_SMG || o->history || o->history_c ||
+        o->stop_norm != SMG_STOP_2NORM || o->xstar || o->err_a || o->sin_angle)
         return SMG_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t cst = static_cast<hipStream_t>(stream);
@@ -413,6 +415,7 @@ int smg_batch_fpcg(smg_batch *bt, const krylov_opts *o, krylov_info *infos, void
         inf.rel_res = std::sqrt(s.rr) / bden;
         inf.true_rel_res = std::sqrt(s.true_rr) / bden;
         inf.solve_seconds = secs;
+        inf.rel_res_c = std::numeric_limits<double>::quiet_NaN();
         if (s.nonfinite)
             inf.status = SMG_ENONFINITE;
         else if (s.breakdown || !std::isfinite(inf.rel_res))

@@ -10,6 +10,8 @@
 // partial per block (wave shuffles, then LDS across the block's waves), and
 // a one-block finalize kernel sums the partials in a fixed order and advances
 // the scalar recurrence on the device.
+#include <vector>
+
 #include "group.h"
 #include "smg_internal.h"
 
@@ -458,7 +460,61 @@ __device__ __forceinline__ void k_fill_body(const FillArgs &a, const Blk &blk)
 }
 SMG_GROUPED_KERNEL(k_fill, 256, FillArgs)
 
+// out = alpha a + beta b (grid-stride)
+__global__ __launch_bounds__(256) void k_axpby(double *out, const double *a, double alpha, const double *b,
+                                               double beta, long long n)
+{
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x)
+        out[c] = alpha * a[c] + beta * b[c];
+}
+
+// partial sums of (a1, b1) and (a2, b2), one slot per block (fixed grid of
+// kRedBlocks blocks; a2 may be null)
+__global__ __launch_bounds__(kRB) void k_dot2(const double *a1, const double *b1, const double *a2, const double *b2,
+                                              long long n, double *partials)
+{
+    __shared__ double lds[kRB / 64];
+    double d1 = 0.0, d2 = 0.0;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+        d1 += a1[c] * b1[c];
+        if (a2) d2 += a2[c] * b2[c];
+    }
+    d1 = block_sum(d1, lds);
+    d2 = block_sum(d2, lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = d1;
+        partials[kRedBlocks + blockIdx.x] = d2;
+    }
+}
+
 }  // namespace
+
+void launch_axpby(double *out, const double *a, double alpha, const double *b, double beta, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(kRedBlocks), dim3(256), 0, st, out, a, alpha, b, beta,
+                       static_cast<long long>(n));
+}
+
+int device_dot2(const double *a1, const double *b1, const double *a2, const double *b2, size_t n, double *partials,
+                hipStream_t st, double *d1, double *d2)
+{
+    hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kRB), 0, st, a1, b1, a2, b2, static_cast<long long>(n),
+                       partials);
+    std::vector<double> h(2 * kRedBlocks);
+    if (hipMemcpyAsync(h.data(), partials, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
+        return SMG_EHIP;
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < kRedBlocks; ++i) {
+        s1 += h[i];
+        s2 += h[kRedBlocks + i];
+    }
+    if (d1) *d1 = s1;
+    if (d2) *d2 = s2;
+    return SMG_OK;
+}
 
 void launch_fill(double *dst, double v, size_t n, hipStream_t st)
 {

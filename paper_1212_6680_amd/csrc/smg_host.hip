@@ -8,9 +8,11 @@
 // 2D hierarchy of x-line blocks in span{Tx, I}.  Planes with equal (ca, cb)
 // share one 2D hierarchy ("plane type") and lines with equal (la, lb) share
 // one Thomas factor table, so the tables are a few hundred KB even at 384^3.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <tuple>
 #include <new>
@@ -738,6 +740,9 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     if (!h || !b || !x || !o) return SMG_EINVAL;
     if (o->max_iter < 0 || !(o->rtol >= 0.0)) return SMG_EINVAL;
     if (o->precond != SMG_PRECOND_SMG && o->precond != SMG_PRECOND_NONE) return SMG_EINVAL;
+    if (o->stop_norm != SMG_STOP_2NORM && o->stop_norm != SMG_STOP_CNORM) return SMG_EINVAL;
+    if ((o->err_a || o->sin_angle) && !o->xstar) return SMG_EINVAL;
+    if (o->xstar && !o->diag_work) return SMG_EINVAL;
     hipStream_t st = as_stream(stream);
     const auto t0 = std::chrono::steady_clock::now();
     const smg_grid &g = h->g;
@@ -747,7 +752,11 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     double *part = h->at<double>(h->L.part);
     KScalars *sc = h->at<KScalars>(h->L.sc);
     KScalars *hs = h->host_sc;
+    const bool cstop = o->stop_norm == SMG_STOP_CNORM;
+    const bool want_c = cstop || o->history_c;
+    const bool diag = o->xstar != nullptr;
     krylov_info inf{};
+    inf.rel_res_c = std::numeric_limits<double>::quiet_NaN();
     auto finish = [&](int status) {
         inf.status = status;
         inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -755,6 +764,19 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         return status;
     };
     auto sync = [&]() { return hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess; };
+    auto precond = [&](const double *in, double *out) {
+        if (o->precond == SMG_PRECOND_SMG)
+            vcycle(h, in, out, 1, static_cast<long long>(n), st);
+        else
+            launch_copy(in, out, n, st);
+    };
+    // ||x* - x||_A^2 with the diagnostic scratch (e = x* - x, then A e)
+    double *de = diag ? o->diag_work : nullptr, *dw = diag ? o->diag_work + n : nullptr;
+    auto err_a2 = [&](double *out) {
+        launch_axpby(de, o->xstar, 1.0, x, -1.0, n, st);
+        launch_matvec7(de, dw, static_cast<long long>(n), 1, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, st);
+        return device_dot2(de, dw, nullptr, nullptr, n, part, st, out, nullptr);
+    };
     // End of an iteration's work on the stream (its scalars are in hs once it
     // completes), so that the next iteration's V-cycle can be queued before
     // the host waits; see the loop.
@@ -782,16 +804,36 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     double rel = std::sqrt(hs->rr) / bden;
     std::vector<double> rels{rel};
     if (o->history) o->history[0] = rel;
-    double c0 = 0.0;
+    // Denominator of the C-norm ratio, sqrt|(T b, b)|.  With x0 = 0 it is the
+    // first iteration's sqrt|(s_0, r_0)|; otherwise T b costs one V-cycle here.
+    double cden = 0.0;
+    bool cden_pending = false;
+    if (want_c) {
+        if (o->precond == SMG_PRECOND_NONE) {
+            cden = bnorm;
+        } else if (o->x0_zero) {
+            cden_pending = true;
+        } else {
+            double tbb = 0.0;
+            precond(b, s);
+            if (device_dot2(s, b, nullptr, nullptr, n, part, st, &tbb, nullptr) != SMG_OK) return finish(SMG_EHIP);
+            cden = std::sqrt(std::fabs(tbb));
+        }
+    }
+    double ea0 = 0.0;
+    if (diag) {
+        if (err_a2(&ea0) != SMG_OK) return finish(SMG_EHIP);
+        if (o->err_a) o->err_a[0] = ea0 > 0.0 ? 1.0 : 0.0;
+    }
     int k = 0, status = SMG_NOT_CONVERGED;
     bool queued = false;   // this iteration's V-cycle is already on the stream
-    for (; k < o->max_iter && rel > o->rtol; ++k) {
+    bool cconv = false;    // C-norm test met
+    for (; k < o->max_iter; ++k) {
+        if (!cstop && !(rel > o->rtol)) break;
         if (queued)
             queued = false;
-        else if (o->precond == SMG_PRECOND_SMG)
-            vcycle(h, r, s, 1, static_cast<long long>(n), st);
         else
-            launch_copy(r, s, n, st);
+            precond(r, s);
         const double *su = s;
         bool dots_done = false;
         if (hook && hook->active) {
@@ -812,7 +854,35 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         }
         if (!dots_done) {
             launch_dots_sr_sq(s, r, q, method == 1 && k > 0, n, part, st);
-            launch_finalize(1, method, k, part, sc, nullptr, st);
+            launch_finalize(1, method, k, part, sc, want_c ? hs : nullptr, st);
+        }
+        if (want_c) {
+            // (s_k, r_k) on the host: the C-norm ratio and its stopping test
+            if (!sync()) return finish(SMG_EHIP);
+            const double crk = std::sqrt(std::fabs(hs->sr));
+            if (cden_pending) {
+                cden = crk;
+                cden_pending = false;
+            }
+            const double relc = crk / (cden > 0.0 ? cden : 1.0);
+            inf.rel_res_c = relc;
+            if (o->history_c) o->history_c[k] = relc;
+            if (cstop && !(relc > o->rtol)) {
+                cconv = true;
+                break;
+            }
+        }
+        if (diag) {
+            // Theorem 1: cos = |(r_k, s_k)| / (||r_k||_{A^{-1}} ||A s_k||_{A^{-1}}), with
+            // ||r_k||_{A^{-1}} = ||x* - x_k||_A and ||A s_k||_{A^{-1}}^2 = (s_k, A s_k)
+            double ea = 0.0, sas = 0.0, sr = 0.0;
+            if (err_a2(&ea) != SMG_OK) return finish(SMG_EHIP);
+            launch_matvec7(su, dw, static_cast<long long>(n), 1, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, st);
+            if (device_dot2(su, dw, su, r, n, part, st, &sas, &sr) != SMG_OK) return finish(SMG_EHIP);
+            if (o->sin_angle) {
+                const double c2 = (ea > 0.0 && sas > 0.0) ? sr * sr / (ea * sas) : 1.0;
+                o->sin_angle[k] = std::sqrt(std::max(0.0, 1.0 - c2));
+            }
         }
         launch_update_p_q(su, pa, pb, q, sc, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
         launch_finalize(2, method, k, part, sc, nullptr, st);
@@ -825,8 +895,8 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         // V-cycle writes s and its own level buffers only, which nothing reads
         // after a stop (the true residual below uses s as scratch).
         const double pred = k == 0 ? 0.5 * rels[0] : rels[k] * (rels[k] / rels[k - 1]);
-        const bool ahead = o->precond == SMG_PRECOND_SMG && !(hook && hook->active) && k + 1 < o->max_iter &&
-                           pred > 4.0 * o->rtol;
+        const bool ahead = o->precond == SMG_PRECOND_SMG && !(hook && hook->active) && !diag && !cstop &&
+                           k + 1 < o->max_iter && pred > 4.0 * o->rtol;
         if (ahead) {
             if (hipEventRecord(done.e, st) != hipSuccess) return finish(SMG_EHIP);
             vcycle(h, r, s, 1, static_cast<long long>(n), st);
@@ -842,11 +912,14 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
             status = SMG_EBREAKDOWN;
             break;
         }
-        if (k == 0) c0 = std::sqrt(std::fabs(hs->sr));
-        if (o->history_c) o->history_c[k] = c0 > 0.0 ? std::sqrt(std::fabs(hs->sr)) / c0 : 0.0;
         rel = std::sqrt(hs->rr) / bden;
         rels.push_back(rel);
         if (o->history) o->history[k + 1] = rel;
+        if (diag && o->err_a) {
+            double ea = 0.0;
+            if (err_a2(&ea) != SMG_OK) return finish(SMG_EHIP);
+            o->err_a[k + 1] = ea0 > 0.0 ? std::sqrt(ea / ea0) : 0.0;
+        }
         if (!std::isfinite(rel)) {
             status = SMG_EBREAKDOWN;
             ++k;
@@ -854,12 +927,8 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         }
         if (hook && hook->active && k >= 1 && rel > 0.9 * rels[k - 1]) fall_back(k + 1, NET_FALLBACK_STAGNATION);
     }
-    if (status != SMG_EBREAKDOWN) {
-        inf.iters = k;
-        status = rel <= o->rtol ? SMG_OK : SMG_NOT_CONVERGED;
-    } else {
-        inf.iters = k;
-    }
+    inf.iters = k;
+    if (status != SMG_EBREAKDOWN) status = (cstop ? cconv : rel <= o->rtol) ? SMG_OK : SMG_NOT_CONVERGED;
     inf.rel_res = rel;
     launch_true_resid(b, x, s, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
     launch_finalize(0, method, 0, part, sc, hs, st);
@@ -905,6 +974,56 @@ int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs)
     return SMG_OK;
 }
 
+namespace {
+
+// Everything smg_setup does except creating the handle: Galerkin tables,
+// schedule, workspace layout and the upload of the tables into ws (which
+// synchronises the stream).  With pinned, the handle also gets the pinned host
+// mirror of the Krylov scalars that the solvers read.
+int fill_handle(smg_handle *h, const smg_grid *g, const smg_opts *o, int32_t max_nrhs, char *ws, size_t ws_bytes,
+                hipStream_t st, bool pinned)
+{
+    const Tables t = build_tables(*g);
+    h->g = *g;
+    h->o = *o;
+    h->ipre = o->inner_pre < 0 ? o->pre : o->inner_pre;
+    h->ipost = o->inner_post < 0 ? o->post : o->inner_post;
+    h->max_nrhs = max_nrhs;
+    h->N = static_cast<size_t>(g->nx) * g->ny * g->nz;
+    h->E = (g->nx + 63) / 64;
+    h->nxp = 64 * h->E;
+    h->nz = t.nz;
+    size_t acc = 0;
+    for (int v : t.nz) {
+        h->pc_off.push_back(acc);
+        acc += v;
+    }
+    h->ny2 = t.ny2;
+    h->lev2_off = t.lev2_off;
+    h->lines_total = t.lines_total;
+    h->nptypes = static_cast<int>(t.ptypes.size());
+    h->nfac = static_cast<int>(t.uniq.size());
+    h->P2 = (g->nz + 1) / 2;
+    h->elem = elem_size(o->precision);
+    choose_fused_schedule(h);
+    h->march_waves = kMarchWaves;
+    h->L = make_layout(*g, *o, max_nrhs, t, h->nxp);
+    h->host_sc = nullptr;
+    if (ws_bytes < h->L.total) return SMG_EWORKSPACE;
+    h->ws = ws;
+    h->prof = false;
+    h->ev_used = 0;
+    h->prof_bytes = 0;
+    if (pinned && hipHostMalloc(reinterpret_cast<void **>(&h->host_sc), sizeof(KScalars), hipHostMallocDefault) !=
+                      hipSuccess) {
+        h->host_sc = nullptr;
+        return SMG_EHIP;
+    }
+    return arith_size(o->precision) == 8 ? upload_tables<double>(h, t, st) : upload_tables<float>(h, t, st);
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -931,49 +1050,10 @@ int smg_setup(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, void *ws, 
     if (check_grid(g, o) != SMG_OK || max_nrhs < 1 || !ws) return SMG_EINVAL;
     smg_handle *h = nullptr;
     try {
-        const Tables t = build_tables(*g);
         h = new smg_handle();
-        h->g = *g;
-        h->o = *o;
-        h->ipre = o->inner_pre < 0 ? o->pre : o->inner_pre;
-        h->ipost = o->inner_post < 0 ? o->post : o->inner_post;
-        h->max_nrhs = max_nrhs;
-        h->N = static_cast<size_t>(g->nx) * g->ny * g->nz;
-        h->E = (g->nx + 63) / 64;
-        h->nxp = 64 * h->E;
-        h->nz = t.nz;
-        size_t acc = 0;
-        for (int v : t.nz) {
-            h->pc_off.push_back(acc);
-            acc += v;
-        }
-        h->ny2 = t.ny2;
-        h->lev2_off = t.lev2_off;
-        h->lines_total = t.lines_total;
-        h->nptypes = static_cast<int>(t.ptypes.size());
-        h->nfac = static_cast<int>(t.uniq.size());
-        h->P2 = (g->nz + 1) / 2;
-        h->elem = elem_size(o->precision);
-        choose_fused_schedule(h);
-        h->march_waves = kMarchWaves;
-        h->L = make_layout(*g, *o, max_nrhs, t, h->nxp);
-        if (ws_bytes < h->L.total) {
-            delete h;
-            return SMG_EWORKSPACE;
-        }
-        h->ws = static_cast<char *>(ws);
-        h->prof = false;
-        h->ev_used = 0;
-        h->prof_bytes = 0;
-        if (hipHostMalloc(reinterpret_cast<void **>(&h->host_sc), sizeof(KScalars), hipHostMallocDefault) !=
-            hipSuccess) {
-            delete h;
-            return SMG_EHIP;
-        }
-        const int rc = arith_size(o->precision) == 8 ? upload_tables<double>(h, t, as_stream(stream))
-                                                      : upload_tables<float>(h, t, as_stream(stream));
+        const int rc = fill_handle(h, g, o, max_nrhs, static_cast<char *>(ws), ws_bytes, as_stream(stream), true);
         if (rc != SMG_OK) {
-            (void)hipHostFree(h->host_sc);
+            if (h->host_sc) (void)hipHostFree(h->host_sc);
             delete h;
             return rc;
         }

@@ -361,6 +361,12 @@ void launch_copy(const double *src, double *dst, size_t n, hipStream_t st);
 void launch_fill(double *dst, double v, size_t n, hipStream_t st);
 void launch_true_resid(const double *b, const double *x, double *tmp, int nx, int ny, int nz, double cx,
                        double cy, double cz, double *partials, hipStream_t st);
+// out = alpha a + beta b
+void launch_axpby(double *out, const double *a, double alpha, const double *b, double beta, size_t n, hipStream_t st);
+// (a1, b1) and (a2, b2) (a2, b2 may be null): fixed-grid partials on the
+// device, summed on the host in a fixed order; synchronises st
+int device_dot2(const double *a1, const double *b1, const double *a2, const double *b2, size_t n, double *partials,
+                hipStream_t st, double *d1, double *d2);
 
 }  // namespace smg
 

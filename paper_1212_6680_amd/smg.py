@@ -40,13 +40,18 @@ class smg_opts(C.Structure):
 
 class krylov_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32),
-                ("x0_zero", C.c_int32), ("reserved", C.c_int32),
-                ("history", C.POINTER(C.c_double)), ("history_c", C.POINTER(C.c_double))]
+                ("x0_zero", C.c_int32), ("stop_norm", C.c_int32),
+                ("history", C.POINTER(C.c_double)), ("history_c", C.POINTER(C.c_double)),
+                ("xstar", C.c_void_p), ("diag_work", C.c_void_p),
+                ("err_a", C.POINTER(C.c_double)), ("sin_angle", C.POINTER(C.c_double))]
 
 
 class krylov_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
-                ("true_rel_res", C.c_double), ("solve_seconds", C.c_double)]
+                ("true_rel_res", C.c_double), ("solve_seconds", C.c_double), ("rel_res_c", C.c_double)]
+
+
+STOP = {"2": 0, "c": 1}
 
 
 class smg_tune_info(C.Structure):
@@ -141,11 +146,52 @@ def _stream():
 
 
 def _dptr(t: torch.Tensor, n: int | None = None):
+    """Device pointer of a contiguous float64 CUDA tensor of exactly n elements (when n is given)."""
+    if n is not None and t.numel() != n:
+        raise SMGError(f"expected {n} elements, got a tensor of shape {tuple(t.shape)}")
     if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise SMGError("expected a contiguous float64 CUDA tensor")
-    if n is not None and t.numel() < n:
-        raise SMGError("tensor too small")
     return C.c_void_p(t.data_ptr())
+
+
+def _block(t: torch.Tensor, n: int, max_cols: int | None = None):
+    """(nrhs, ld) of a block of vectors of length n: a 1-D tensor of n elements,
+    or a 2-D (nrhs, n) tensor with unit column stride and row stride ld >= n.
+    Checked before anything reaches the device."""
+    if t.dim() == 1:
+        if t.shape[0] != n:
+            raise SMGError(f"expected a vector of {n} elements, got shape {tuple(t.shape)}")
+        nrhs, ld = 1, n
+    elif t.dim() == 2:
+        if t.shape[1] != n or t.shape[0] < 1:
+            raise SMGError(f"expected an (nrhs, {n}) block, got shape {tuple(t.shape)}")
+        if t.stride(1) != 1 or (t.shape[0] > 1 and t.stride(0) < n):
+            raise SMGError("block rows must be contiguous with a row stride >= n")
+        nrhs, ld = t.shape[0], (t.stride(0) if t.shape[0] > 1 else n)
+    else:
+        raise SMGError(f"expected a 1-D or 2-D tensor, got shape {tuple(t.shape)}")
+    if max_cols is not None and nrhs > max_cols:
+        raise SMGError(f"{nrhs} right-hand sides exceed max_nrhs = {max_cols}")
+    return nrhs, ld
+
+
+def _on_device(*ts: torch.Tensor):
+    for t in ts:
+        if not t.is_cuda or t.dtype != torch.float64:
+            raise SMGError("expected a float64 CUDA tensor")
+
+
+def _like(t: torch.Tensor) -> torch.Tensor:
+    """An output with t's shape and strides (the library uses one leading dimension for both)."""
+    return torch.empty_strided(t.shape, t.stride(), dtype=t.dtype, device=t.device)
+
+
+def _same_layout(a: torch.Tensor, b: torch.Tensor):
+    if a.shape != b.shape or (a.dim() == 2 and a.shape[0] > 1 and a.stride() != b.stride()):
+        raise SMGError(f"output shape/strides {tuple(b.shape)}/{b.stride()} differ from the input's "
+                       f"{tuple(a.shape)}/{a.stride()}")
+    if b.dtype != a.dtype or b.device != a.device:
+        raise SMGError("output dtype/device differ from the input's")
 
 
 class Info(dict):
@@ -156,7 +202,7 @@ class SMG:
     """One SMG hierarchy on the GPU for an (nx, ny, nz) brick with coefficients c."""
 
     def __init__(self, shape, c=(1.0, 1.0, 1.0), pre=1, post=1, inner_pre=-1, inner_post=-1, order=0,
-                 precision="f64", max_nrhs=1, device="cuda", kernel_mode=0):
+                 precision="f64", max_nrhs=1, device="cuda", kernel_mode=0, ws_fill=None):
         L = lib()
         self.shape = tuple(int(v) for v in shape)
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
@@ -168,6 +214,8 @@ class SMG:
                                      C.byref(nbytes)), "smg_workspace_bytes")
         self.ws_bytes = nbytes.value
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        if ws_fill is not None:             # byte pattern left in the workspace before setup
+            self.ws.fill_(int(ws_fill))
         h = C.c_void_p()
         _check(L.smg_setup(C.byref(self.grid), C.byref(self.opts), self.max_nrhs,
                            C.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream(), C.byref(h)),
@@ -180,35 +228,54 @@ class SMG:
             _lib.smg_destroy(h)
             self.h = None
 
-    def _ld(self, t):
-        return self.n if t.dim() <= 1 else t.stride(0)
-
     def apply(self, r: torch.Tensor, s: torch.Tensor | None = None) -> torch.Tensor:
-        """s = T r; r is (n,) or (nrhs, n) (one vector per row)."""
-        nrhs = 1 if r.dim() == 1 else r.shape[0]
+        """s = T r; r is (n,) or (nrhs, n) (one vector per row, row stride >= n)."""
+        nrhs, ld = _block(r, self.n, self.max_nrhs)
         if s is None:
-            s = torch.empty_like(r)
-        _check(lib().smg_apply(self.h, _dptr(r), _dptr(s), nrhs, self._ld(r), _stream()), "smg_apply")
+            s = _like(r)
+        _same_layout(r, s)
+        _on_device(r, s)
+        _check(lib().smg_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(s.data_ptr()), nrhs, ld, _stream()),
+               "smg_apply")
         return s
 
     def matvec(self, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
-        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        """y = A x; x is (n,) or (nrhs, n) (one vector per row, row stride >= n)."""
+        nrhs, ld = _block(x, self.n)
         if y is None:
-            y = torch.empty_like(x)
-        _check(lib().smg_matvec(self.h, _dptr(x), _dptr(y), nrhs, self._ld(x), _stream()), "smg_matvec")
+            y = _like(x)
+        _same_layout(x, y)
+        _on_device(x, y)
+        _check(lib().smg_matvec(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, ld, _stream()),
+               "smg_matvec")
         return y
 
-    def _solve(self, fn, b, x, rtol, max_iter, precond, history, zero_x0, net=None):
+    def _solve(self, fn, b, x, rtol, max_iter, precond, history, zero_x0, net=None, stop="2", xstar=None):
+        vecs = [t for t in (b, x, xstar) if t is not None]
+        for t in vecs:                      # sizes first, then the device
+            if t.numel() != self.n:
+                raise SMGError(f"expected {self.n} elements, got a tensor of shape {tuple(t.shape)}")
+        for t in vecs:
+            _dptr(t, self.n)
+        if max_iter < 0:
+            raise SMGError("max_iter must be >= 0")
         if x is None:
             x = torch.empty_like(b)
             x0_zero = 1
         else:
             x0_zero = 1 if zero_x0 else 0
+        dbl = C.POINTER(C.c_double)
         hist = (C.c_double * (max_iter + 1))() if history else None
         histc = (C.c_double * max(max_iter, 1))() if history else None
-        o = krylov_opts(rtol, max_iter, PRECOND[precond], x0_zero, 0,
-                        C.cast(hist, C.POINTER(C.c_double)) if history else None,
-                        C.cast(histc, C.POINTER(C.c_double)) if history else None)
+        erra = (C.c_double * (max_iter + 1))() if xstar is not None else None
+        sina = (C.c_double * max(max_iter, 1))() if xstar is not None else None
+        work = torch.empty(2 * self.n, dtype=torch.float64, device=b.device) if xstar is not None else None
+        o = krylov_opts(rtol, max_iter, PRECOND[precond], x0_zero, STOP[stop],
+                        C.cast(hist, dbl) if history else None, C.cast(histc, dbl) if history else None,
+                        C.c_void_p(xstar.data_ptr()) if xstar is not None else None,
+                        C.c_void_p(work.data_ptr()) if work is not None else None,
+                        C.cast(erra, dbl) if erra is not None else None,
+                        C.cast(sina, dbl) if sina is not None else None)
         info = krylov_info()
         if net is None:
             code = fn(self.h, _dptr(b, self.n), _dptr(x, self.n), C.byref(o), C.byref(info), _stream())
@@ -218,29 +285,44 @@ class SMG:
                       C.byref(ninfo), _stream())
         _check(code, fn.__name__, ok=(SMG_OK, SMG_NOT_CONVERGED))
         out = Info(iters=info.iters, status=info.status, rel_res=info.rel_res,
-                   true_rel_res=info.true_rel_res, seconds=info.solve_seconds)
+                   true_rel_res=info.true_rel_res, seconds=info.solve_seconds, rel_res_c=info.rel_res_c)
         if net is not None:
             out["fallback_iter"] = ninfo.fallback_iter
             out["fallback_reason"] = FALLBACK[ninfo.fallback_reason]
         if history:
             out["history"] = list(hist[:info.iters + 1])
-            out["history_c"] = list(histc[:info.iters])
+            nc = info.iters + (1 if stop == "c" and info.status == SMG_OK else 0)
+            out["history_c"] = list(histc[:min(nc, max_iter)])
+        if xstar is not None:
+            out["err_a"] = list(erra[:info.iters + 1])
+            out["sin_angle"] = list(sina[:info.iters])
         return x, out
 
-    def pcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False):
-        """Algorithm 1 with beta from equation (1)."""
-        return self._solve(lib().pcg_solve, b, x, rtol, max_iter, precond, history, zero_x0)
+    def pcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False, stop="2",
+            xstar=None):
+        """Algorithm 1 with beta from equation (1); stop "2" (||r||/||b||) or "c" (C-norm ratio); xstar: exact
+        solution for the per-step Section 5 diagnostics (err_a, sin_angle)."""
+        return self._solve(lib().pcg_solve, b, x, rtol, max_iter, precond, history, zero_x0, stop=stop,
+                           xstar=xstar)
 
-    def fpcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False):
-        """Algorithm 1 with beta from equation (2)."""
-        return self._solve(lib().fpcg_solve, b, x, rtol, max_iter, precond, history, zero_x0)
+    def fpcg(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False, stop="2",
+            xstar=None):
+        """Algorithm 1 with beta from equation (2); stop "2" (||r||/||b||) or "c" (C-norm ratio); xstar: exact
+        solution for the per-step Section 5 diagnostics (err_a, sin_angle)."""
+        return self._solve(lib().fpcg_solve, b, x, rtol, max_iter, precond, history, zero_x0, stop=stop,
+                           xstar=xstar)
 
-    def psd(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False):
-        """Algorithm 1 with beta = 0."""
-        return self._solve(lib().psd_solve, b, x, rtol, max_iter, precond, history, zero_x0)
+    def psd(self, b, x=None, rtol=1e-8, max_iter=500, precond="smg", history=False, zero_x0=False, stop="2",
+            xstar=None):
+        """Algorithm 1 with beta = 0; stop "2" (||r||/||b||) or "c" (C-norm ratio); xstar: exact
+        solution for the per-step Section 5 diagnostics (err_a, sin_angle)."""
+        return self._solve(lib().psd_solve, b, x, rtol, max_iter, precond, history, zero_x0, stop=stop,
+                           xstar=xstar)
 
     def fpcg_learned(self, net, b, x=None, rtol=1e-8, max_iter=500, history=False, zero_x0=False):
         """Flexible PCG with the V-cycle followed by the learned correction of `net` (with fallback)."""
+        if net.max_voxels < self.n:
+            raise SMGError(f"network workspace holds {net.max_voxels} voxels, the grid has {self.n}")
         return self._solve(lib().fpcg_learned_solve, b, x, rtol, max_iter, "smg", history, zero_x0, net=net)
 
     def lobpcg(self, X0: torch.Tensor, rtol=1e-8, max_iter=500, precond="smg", guard=0):
@@ -248,8 +330,16 @@ class SMG:
 
         Returns (Ritz values (m + guard,) as a NumPy array, Ritz vectors (m + guard, n), info);
         convergence is required of the first m."""
+        if X0.dim() != 2 or X0.shape[1] != self.n:
+            raise SMGError(f"X0 must be (m + guard, {self.n}), got shape {tuple(X0.shape)}")
         mb = X0.shape[0]
         m = mb - guard
+        if guard < 0 or m < 1:
+            raise SMGError(f"need at least one wanted column (block {mb}, guard {guard})")
+        if precond == "smg" and mb > self.max_nrhs:
+            raise SMGError(f"block of {mb} columns exceeds max_nrhs = {self.max_nrhs}")
+        if not X0.is_cuda or X0.dtype != torch.float64:
+            raise SMGError("X0 must be a float64 CUDA tensor")
         nbytes = C.c_size_t(0)
         _check(lib().lobpcg_workspace_bytes(self.h, mb, C.byref(nbytes)), "lobpcg_workspace_bytes")
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=X0.device)

@@ -88,3 +88,60 @@ def test_net_workspace_query_and_invalid_arguments():
     assert L.net_setup(32 ** 3, 0, 0, C.cast(buf, C.c_void_p), 64, None, C.byref(h)) == -2
     assert not h.value
     assert L.net_setup(32 ** 3, 0, 0, None, 1 << 30, None, C.byref(h)) == -1
+
+
+def _bare_smg(n=1000, max_nrhs=2):
+    """An SMG binding object without a device handle: the operand checks run
+    before anything reaches the library, so they can be exercised on the CPU."""
+    G = object.__new__(S.SMG)
+    G.n, G.max_nrhs, G.h = n, max_nrhs, None
+    return G
+
+
+def test_binding_rejects_wrong_operand_sizes_before_any_launch():
+    import torch
+    G = _bare_smg()
+    f64 = torch.float64
+    for bad in (torch.zeros(999, dtype=f64), torch.zeros(1001, dtype=f64), torch.zeros(2, 999, dtype=f64),
+                torch.zeros(3, 1000, dtype=f64), torch.zeros(1000, 1, dtype=f64), torch.zeros(2, 2, 1000, dtype=f64),
+                torch.zeros(2, 1500, dtype=f64)[:, ::2][:, :1000]):
+        with pytest.raises(S.SMGError):
+            G.apply(bad)
+    with pytest.raises(S.SMGError, match="max_nrhs"):
+        G.apply(torch.zeros(3, 1000, dtype=f64))
+    with pytest.raises(S.SMGError):
+        G.matvec(torch.zeros(1001, dtype=f64))
+    # outputs must match the input's shape and strides
+    r = torch.zeros(2, 1200, dtype=f64)[:, :1000]
+    with pytest.raises(S.SMGError, match="differ"):
+        G.apply(r, torch.zeros(2, 1000, dtype=f64))
+    with pytest.raises(S.SMGError, match="differ"):
+        G.matvec(torch.zeros(1000, dtype=f64), torch.zeros(999, dtype=f64))
+    # right shapes on a CPU tensor: rejected for the device, after the shape checks
+    with pytest.raises(S.SMGError, match="CUDA"):
+        G.apply(torch.zeros(1000, dtype=f64))
+    # solver vectors must have exactly n entries
+    for b in (torch.zeros(999, dtype=f64), torch.zeros(1001, dtype=f64)):
+        with pytest.raises(S.SMGError, match="elements"):
+            G.fpcg(b)
+    with pytest.raises(S.SMGError, match="elements"):
+        G.fpcg(torch.zeros(1000, dtype=f64), torch.zeros(1002, dtype=f64))
+    # LOBPCG's initial block must be (m + guard, n)
+    for X0 in (torch.zeros(4, 999, dtype=f64), torch.zeros(1000, dtype=f64), torch.zeros(1000, 4, dtype=f64)):
+        with pytest.raises(S.SMGError, match="X0"):
+            G.lobpcg(X0)
+    with pytest.raises(S.SMGError, match="max_nrhs"):
+        G.lobpcg(torch.zeros(3, 1000, dtype=f64))
+    with pytest.raises(S.SMGError, match="wanted"):
+        G.lobpcg(torch.zeros(2, 1000, dtype=f64), guard=2)
+
+
+def test_padded_block_layout_is_accepted():
+    import torch
+    G = _bare_smg()
+    X = torch.zeros(2, 1300, dtype=torch.float64)[:, :1000]
+    assert S._block(X, 1000) == (2, 1300)
+    assert S._block(torch.zeros(1000, dtype=torch.float64).view(1, 1000), 1000) == (1, 1000)
+    Y = S._like(X)
+    assert Y.shape == X.shape and Y.stride() == X.stride()
+    S._same_layout(X, Y)

@@ -100,3 +100,7 @@ def test_batch_48_uneven_boxes_full_size():
         b = bs[i].cpu().numpy()
         r = b - O.matvec(x, dims[i], (1.0, 1.0, 1.0))
         assert np.linalg.norm(r) <= 1.5e-8 * np.linalg.norm(b)
+        # the oracle's own FPCG-SMG(1,0) solve of the same box
+        ref = O.krylov(O.FPCG, b, dims[i], (1.0, 1.0, 1.0), O.SMG(dims[i], (1.0, 1.0, 1.0), 1, 0), history=False)
+        assert ref.status == 0 and abs(infos[i].iters - ref.iters) <= 1
+        assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)

@@ -332,3 +332,102 @@ def test_zero_network_is_plain_fpcg():
     x1, info = G.fpcg_learned(net, b, history=True)
     assert info.fallback_reason == "none" and info.iters == plain.iters
     assert np.allclose(info.history, plain.history, rtol=1e-12, atol=0)
+
+
+def _loop_nets():
+    """Networks for the flexible-PCG loop parity: no correction, a mild one,
+    one that stagnates, one that overflows, one with a huge constant output."""
+    zero = [(W * 0, b * 0) for W, b in L.init_params(0)]
+    mild = [(W * (0.1 if i == 3 else 1.0), b * 0) for i, (W, b) in enumerate(L.init_params(1))]
+    he = L.init_params(0)
+    huge = L.unflatten(np.full(L.NPARAMS, 1e150))
+    const = L.unflatten(_corrupt("constant", "f64"))
+    return {"zero": zero, "mild": mild, "he": he, "huge": huge, "constant": const}
+
+
+@pytest.mark.parametrize("name", ["zero", "mild", "he", "huge", "constant"])
+def test_learned_fpcg_loop_matches_oracle_f64(name):
+    """The learned flexible PCG (V-cycle without post-smoothing, network
+    correction, the three fallback rules) against the oracle's composition of
+    the same steps, with the network in FP64: the same fallback decision (reason,
+    and iteration within one), iteration counts within one, solutions to 1e-6."""
+    n = 24
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    b = synth.rhs(n, n, n, 1)
+    params = _loop_nets()[name]
+    xr, kr, rels, fb_iter, fb_reason = L.fpcg_learned(b, shape, c, O.SMG(shape, c, 1, 0), params)
+    G = _smg(shape, c, 1, 0)
+    net = _net(G.n, "f64", train=False)
+    net.set_params(L.flatten(params))
+    x, info = G.fpcg_learned(net, _dev(b), history=True)
+    print(name, "gpu", info.iters, info.fallback_reason, info.fallback_iter, "oracle", kr, fb_reason, fb_iter)
+    assert info.status == 0 and rels[-1] <= 1e-8
+    assert info.fallback_reason == fb_reason
+    assert abs(info.fallback_iter - fb_iter) <= 1
+    assert abs(info.iters - kr) <= 1
+    assert info.true_rel_res <= 1.5e-8
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-6 * np.linalg.norm(xr)
+    k = min(len(info.history), len(rels), 6)
+    assert np.allclose(info.history[:k], rels[:k], rtol=1e-6, atol=1e-14)
+
+
+def test_learned_fpcg_loop_matches_oracle_bf16():
+    """The same loop with the network in BF16 storage and FP32 accumulation,
+    against the oracle rounding where the kernels store: iterations within one,
+    the same fallback decision, solutions to 1e-6."""
+    n = 24
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    b = synth.rhs(n, n, n, 3)
+    params = _loop_nets()["mild"]
+    pq = [(W, bb.astype(np.float32).astype(np.float64)) for W, bb in params]
+    xr, kr, rels, fb_iter, fb_reason = L.fpcg_learned(b, shape, c, O.SMG(shape, c, 1, 0), pq,
+                                                      quantize=L.round_bf16)
+    G = _smg(shape, c, 1, 0)
+    net = _net(G.n, "bf16", train=False)
+    net.set_params(L.flatten(params))
+    x, info = G.fpcg_learned(net, _dev(b))
+    assert info.status == 0 and info.fallback_reason == fb_reason
+    assert abs(info.iters - kr) <= 1
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-6 * np.linalg.norm(xr)
+
+
+def test_trained_network_gains_over_plain_smg10():
+    """What the trained network buys: trained on the GPU (pairs from SMG(1,0),
+    exact solves by FPCG-SMG(1,1), Adam on the energy loss) at 32^3, then used
+    in flexible PCG on right-hand sides it never saw.  It must take fewer
+    iterations than FPCG-SMG(1,0) on average and never more, reach the same
+    true residual, and need no fallback.  The time ratio is printed."""
+    import time
+    n = 32
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    Gp, Ge = _smg(shape, c, 1, 0), _smg(shape, c, 1, 1)
+    net = _net(Gp.n, "bf16")
+    npairs, steps = 256, 1500
+    inputs, targets, _ = net.make_pairs(Gp, Ge, npairs, 20000, exact_rtol=1e-10)
+    net.set_params(synth.he_init(0))
+    order = np.resize(np.random.default_rng(0).permutation(npairs), steps)
+    lr = 2e-3 * (0.05 + 0.95 * 0.5 * (1 + np.cos(np.pi * np.arange(steps) / steps)))
+    hist = net.train(shape, inputs, targets, order, lr, loss="energy")
+    assert np.all(np.isfinite(hist))
+    ev = _net(Gp.n, "bf16", train=False)
+    ev.set_params(net.get_params())
+    gains, ratios = [], []
+    for seed in (7, 8, 9, 10):
+        b = _dev(synth.rhs(n, n, n, seed))
+        for _ in range(2):          # the second of each pair is timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, plain = Gp.fpcg(b)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, lrn = Gp.fpcg_learned(ev, b)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        print(f"seed {seed}: SMG(1,0) {plain.iters} it {1e3 * (t1 - t0):.2f} ms, "
+              f"learned {lrn.iters} it {1e3 * (t2 - t1):.2f} ms, fallback {lrn.fallback_reason}")
+        assert lrn.status == 0 and lrn.fallback_reason == "none" and lrn.true_rel_res <= 1.5e-8
+        assert lrn.iters <= plain.iters
+        gains.append(plain.iters - lrn.iters)
+        ratios.append((t2 - t1) / (t1 - t0))
+    print(f"mean iteration gain {np.mean(gains):.2f}, mean time ratio learned/plain {np.mean(ratios):.2f}")
+    assert np.mean(gains) >= 1.0
