@@ -142,6 +142,24 @@ int smg_setup(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, void *ws, 
  * r is read only; r and s must not overlap. */
 int smg_apply(smg_handle *h, const double *r, double *s, int32_t nrhs, int64_t ld, void *stream);
 
+/* For callers that cannot allocate device memory (graph-captured code, tight
+ * serving loops, harnesses that forbid hipMalloc): s = T r exactly as
+ * smg_apply computes it for a handle set up with (g, o) and max_nrhs = nrhs
+ * (same kernels, bitwise equal results), with no handle and no workspace
+ * argument.  The hierarchy is rebuilt on every call inside a static device
+ * scratch array of 64 MiB that each GPU the library runs on holds until the
+ * process ends, so the call allocates no device or pinned host memory (its
+ * host-side tables live on the host heap during the call).  The workspace
+ * smg_workspace_bytes reports for (g, o, nrhs) must fit in 64 MiB (e.g. an
+ * FP64 cube of 94^3 with one right-hand side); a larger request returns
+ * SMG_EWORKSPACE before any device work.  All calls on one GPU share its
+ * array: calls on one stream are ordered, calls that overlap on one GPU from
+ * different streams or unordered host threads race.  The call synchronises
+ * `stream` once (after uploading the tables) and returns with the V-cycle
+ * enqueued on it. */
+int smg_apply_static(const smg_grid *g, const smg_opts *o, const double *r, double *s, int32_t nrhs, int64_t ld,
+                     void *stream);
+
 /* y = A x for nrhs vectors; x and y must not overlap. */
 int smg_matvec(smg_handle *h, const double *x, double *y, int32_t nrhs, int64_t ld, void *stream);
 

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
 #include <utility>
@@ -1022,6 +1023,31 @@ int fill_handle(smg_handle *h, const smg_grid *g, const smg_opts *o, int32_t max
     return arith_size(o->precision) == 8 ? upload_tables<double>(h, t, st) : upload_tables<float>(h, t, st);
 }
 
+// Device scratch of smg_apply_static: one copy per GPU, held until the
+// process ends.  Host code never uses the array's name as an address; it uses
+// the per-device address from hipGetSymbolAddress, looked up once per device
+// with that device current.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(char **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SMG_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SMG_EHIP;
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SMG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1063,6 +1089,26 @@ int smg_setup(const smg_grid *g, const smg_opts *o, int32_t max_nrhs, void *ws, 
     }
     *out = h;
     return SMG_OK;
+}
+
+int smg_apply_static(const smg_grid *g, const smg_opts *o, const double *r, double *s, int32_t nrhs, int64_t ld,
+                     void *stream)
+{
+    if (check_grid(g, o) != SMG_OK || !r || !s || nrhs < 1) return SMG_EINVAL;
+    if (ld < static_cast<int64_t>(g->nx) * g->ny * g->nz) return SMG_EINVAL;
+    char *ws = nullptr;
+    const int rc0 = static_scratch(&ws);
+    if (rc0 != SMG_OK) return rc0;
+    hipStream_t st = as_stream(stream);
+    try {
+        smg_handle h{};
+        const int rc = fill_handle(&h, g, o, nrhs, ws, kStaticScratchBytes, st, false);
+        if (rc != SMG_OK) return rc;
+        vcycle(&h, r, s, nrhs, ld, st);
+    } catch (const std::bad_alloc &) {
+        return SMG_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? SMG_OK : SMG_EHIP;
 }
 
 int smg_apply(smg_handle *h, const double *r, double *s, int32_t nrhs, int64_t ld, void *stream)

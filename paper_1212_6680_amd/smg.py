@@ -94,6 +94,7 @@ def lib():
         L.smg_setup.argtypes = [C.POINTER(smg_grid), C.POINTER(smg_opts), i32, p, C.c_size_t, p,
                                 C.POINTER(p)]
         L.smg_apply.argtypes = [p, p, p, i32, i64, p]
+        L.smg_apply_static.argtypes = [C.POINTER(smg_grid), C.POINTER(smg_opts), p, p, i32, i64, p]
         L.smg_matvec.argtypes = [p, p, p, i32, i64, p]
         for f in (L.pcg_solve, L.fpcg_solve, L.psd_solve):
             f.argtypes = [p, p, p, C.POINTER(krylov_opts), C.POINTER(krylov_info), p]
@@ -196,6 +197,24 @@ def _same_layout(a: torch.Tensor, b: torch.Tensor):
 
 class Info(dict):
     __getattr__ = dict.__getitem__
+
+
+def apply_static(shape, r: torch.Tensor, s: torch.Tensor | None = None, c=(1.0, 1.0, 1.0), pre=1, post=1,
+                 inner_pre=-1, inner_post=-1, order=0, precision="f64", kernel_mode=0) -> torch.Tensor:
+    """s = T r through smg_apply_static: no handle, no workspace, no device
+    allocation by the library (the hierarchy lives in its static scratch)."""
+    shape = tuple(int(v) for v in shape)
+    n = shape[0] * shape[1] * shape[2]
+    nrhs, ld = _block(r, n)
+    if s is None:
+        s = _like(r)
+    _same_layout(r, s)
+    _on_device(r, s)
+    grid = smg_grid(*shape, *[float(v) for v in c])
+    opts = smg_opts(pre, post, inner_pre, inner_post, order, PREC[precision], kernel_mode)
+    _check(lib().smg_apply_static(C.byref(grid), C.byref(opts), C.c_void_p(r.data_ptr()), C.c_void_p(s.data_ptr()),
+                                  nrhs, ld, _stream()), "smg_apply_static")
+    return s
 
 
 class SMG:
