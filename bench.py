@@ -258,6 +258,79 @@ def learned_config(torch, dev, npairs=2000, steps=2000):
     return out
 
 
+def host_cpu_info():
+    """The host's processors as lscpu reports them, and the CPUs this process may use."""
+    import subprocess
+    info = {"logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = dict((k.strip(), v.strip()) for k, v in (ln.split(":", 1) for ln in txt.splitlines() if ":" in ln))
+        for key, name in (("Model name", "model"), ("Socket(s)", "sockets"), ("Core(s) per socket", "cores_per_socket"),
+                          ("Thread(s) per core", "threads_per_core"), ("CPU max MHz", "max_mhz")):
+            if key in kv:
+                info[name] = kv[key]
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def oracle_beside(torch, dev, configs):
+    """The CPU oracle timed beside the GPU on the other workloads: every
+    method and smoothing at 32^3 (whole solves, both sides); FPCG-SMG(1,0) at
+    384^3 in FP64 (whole solve); LOBPCG m = 16 at 128^3 on a bounded sample of
+    3 iterations (the oracle's per-iteration time beside the GPU's)."""
+    import synth
+    from oracle import lobpcg as OL
+    from oracle import oracle as O
+    from paper_1212_6680_amd.smg import SMG
+    res = {"threads": O.num_threads()}
+    n = 32
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    b = synth.rhs(n, n, n, 1)
+    bd = torch.from_numpy(b).to(dev)
+    c1 = {}
+    for pp in ((1, 1), (1, 0)):
+        S = O.SMG(shape, c, *pp)
+        G = SMG(shape, c, *pp)
+        for name, meth in (("pcg", O.PCG), ("fpcg", O.FPCG), ("psd", O.PSD)):
+            maxit = 100 if (name == "pcg" and pp == (1, 0)) else 500
+            t0 = time.perf_counter()
+            ref = O.krylov(meth, b, shape, c, S, max_iter=maxit, history=False)
+            t_cpu = time.perf_counter() - t0
+            getattr(G, name)(bd, max_iter=3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = getattr(G, name)(bd, max_iter=maxit)
+            torch.cuda.synchronize()
+            c1[f"{name}_{pp[0]}{pp[1]}"] = {"oracle_s": t_cpu, "oracle_iters": ref.iters, "gpu_s": time.perf_counter() - t0,
+                                            "gpu_iters": info.iters, "status": [ref.status, info.status]}
+    res["c1_32"] = c1
+    n = 384
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    b = synth.rhs(n, n, n, 5)
+    S = O.SMG(shape, c, 1, 0)
+    t0 = time.perf_counter()
+    ref = O.krylov(O.FPCG, b, shape, c, S, history=False)
+    g = configs.get("fpcg_384_smg_f64", {})
+    res["c4_384_f64"] = {"oracle_s": time.perf_counter() - t0, "oracle_iters": ref.iters, "gpu_s": g.get("s"),
+                         "gpu_iters": g.get("iters")}
+    del S, ref, b
+    n, m, its = 128, 16, 3
+    shape, c = (n, n, n), ((n + 1.0) ** 2,) * 3
+    S = O.SMG(shape, c, 1, 0)
+    X0 = synth.block(n ** 3, m, 3)
+    apply_A = lambda V: np.stack([O.matvec(v, shape, c) for v in V])
+    apply_T = lambda V: np.stack([S.apply(v) for v in V])
+    t0 = time.perf_counter()
+    OL.lobpcg(apply_A, apply_T, X0, rtol=1e-8, max_iter=its)
+    t_cpu = time.perf_counter() - t0
+    g = configs.get("lobpcg_128_m16", {})
+    res["c3a_lobpcg_128_m16"] = {"oracle_s_per_iter": t_cpu / its, "sample": f"{its} iterations (setup included)",
+                                 "gpu_s_per_iter": (g["s"] / g["iters"]) if g.get("iters") else None}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +338,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single-thread", action="store_true", help="skip the single-threaded oracle leg")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned post-smoother workload")
     ap.add_argument("--no-configs", action="store_true",
@@ -449,13 +523,24 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         S = O.SMG(shape, c, 1, 0)
+        threads = O.num_threads()
         t0 = time.perf_counter()
         r = O.krylov(O.FPCG, b_host, shape, c, S, rtol=1e-8, max_iter=500, history=False)
         t_cpu = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": t_cpu, "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+        out["cpu_baseline"] = {"value": t_cpu, "unit": "s", "cores": threads, "kind": "oracle",
                                "sample": f"the whole FPCG-SMG(1,0) solve at {n}^3 ({r.iters} iterations, "
                                          f"setup excluded), FP64 C/OpenMP oracle",
-                               "iters": r.iters}
+                               "iters": r.iters, "host": host_cpu_info()}
+        if not args.no_single_thread:
+            O.set_num_threads(1)
+            t0 = time.perf_counter()
+            r1 = O.krylov(O.FPCG, b_host, shape, c, S, rtol=1e-8, max_iter=500, history=False)
+            out["cpu_baseline"]["single_thread"] = {"value": time.perf_counter() - t0, "unit": "s", "cores": 1,
+                                                    "iters": r1.iters}
+            O.set_num_threads(threads)
+        del S
+        if not args.no_configs:
+            out["oracle_beside"] = oracle_beside(torch, dev, out.get("configs", {}))
     print(json.dumps(out))
 
 

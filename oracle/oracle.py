@@ -57,6 +57,7 @@ def lib():
                                     C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_krylov.restype = i
         L.oracle_num_threads.restype = i
+        L.oracle_set_num_threads.argtypes = [i]
         _lib = L
     return _lib
 
@@ -68,6 +69,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops from now on."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def matvec(x: np.ndarray, shape, c=(1.0, 1.0, 1.0)) -> np.ndarray:

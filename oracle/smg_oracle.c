@@ -575,3 +575,14 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the parallel loops from here on (for timing the oracle on one
+ * core beside all of them). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
