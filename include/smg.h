@@ -269,6 +269,34 @@ int smg_set_march(smg_handle *h, int32_t march_waves);
 int lobpcg_profile_gram(smg_handle *h, int32_t m, int32_t k, void *ws, size_t ws_bytes, int32_t reps, void *stream,
                         double *ms);
 
+/* Section 5 diagnostics.  Assumption (4) of the convergence bound (3) for PSD
+ * reads ||I - c A T||_{A^{-1}} <= delta < 1; with r = A e this is the operator
+ * norm ||I - c T A||_A.  Power iteration on E# E, where E = I - c T A and
+ * E# = I - c T^T A is its adjoint in the A inner product, gives Rayleigh
+ * quotients that increase to delta(c)^2.
+ *
+ * smg_delta: delta(c) for the preconditioner of h after `iters` (>= 1) power
+ * steps from the device vector v0 (nx*ny*nz doubles, nonzero).  ht must hold
+ * T's transpose: the same grid and options with pre and post swapped (the
+ * transposed V-cycle runs the adjoint sweeps in reverse order; with the
+ * restriction P^T of the prolongation P the result is exact), or h itself
+ * when pre = post.  work: device, 5*nx*ny*nz doubles.  Each step costs two
+ * V-cycles and two stencil passes and synchronises the stream.
+ * smg_delta_min: min over c in [c_lo, c_hi] of delta(c) (golden-section
+ * search to relative width tol; delta(c) is convex in c), the best c in
+ * *c_best: the scaling-free form of assumption (4).
+ * smg_spectrum: for an SPD T (pre = post), the extreme eigenvalues of T A
+ * (self-adjoint in the A inner product) by power iteration on T A and then on
+ * lambda_max I - T A, `iters` steps each; work: 3*nx*ny*nz doubles.  With
+ * Theorem 2's prescaling c = 2 / (lambda_min + lambda_max), delta(c) =
+ * (kappa - 1) / (kappa + 1), kappa = lambda_max / lambda_min. */
+int smg_delta(smg_handle *h, smg_handle *ht, double c, const double *v0, int32_t iters, double *work, double *delta,
+              void *stream);
+int smg_delta_min(smg_handle *h, smg_handle *ht, double c_lo, double c_hi, double tol, const double *v0,
+                  int32_t iters, double *work, double *c_best, double *delta, void *stream);
+int smg_spectrum(smg_handle *h, const double *v0, int32_t iters, double *work, double *lmin, double *lmax,
+                 void *stream);
+
 /* Releases the host-side handle (the caller's workspace is not freed). */
 int smg_destroy(smg_handle *h);
 

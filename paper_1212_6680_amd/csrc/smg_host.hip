@@ -947,6 +947,8 @@ int smg_handle_size(const smg_handle *h, size_t *n)
 
 const smg_grid *smg_handle_grid(const smg_handle *h) { return h ? &h->g : nullptr; }
 
+double *smg::handle_partials(smg_handle *h) { return h->at<double>(h->L.part); }
+
 int smg::krylov_view(smg_handle *h, KrylovView *v)
 {
     if (!h || !v) return SMG_EINVAL;

@@ -385,4 +385,9 @@ void vcycle_apply(smg_handle *h, const double *r, double *s, int nrhs, long long
 
 // Handle queries shared by the library's translation units.
 int smg_handle_size(const smg_handle *h, size_t *n);
+const smg_grid *smg_handle_grid(const smg_handle *h);
+namespace smg {
+// the handle's reduction partials (2 * kRedBlocks doubles), free between solver steps
+double *handle_partials(smg_handle *h);
+}  // namespace smg
 int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs);

@@ -108,6 +108,9 @@ def lib():
             L.lobpcg_solve.argtypes = [p, i32, p, p, p, p, C.c_size_t,
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
         L.smg_autotune.argtypes = [p, p, p, i32, p, C.POINTER(smg_tune_info)]
+        L.smg_delta.argtypes = [p, p, d, p, i32, p, C.POINTER(d), p]
+        L.smg_delta_min.argtypes = [p, p, d, d, d, p, i32, p, C.POINTER(d), C.POINTER(d), p]
+        L.smg_spectrum.argtypes = [p, p, i32, p, C.POINTER(d), C.POINTER(d), p]
         L.smg_get_schedule.argtypes = [p, C.POINTER(smg_tune_info)]
         L.smg_set_march.argtypes = [p, i32]
         L.smg_batch_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
@@ -374,6 +377,41 @@ class SMG:
         out = Info(iters=info.iters, nconv=info.nconv, status=info.status, seconds=info.seconds,
                    resnorms=np.array(res[:]))
         return np.array(lam[:]), X, out
+
+    def _theory_args(self, ht, v0, nwork):
+        if ht is not None and ht.n != self.n:
+            raise SMGError("the transposed preconditioner must be on the same grid")
+        _dptr(v0, self.n)
+        return torch.empty(nwork * self.n, dtype=torch.float64, device=v0.device)
+
+    def delta(self, c: float, v0: torch.Tensor, iters: int = 50, transpose: "SMG | None" = None) -> float:
+        """Power-iteration estimate of ||I - c A T||_{A^{-1}} (Section 5, assumption (4));
+        transpose: a handle of T's transpose (pre and post swapped), self when omitted."""
+        ht = self if transpose is None else transpose
+        work = self._theory_args(ht, v0, 5)
+        out = C.c_double(0)
+        _check(lib().smg_delta(self.h, ht.h, float(c), _dptr(v0, self.n), int(iters), C.c_void_p(work.data_ptr()),
+                               C.byref(out), _stream()), "smg_delta")
+        return out.value
+
+    def delta_min(self, v0: torch.Tensor, c_lo=0.5, c_hi=2.0, tol=1e-3, iters: int = 50,
+                  transpose: "SMG | None" = None):
+        """(c, min_c ||I - c A T||_{A^{-1}}) by golden-section search over [c_lo, c_hi]."""
+        ht = self if transpose is None else transpose
+        work = self._theory_args(ht, v0, 5)
+        cb, out = C.c_double(0), C.c_double(0)
+        _check(lib().smg_delta_min(self.h, ht.h, float(c_lo), float(c_hi), float(tol), _dptr(v0, self.n), int(iters),
+                                   C.c_void_p(work.data_ptr()), C.byref(cb), C.byref(out), _stream()),
+               "smg_delta_min")
+        return cb.value, out.value
+
+    def spectrum(self, v0: torch.Tensor, iters: int = 50):
+        """(lambda_min, lambda_max) of T A for an SPD T (pre = post) by power iteration."""
+        work = self._theory_args(None, v0, 3)
+        lo, hi = C.c_double(0), C.c_double(0)
+        _check(lib().smg_spectrum(self.h, _dptr(v0, self.n), int(iters), C.c_void_p(work.data_ptr()), C.byref(lo),
+                                  C.byref(hi), _stream()), "smg_spectrum")
+        return lo.value, hi.value
 
     def autotune(self, r: torch.Tensor, reps: int = 5):
         """Times the candidate fused schedules on r and keeps the fastest; returns the tuning info."""

@@ -115,10 +115,11 @@ def test_batched_rhs_equal_single_rhs_bitwise():
         si = G.apply(_dev(R[i])).cpu().numpy()
         assert np.array_equal(Sb[i], si)
     # and with a leading dimension larger than n
-    Rp = np.zeros((3, np.prod(shape) + 64))
-    Rp[:, :np.prod(shape)] = R[:3]
-    Sp = G.apply(_dev(Rp)).cpu().numpy()
-    assert np.array_equal(Sp[:, :np.prod(shape)], Sb[:3])
+    n = int(np.prod(shape))
+    Rp = np.zeros((3, n + 64))
+    Rp[:, :n] = R[:3]
+    Sp = G.apply(_dev(Rp)[:, :n]).cpu().numpy()          # rows of a padded block: ld = n + 64
+    assert np.array_equal(Sp, Sb[:3])
 
 
 def test_repeatable_bitwise():
