@@ -27,6 +27,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int kT = 64;      // output tile edge of the MFMA kernels
+constexpr int kNarrow = 8;  // bases of at most this many columns use the streaming kernels
 constexpr int kK = 16;      // reduction slice staged in LDS per step
 constexpr int kLdsPad = 4;  // LDS row padding (doubles)
 
@@ -437,6 +438,83 @@ __global__ __launch_bounds__(256) void k_block_update_wide(
     }
 }
 
+// Narrow bases (k <= K <= 8 columns: LOBPCG with m <= 2).  A product over a
+// few columns moves 8 N k bytes per operand and does ~k flops per byte read,
+// far from the matrix cores' regime: plain streaming kernels whose threads
+// keep every column of a row in registers run at the memory's pace, where the
+// 16-column MFMA tiles would spend most of their work on padding.
+//
+// part[z][i][j] = sum over rows of slice z of U[n, i] V[n, j], i, j < k (with
+// SYM, V = U and the lower triangle mirrored); fixed slices and a fixed
+// reduction order, like the tiled Gram kernels.
+template <int K, bool SYM>
+__global__ __launch_bounds__(256) void k_gram_narrow(const double *U, const double *V, long long ld, int k, long long n,
+                                                     long long slice, double *part)
+{
+    __shared__ double sums[4][K * K];
+    const int z = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long beg = static_cast<long long>(z) * slice;
+    const long long end = beg + slice < n ? beg + slice : n;
+    double acc[K][K];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[i][j] = 0.0;
+    for (long long e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        double u[K], v[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            u[i] = i < k ? U[e + i * ld] : 0.0;
+            if (!SYM) v[i] = i < k ? V[e + i * ld] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (!SYM || j >= i) acc[i][j] += u[i] * (SYM ? u[j] : v[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (SYM && j < i) continue;
+            double t = acc[i][j];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+            if (lane == 0) sums[w][i * K + j] = t;
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+        const int i = t / k, j = t % k;
+        const int src = SYM && j < i ? j * K + i : i * K + j;
+        part[static_cast<long long>(z) * k * k + t] = ((sums[0][src] + sums[1][src]) + sums[2][src]) + sums[3][src];
+    }
+}
+
+// Y[:, j] = sum_{i<k} U[:, i] C[i][j] for j < mo (C row-major k x mo, k <= K,
+// mo <= 16); columns from jsplit on go to Y2 (column jsplit + c to Y2[:, c]).
+template <int K>
+__global__ __launch_bounds__(256) void k_update_narrow(const double *U, long long ld, int k, const double *C, int mo,
+                                                       double *Y, double *Y2, int jsplit, long long n)
+{
+    __shared__ double Cs[K * 16];
+    for (int t = threadIdx.x; t < k * mo; t += blockDim.x) Cs[(t / mo) * 16 + t % mo] = C[t];
+    __syncthreads();
+    for (long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        double u[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) u[i] = i < k ? U[e + i * ld] : 0.0;
+        for (int j = 0; j < mo; ++j) {
+            double y = 0.0;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (i < k) y += u[i] * Cs[i * 16 + j];
+            (j < jsplit ? Y + j * ld : Y2 + (j - jsplit) * ld)[e] = y;
+        }
+    }
+}
+
 // part[c][z] = sum over slice z of U[:, c] .* V[:, c]
 __global__ __launch_bounds__(256) void k_coldot_partial(const double *U, const double *V, long long ld, long long n,
                                                         long long slice, double *part, int nslices)
@@ -557,7 +635,9 @@ LobLayout lob_layout(size_t N, int m)
     L.G = take(k3 * k3 * 8);
     L.C = take(k3 * 2 * m * 8 + k3 * k3 * 8);
     L.theta = take(k3 * 8);
-    L.nslices_col = static_cast<int>(std::min<long long>(256, (N + 4095) / 4096));
+    // column passes: enough slices to fill the chip when the block is narrow
+    L.nslices_col = static_cast<int>(
+        std::min<long long>(std::max<long long>(256, 2048 / m), static_cast<long long>((N + 4095) / 4096)));
     if (L.nslices_col < 1) L.nslices_col = 1;
     L.cpart = take(k3 * L.nslices_col * 8 * 2);
     L.cout = take(k3 * 8 * 2);
@@ -582,6 +662,30 @@ struct Lob {
     void gram_launch(const double *U, int p, const double *V, int q, bool sym)
     {
         const int s = sym && p == q ? 1 : 0;
+        if (s && p <= kNarrow) {   // a few columns: streaming kernel
+            const long long ln = static_cast<long long>(N);
+            const long long want = std::min<long long>(1024, L.nslices_gram);
+            const long long sl = (ln + want - 1) / want;
+            const int nz = static_cast<int>((ln + sl - 1) / sl);
+            double *pt = at<double>(L.part);
+            if (U == V) {
+                if (p <= 4)
+                    hipLaunchKernelGGL((k_gram_narrow<4, true>), dim3(nz), dim3(256), 0, st, U, V, ln, p, ln, sl, pt);
+                else
+                    hipLaunchKernelGGL((k_gram_narrow<kNarrow, true>), dim3(nz), dim3(256), 0, st, U, V, ln, p, ln, sl,
+                                       pt);
+            } else {
+                if (p <= 4)
+                    hipLaunchKernelGGL((k_gram_narrow<4, false>), dim3(nz), dim3(256), 0, st, U, V, ln, p, ln, sl,
+                                       pt);
+                else
+                    hipLaunchKernelGGL((k_gram_narrow<kNarrow, false>), dim3(nz), dim3(256), 0, st, U, V, ln, p, ln,
+                                       sl, pt);
+            }
+            hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 64)), dim3(64 * kRedGroups), 0, st,
+                               pt, nz, p, q, 16, 0, at<double>(L.G));
+            return;
+        }
         if (s && p <= kTriMax) {   // narrow: all upper 16-blocks per block, slices of N
             // one block per CU for the widest instance; the narrower ones fit
             // two and four per CU
@@ -645,6 +749,17 @@ struct Lob {
         if (!Y2) jsplit = mo;
         if (hipMemcpyAsync(at<double>(L.C), C.data(), C.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
+        if (k <= kNarrow && mo <= 16) {   // a few columns: streaming kernel
+            const long long ln = static_cast<long long>(N);
+            const unsigned nb = std::min<unsigned>(nblk(ln, 256), 4096);
+            if (k <= 4)
+                hipLaunchKernelGGL(k_update_narrow<4>, dim3(nb), dim3(256), 0, st, U, ln, k, at<double>(L.C), mo, Y,
+                                   Y2, jsplit, ln);
+            else
+                hipLaunchKernelGGL(k_update_narrow<kNarrow>, dim3(nb), dim3(256), 0, st, U, ln, k, at<double>(L.C), mo,
+                                   Y, Y2, jsplit, ln);
+            return hipStreamSynchronize(st) == hipSuccess && ok();
+        }
         // one 64-column tile of k_block_update reads U once already; it is
         // kept for 49..64 columns, where the 4-block instance needs 195 VGPRs
         if (mo <= kTriMax && (mo <= 48 || mo > kT)) {

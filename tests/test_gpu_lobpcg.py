@@ -94,3 +94,21 @@ def test_lobpcg_full_size_128(m, guard):
     for i in (0, m // 2, m - 1):
         r = O.matvec(Xh[i], shape, c) - lam[i] * Xh[i]
         assert np.linalg.norm(r) <= 1.01e-8 * lam[i] * np.linalg.norm(Xh[i])
+
+
+@pytest.mark.parametrize("shape,m,guard,pp", [((24, 20, 16), 1, 0, (1, 0)), ((24, 20, 16), 2, 0, (1, 1)),
+                                              ((16, 32, 16), 1, 1, (1, 0)), ((30, 12, 9), 2, 0, (1, 0)),
+                                              ((9, 40, 20), 1, 0, (1, 1))])
+def test_lobpcg_narrow_blocks(shape, m, guard, pp):
+    """Bases of at most 8 columns (m + guard <= 2) take the streaming Gram and
+    update kernels: eigenvalues against the closed form, orthonormal output."""
+    c = (1.0, 1.0, 1.0)
+    mb = m + guard
+    N = int(np.prod(shape))
+    G = _smg(shape, c, *pp, max_nrhs=mb)
+    lam, X, info = G.lobpcg(torch.from_numpy(synth.block(N, mb, 5)).cuda(), rtol=1e-8, max_iter=300, guard=guard)
+    assert info.status == 0 and info.nconv == m
+    ex = D.smallest_eigenvalues(shape, c, m)
+    assert np.max(np.abs(lam[:m] - ex) / ex) <= 1e-10
+    Xh = X.cpu().numpy()
+    assert np.abs(Xh @ Xh.T - np.eye(mb)).max() <= 1e-11
