@@ -91,3 +91,72 @@ def he_init(seed: int) -> np.ndarray:
         out.append(0.01 * gaussian(seed, co, pos))
         pos += co
     return np.concatenate(out)
+
+
+# --- variable-coefficient problems -----------------------------------------
+# A diffusion problem -div(kappa grad u) on the brick, discretised like the
+# model problem (one unknown per grid point, neighbours outside the brick are
+# zero): the coupling across the face between two neighbours is the axis
+# factor times the harmonic mean of their conductivities (kappa itself across a
+# boundary face), and the diagonal is the sum of the six face couplings.  With
+# kappa = 1 this is the model operator with coefficients c.
+
+def conductivity(shape, kind: str, seed: int, contrast: float = 1e3):
+    """Per-point conductivities (kx, ky, kz) of a named test field, x fastest:
+    "const": 1 everywhere;
+    "layers": z-layers of 2..9 planes, alternately 1 and `contrast`;
+    "aniso_layers": the same layers, with kx = 100 ky inside every other layer;
+    "lognormal": exp(1.5 g), g standard normal i.i.d. per point."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    one = np.ones(n)
+    if kind == "const":
+        return one, one.copy(), one.copy()
+    if kind in ("layers", "aniso_layers"):
+        u = uniform01(seed, nz)
+        kz_plane, ax_plane = np.empty(nz), np.ones(nz)
+        k, layer = 0, 0
+        while k < nz:
+            t = 2 + int(u[k] * 8)
+            kz_plane[k:k + t] = contrast if layer % 2 else 1.0
+            if kind == "aniso_layers" and layer % 2 == 0:
+                ax_plane[k:k + t] = 100.0
+            k += t
+            layer += 1
+        kap = np.repeat(kz_plane, nx * ny)
+        return kap * np.repeat(ax_plane, nx * ny), kap.copy(), kap.copy()
+    if kind == "lognormal":
+        kap = np.exp(1.5 * gaussian(seed, n))
+        return kap, kap.copy(), kap.copy()
+    raise ValueError(kind)
+
+
+def diffusion_stencil(shape, kx, ky, kz, c=(1.0, 1.0, 1.0)):
+    """(diag, ax, ay, az) of the 7-point operator: A[p, p+e] = -a_e[p] for the
+    neighbour p+e along each axis (a_e = 0 where p+e is outside the brick) and
+    A[p, p] = diag[p]."""
+    nx, ny, nz = shape
+    shp = (nz, ny, nx)
+    K = [np.asarray(v, dtype=np.float64).reshape(shp) for v in (kx, ky, kz)]
+    diag = np.zeros(shp)
+    out = []
+    for axis, (Kx, cc) in enumerate(zip(K, c)):
+        ax3 = 2 - axis                       # array axis of this grid axis (z, y, x order)
+        a = np.zeros(shp)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax3] = slice(0, -1)
+        hi[ax3] = slice(1, None)
+        lo, hi = tuple(lo), tuple(hi)
+        a[lo] = cc * 2.0 * Kx[lo] * Kx[hi] / (Kx[lo] + Kx[hi])
+        diag += a
+        diag[hi] += a[lo]
+        # the two boundary faces along this axis couple to zero values outside
+        first = [slice(None)] * 3
+        last = [slice(None)] * 3
+        first[ax3] = 0
+        last[ax3] = -1
+        diag[tuple(first)] += cc * Kx[tuple(first)]
+        diag[tuple(last)] += cc * Kx[tuple(last)]
+        out.append(a.reshape(-1))
+    return diag.reshape(-1), out[0], out[1], out[2]
