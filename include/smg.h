@@ -269,6 +269,46 @@ int smg_set_march(smg_handle *h, int32_t march_waves);
 int lobpcg_profile_gram(smg_handle *h, int32_t m, int32_t k, void *ws, size_t ws_bytes, int32_t reps, void *stream,
                         double *ms);
 
+/* Variable coefficients.  SMG was designed for general structured-grid
+ * operators (Section 1 cites Schaffer's semicoarsening multigrid); these
+ * entry points build the same V-cycle for a symmetric 7-point operator given
+ * per point (device arrays of nx*ny*nz doubles, index i + nx*(j + ny*k)):
+ *     (A x)_p = diag[p] x_p - sum over axes e of (a_e[p] x_{p+e} + a_e[p-e] x_{p-e}),
+ * a_e[p] being ignored where p+e is outside the brick (for a diffusion
+ * operator, a_e is the coupling across the face between p and p+e and diag
+ * the sum of the six face couplings).  The operator should be symmetric
+ * positive definite.  Per 3D level the Galerkin operator P^T A P is stored per
+ * point (15-point: 5 in-plane points on 3 planes), every plane has its own
+ * 2D hierarchy (9-point) and every x-line its own LU factors.  Prolongation
+ * weights of an even (F) plane from its two C-plane neighbours:
+ * SMG_INTERP_LINEAR: 1/2 each; SMG_INTERP_OPERATOR: from the F-point's
+ * collapsed couplings a (to the plane below) and b (above), a/(a+b) and
+ * b/(a+b), following jumps of the coefficients across planes (1/2 each where
+ * they are not both positive); the same rule in y inside planes.  With
+ * constant coefficients both give the model problem's V-cycle.
+ * The returned handle is used like smg_setup's with smg_apply, smg_matvec,
+ * pcg_solve, fpcg_solve, psd_solve, lobpcg_solve and the Section 5
+ * diagnostics; opts->precision must be SMG_PREC_F64 (kernel_mode is
+ * ignored).  smg_autotune, smg_profile_kernel, the batched solver and the
+ * learned post-smoother reject such handles (SMG_EINVAL).  The caller's
+ * coefficient arrays are read during setup only. */
+enum { SMG_INTERP_LINEAR = 0, SMG_INTERP_OPERATOR = 1 };
+int smgv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const smg_opts *o, int32_t interp, int32_t max_nrhs,
+                         size_t *bytes);
+int smgv_setup(int32_t nx, int32_t ny, int32_t nz, const double *diag, const double *ax, const double *ay,
+               const double *az, int32_t interp, const smg_opts *o, int32_t max_nrhs, void *ws, size_t ws_bytes,
+               void *stream, smg_handle **out);
+/* Number of 3D levels and of 2D levels per plane of a variable handle. */
+int smgv_levels(const smg_handle *h, int32_t *nlev3, int32_t *nlev2);
+/* Copies the stored operator of 3D level `level` into the device buffer out:
+ * with level2 = -1, eight arrays of nz_l*nx*ny doubles (the entries of the
+ * in-plane block C_k: centre, to (i+1,j), to (i,j+1); of the coupling U_k
+ * from plane k to plane k+1: to (i,j), (i+1,j), (i-1,j), (i,j+1), (i,j-1));
+ * with level2 >= 0, the 2D level of every plane of that 3D level, five arrays
+ * of nz_l*ny_l2*nx doubles (line block: centre, to i+1; coupling of line j to
+ * line j+1: to i, i+1, i-1).  Matrix entries, not negated.  Synchronises. */
+int smgv_export(smg_handle *h, int32_t level, int32_t level2, double *out, void *stream);
+
 /* Section 5 diagnostics.  Assumption (4) of the convergence bound (3) for PSD
  * reads ||I - c A T||_{A^{-1}} <= delta < 1; with r = A e this is the operator
  * norm ||I - c T A||_A.  Power iteration on E# E, where E = I - c T A and

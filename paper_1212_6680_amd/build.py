@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libsmg.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["smg_kernels.hip", "smg_fused.hip", "krylov_kernels.hip", "smg_host.hip", "lobpcg.hip",
-           "net_kernels.hip", "net_host.hip", "batch.hip", "theory.hip"]
+           "net_kernels.hip", "net_host.hip", "batch.hip", "theory.hip", "varcoef.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -179,7 +179,7 @@ int check_boxes(smg_handle *const *hs, int nbox, std::vector<KrylovView> &kv)
     if (!hs || nbox < 1) return SMG_EINVAL;
     kv.resize(nbox);
     for (int i = 0; i < nbox; ++i) {
-        if (!hs[i] || krylov_view(hs[i], &kv[i]) != SMG_OK) return SMG_EINVAL;
+        if (!hs[i] || smg_handle_is_var(hs[i]) || krylov_view(hs[i], &kv[i]) != SMG_OK) return SMG_EINVAL;
         if (kv[i].precision != SMG_PREC_F64) return SMG_EINVAL;
         for (int j = 0; j < i; ++j)
             if (hs[j] == hs[i]) return SMG_EINVAL;

@@ -574,7 +574,7 @@ int net_train(net_handle *n, int32_t nx, int32_t ny, int32_t nz, const void *inp
 int net_correct(net_handle *n, smg_handle *h, const double *r, const double *s, double *out, double *sigma,
                 void *stream)
 {
-    if (!n || !h || !r || !s || !out) return SMG_EINVAL;
+    if (!n || !h || !r || !s || !out || smg_handle_is_var(h)) return SMG_EINVAL;
     const smg_grid *g = smg_handle_grid(h);
     if (!grid_ok(n, g->nx, g->ny, g->nz)) return SMG_EINVAL;
     hipStream_t st = as_st(stream);
@@ -598,7 +598,7 @@ int net_make_pairs(net_handle *n, smg_handle *h_pre, smg_handle *h_exact, int32_
                    void *stream)
 {
     if (!n || !n->train || !h_pre || !h_exact || npairs < 1 || !inputs || !targets || !(exact_rtol > 0.0) ||
-        exact_max_iter < 1)
+        exact_max_iter < 1 || smg_handle_is_var(h_pre) || smg_handle_is_var(h_exact))
         return SMG_EINVAL;
     const smg_grid *g = smg_handle_grid(h_pre);
     const smg_grid *ge = smg_handle_grid(h_exact);
@@ -644,7 +644,7 @@ int net_make_pairs(net_handle *n, smg_handle *h_pre, smg_handle *h_exact, int32_
 int fpcg_learned_solve(smg_handle *h, net_handle *n, const double *b, double *x, const krylov_opts *o,
                        krylov_info *info, net_solve_info *ninfo, void *stream)
 {
-    if (!h || !n || !o) return SMG_EINVAL;
+    if (!h || !n || !o || smg_handle_is_var(h)) return SMG_EINVAL;
     const smg_grid *g = smg_handle_grid(h);
     if (!grid_ok(n, g->nx, g->ny, g->nz) || o->precond != SMG_PRECOND_SMG) return SMG_EINVAL;
     HookCtx ctx{n, h};

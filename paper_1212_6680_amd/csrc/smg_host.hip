@@ -104,6 +104,7 @@ struct smg_handle {
     char *ws;
     Layout L;
     KScalars *host_sc;            // pinned host mirror of the device scalars
+    smg::VarHier *var = nullptr;  // variable-coefficient hierarchy (smgv_setup), else null
     // per-kernel profiling: launches of family prof_family get dispatch-stamped
     // events and their algorithmic bytes are summed
     bool prof;
@@ -679,6 +680,10 @@ void run_vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long l
 
 void vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
 {
+    if (h->var) {
+        var_vcycle(h->var, r, s, nrhs, ld, st);
+        return;
+    }
     switch (h->o.precision) {
     case SMG_PREC_F64: run_vcycle<double, double>(h, r, s, nrhs, ld, st); break;
     case SMG_PREC_F32: run_vcycle<float, float>(h, r, s, nrhs, ld, st); break;
@@ -773,9 +778,29 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     };
     // ||x* - x||_A^2 with the diagnostic scratch (e = x* - x, then A e)
     double *de = diag ? o->diag_work : nullptr, *dw = diag ? o->diag_work + n : nullptr;
+    // the operator's passes: the 7-point model stencil, or the handle's
+    // variable-coefficient operator
+    auto op_matvec = [&](const double *in, double *out) {
+        if (h->var)
+            var_matvec(h->var, in, out, 1, static_cast<long long>(n), st);
+        else
+            launch_matvec7(in, out, static_cast<long long>(n), 1, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, st);
+    };
+    auto op_resid = [&](const double *bb, const double *xx, double *rr, int x_zero) {
+        if (h->var)
+            var_init_resid(h->var, bb, xx, rr, x_zero, part, st);
+        else
+            launch_init_resid(bb, xx, rr, x_zero, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+    };
+    auto op_update_p_q = [&](const double *su, double *p_old, double *p_new) {
+        if (h->var)
+            var_update_p_q(h->var, su, p_old, p_new, q, sc, part, st);
+        else
+            launch_update_p_q(su, p_old, p_new, q, sc, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+    };
     auto err_a2 = [&](double *out) {
         launch_axpby(de, o->xstar, 1.0, x, -1.0, n, st);
-        launch_matvec7(de, dw, static_cast<long long>(n), 1, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, st);
+        op_matvec(de, dw);
         return device_dot2(de, dw, nullptr, nullptr, n, part, st, out, nullptr);
     };
     // End of an iteration's work on the stream (its scalars are in hs once it
@@ -796,7 +821,7 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     };
 
     if (o->x0_zero) launch_fill(x, 0.0, n, st);
-    launch_init_resid(b, x, r, o->x0_zero ? 1 : 0, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+    op_resid(b, x, r, o->x0_zero ? 1 : 0);
     launch_finalize(0, method, 0, part, sc, hs, st);
     if (!sync()) return finish(SMG_EHIP);
     if (!std::isfinite(hs->rr) || !std::isfinite(hs->bb)) return finish(SMG_ENONFINITE);
@@ -878,14 +903,14 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
             // ||r_k||_{A^{-1}} = ||x* - x_k||_A and ||A s_k||_{A^{-1}}^2 = (s_k, A s_k)
             double ea = 0.0, sas = 0.0, sr = 0.0;
             if (err_a2(&ea) != SMG_OK) return finish(SMG_EHIP);
-            launch_matvec7(su, dw, static_cast<long long>(n), 1, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, st);
+            op_matvec(su, dw);
             if (device_dot2(su, dw, su, r, n, part, st, &sas, &sr) != SMG_OK) return finish(SMG_EHIP);
             if (o->sin_angle) {
                 const double c2 = (ea > 0.0 && sas > 0.0) ? sr * sr / (ea * sas) : 1.0;
                 o->sin_angle[k] = std::sqrt(std::max(0.0, 1.0 - c2));
             }
         }
-        launch_update_p_q(su, pa, pb, q, sc, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+        op_update_p_q(su, pa, pb);
         launch_finalize(2, method, k, part, sc, nullptr, st);
         launch_update_xr(x, r, pb, q, sc, n, part, st);
         launch_finalize(3, method, k, part, sc, hs, st);
@@ -931,7 +956,7 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     inf.iters = k;
     if (status != SMG_EBREAKDOWN) status = (cstop ? cconv : rel <= o->rtol) ? SMG_OK : SMG_NOT_CONVERGED;
     inf.rel_res = rel;
-    launch_true_resid(b, x, s, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, part, st);
+    op_resid(b, x, s, 0);
     launch_finalize(0, method, 0, part, sc, hs, st);
     if (!sync()) return finish(SMG_EHIP);
     inf.true_rel_res = std::sqrt(hs->rr) / bden;
@@ -948,6 +973,8 @@ int smg_handle_size(const smg_handle *h, size_t *n)
 const smg_grid *smg_handle_grid(const smg_handle *h) { return h ? &h->g : nullptr; }
 
 double *smg::handle_partials(smg_handle *h) { return h->at<double>(h->L.part); }
+
+int smg_handle_is_var(const smg_handle *h) { return h && h->var ? 1 : 0; }
 
 int smg::krylov_view(smg_handle *h, KrylovView *v)
 {
@@ -1123,6 +1150,10 @@ int smg_apply(smg_handle *h, const double *r, double *s, int32_t nrhs, int64_t l
 int smg_matvec(smg_handle *h, const double *x, double *y, int32_t nrhs, int64_t ld, void *stream)
 {
     if (!h || !x || !y || nrhs < 1 || ld < static_cast<int64_t>(h->N) || nrhs > 65535) return SMG_EINVAL;
+    if (h->var) {
+        var_matvec(h->var, x, y, nrhs, ld, as_stream(stream));
+        return hipGetLastError() == hipSuccess ? SMG_OK : SMG_EHIP;
+    }
     launch_matvec7(x, y, ld, nrhs, h->g.nx, h->g.ny, h->g.nz, h->g.cx, h->g.cy, h->g.cz, as_stream(stream));
     return hipGetLastError() == hipSuccess ? SMG_OK : SMG_EHIP;
 }
@@ -1142,11 +1173,121 @@ int psd_solve(smg_handle *h, const double *b, double *x, const krylov_opts *o, k
     return krylov_run(h, 2, b, x, o, info, stream, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Variable coefficients
+// ---------------------------------------------------------------------------
+namespace {
+
+int check_var(int32_t nx, int32_t ny, int32_t nz, const smg_opts *o, int32_t interp)
+{
+    if (!o || nx < 1 || ny < 1 || nz < 1 || nx > kMaxNx) return SMG_EINVAL;
+    if (o->pre < 0 || o->post < 0 || o->pre > kMaxSmooth || o->post > kMaxSmooth) return SMG_EINVAL;
+    if (o->inner_pre < -1 || o->inner_post < -1 || o->inner_pre > kMaxSmooth || o->inner_post > kMaxSmooth)
+        return SMG_EINVAL;
+    if (o->order != 0 && o->order != 1) return SMG_EINVAL;
+    if (o->precision != SMG_PREC_F64) return SMG_EINVAL;
+    if (interp != SMG_INTERP_LINEAR && interp != SMG_INTERP_OPERATOR) return SMG_EINVAL;
+    return SMG_OK;
+}
+
+// Krylov vectors and scalars after the hierarchy
+Layout var_krylov_layout(size_t base, size_t N)
+{
+    Layout L{};
+    size_t off = base;
+    auto take = [&](size_t b) {
+        const size_t r = off;
+        off = (off + b + 255) / 256 * 256;
+        return r;
+    };
+    L.kr = take(N * 8);
+    L.ks = take(N * 8);
+    L.kp0 = take(N * 8);
+    L.kp1 = take(N * 8);
+    L.kq = take(N * 8);
+    L.part = take(2 * kRedBlocks * 8);
+    L.sc = take(sizeof(KScalars));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+int smgv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const smg_opts *o, int32_t interp, int32_t max_nrhs,
+                         size_t *bytes)
+{
+    if (check_var(nx, ny, nz, o, interp) != SMG_OK || max_nrhs < 1 || !bytes) return SMG_EINVAL;
+    const size_t N = static_cast<size_t>(nx) * ny * nz;
+    *bytes = var_krylov_layout(var_workspace_bytes(nx, ny, nz), N).total;
+    return SMG_OK;
+}
+
+int smgv_setup(int32_t nx, int32_t ny, int32_t nz, const double *diag, const double *ax, const double *ay,
+               const double *az, int32_t interp, const smg_opts *o, int32_t max_nrhs, void *ws, size_t ws_bytes,
+               void *stream, smg_handle **out)
+{
+    if (!out) return SMG_EINVAL;
+    *out = nullptr;
+    if (check_var(nx, ny, nz, o, interp) != SMG_OK || max_nrhs < 1 || !ws || !diag || !ax || !ay || !az)
+        return SMG_EINVAL;
+    const size_t N = static_cast<size_t>(nx) * ny * nz;
+    const Layout L = var_krylov_layout(var_workspace_bytes(nx, ny, nz), N);
+    if (ws_bytes < L.total) return SMG_EWORKSPACE;
+    hipStream_t st = as_stream(stream);
+    smg_handle *h = new (std::nothrow) smg_handle();
+    if (!h) return SMG_EINVAL;
+    h->g = smg_grid{nx, ny, nz, 1.0, 1.0, 1.0};
+    h->o = *o;
+    h->ipre = o->inner_pre < 0 ? o->pre : o->inner_pre;
+    h->ipost = o->inner_post < 0 ? o->post : o->inner_post;
+    h->max_nrhs = max_nrhs;
+    h->N = N;
+    h->E = (nx + 63) / 64;
+    h->nxp = 64 * h->E;
+    h->fused = false;
+    h->L = L;
+    h->ws = static_cast<char *>(ws);
+    h->prof = false;
+    h->ev_used = 0;
+    h->prof_bytes = 0;
+    h->host_sc = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void **>(&h->host_sc), sizeof(KScalars), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return SMG_EHIP;
+    }
+    h->var = var_create(nx, ny, nz, o, interp, h->ws, diag, ax, ay, az, st);
+    if (!h->var || hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) {
+        smg_destroy(h);
+        return SMG_EHIP;
+    }
+    *out = h;
+    return SMG_OK;
+}
+
+int smgv_levels(const smg_handle *h, int32_t *nlev3, int32_t *nlev2)
+{
+    if (!h || !h->var || !nlev3 || !nlev2) return SMG_EINVAL;
+    int a = 0, b = 0;
+    var_levels(h->var, &a, &b);
+    *nlev3 = a;
+    *nlev2 = b;
+    return SMG_OK;
+}
+
+int smgv_export(smg_handle *h, int32_t level, int32_t level2, double *out, void *stream)
+{
+    if (!h || !h->var || !out) return SMG_EINVAL;
+    const int rc = var_export(h->var, level, level2, out, as_stream(stream));
+    if (rc != SMG_OK) return rc;
+    return hipStreamSynchronize(as_stream(stream)) == hipSuccess ? SMG_OK : SMG_EHIP;
+}
+
 int smg_destroy(smg_handle *h)
 {
     if (!h) return SMG_EINVAL;
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     if (h->host_sc) (void)hipHostFree(h->host_sc);
+    if (h->var) var_destroy(h->var);
     delete h;
     return SMG_OK;
 }
@@ -1186,7 +1327,7 @@ int smg_get_schedule(const smg_handle *h, smg_tune_info *info)
 
 int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *stream, smg_tune_info *info)
 {
-    if (!h || !r || !s || reps < 1) return SMG_EINVAL;
+    if (!h || !r || !s || reps < 1 || h->var) return SMG_EINVAL;
     hipStream_t st = as_stream(stream);
     smg_tune_info inf{};
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1286,7 +1427,7 @@ int smg_autotune(smg_handle *h, const double *r, double *s, int32_t reps, void *
 int smg_profile_kernel(smg_handle *h, int32_t family, const double *r, double *s, int32_t reps, void *stream,
                        int32_t *launches, double *kernel_ms, double *bytes)
 {
-    if (!h || !r || !s || reps < 1 || !launches || !kernel_ms || !bytes) return SMG_EINVAL;
+    if (!h || !r || !s || reps < 1 || !launches || !kernel_ms || !bytes || h->var) return SMG_EINVAL;
     if (family < 0 || family >= SMG_KERNEL_COUNT) return SMG_EINVAL;
     hipStream_t st = as_stream(stream);
     if (h->ev.empty()) {

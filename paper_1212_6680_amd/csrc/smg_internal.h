@@ -389,5 +389,22 @@ const smg_grid *smg_handle_grid(const smg_handle *h);
 namespace smg {
 // the handle's reduction partials (2 * kRedBlocks doubles), free between solver steps
 double *handle_partials(smg_handle *h);
+
+// Variable-coefficient hierarchy (varcoef.hip): one per handle set up by smgv_setup
+struct VarHier;
+size_t var_workspace_bytes(int nx, int ny, int nz);
+VarHier *var_create(int nx, int ny, int nz, const smg_opts *o, int interp, char *ws, const double *diag,
+                    const double *ax, const double *ay, const double *az, hipStream_t st);
+void var_destroy(VarHier *H);
+void var_vcycle(VarHier *H, const double *r, double *s, int nrhs, long long ld, hipStream_t st);
+void var_matvec(VarHier *H, const double *x, double *y, int nrhs, long long ld, hipStream_t st);
+void var_init_resid(VarHier *H, const double *b, const double *x, double *r, int x_zero, double *partials,
+                    hipStream_t st);
+void var_update_p_q(VarHier *H, const double *s, const double *p_old, double *p_new, double *q, const KScalars *sc,
+                    double *partials, hipStream_t st);
+int var_levels(const VarHier *H, int *nlev3, int *nlev2);
+int var_export(const VarHier *H, int l, int l2, double *out, hipStream_t st);
 }  // namespace smg
+// nonzero for a handle of smgv_setup (variable coefficients)
+int smg_handle_is_var(const smg_handle *h);
 int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs);

@@ -1,0 +1,949 @@
+// SMG for a variable-coefficient 7-point operator on gfx950.
+//
+// SMG was built for general structured-grid operators (Section 1, Schaffer's
+// semicoarsening multigrid); the paper applies it to the constant Laplacian.
+// This file carries the same V-cycle (z-semicoarsening, zebra plane
+// relaxation whose plane solves are 2D y-semicoarsening cycles with zebra
+// x-line relaxation, Galerkin coarse operators, correction form, pre F then
+// C and post C then F) to a symmetric 7-point operator given per point,
+//     (A x)_p = diag_p x_p - sum_e (a_e[p] x_{p+e} + a_e[p-e] x_{p-e}),
+// where nothing is shared between points any more:
+//   * every 3D level stores its operator per point: the in-plane block C_k
+//     (5-point, symmetric: centre, east, north) and the coupling U_k from
+//     plane k to plane k+1 (5-point: centre, east, west, north, south);
+//   * prolongation has one weight per point of an even (F) plane for each of
+//     its two C-plane neighbours: 1/2 (linear), or the F-point's collapsed
+//     couplings to the two planes, a/(a+b) and b/(a+b) (operator-dependent);
+//     an F-plane with one C-neighbour takes 1/2 from it;
+//   * the Galerkin product P^T A P is formed per coarse point from the fine
+//     blocks and the diagonal weight matrices; the products of diagonal
+//     weights with 5-point blocks stay 5-point, so coarse 3D levels are
+//     15-point (5 in-plane points on 3 planes);
+//   * every plane of every 3D level has its own 2D hierarchy built the same
+//     way in y: line blocks L_j (tridiagonal, symmetric) and couplings V_j
+//     (tridiagonal) per point, 9-point coarse 2D operators;
+//   * x-line solves use per-line LU factors of L_j.  One wave solves one line
+//     of up to 512 points: each lane holds E consecutive points, composes the
+//     affine maps of the forward (and then backward) Thomas recurrence over
+//     them, and the 64 lanes combine their maps by a shuffle scan.
+// Storage, all FP64, x fastest within a plane, planes (or lines) outermost.
+// The hierarchy lives in the caller's workspace; the host schedules one
+// launch per stage (no fused schedule), looping over right-hand sides.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "smg_internal.h"
+
+namespace smg {
+
+struct VarLevel3 {
+    int nz;                      // planes
+    size_t cc, ce, cn;           // C_k: centre, (i,j)-(i+1,j), (i,j)-(i,j+1)
+    size_t uc, ue, uw, un, us;   // U_k: (i,j) in plane k to (i,j), (i+1,j), (i-1,j), (i,j+1), (i,j-1) in k+1
+    size_t wdn, wup;             // weights of even planes (to coarse K-1 below and K above)
+    size_t x, b;                 // level vectors (levels >= 1)
+    std::vector<size_t> lc, le, vc, ve, vw, ydn, yup, invm, g;   // per 2D level, all planes
+};
+
+struct VarHier {
+    int nx, ny, nz, pre, post, ipre, ipost, order, interp;
+    size_t N;
+    char *ws;
+    std::vector<int> ny2;        // lines per 2D level
+    std::vector<VarLevel3> lev;
+    std::vector<size_t> bx2, bb2;   // 2D batch buffers per 2D level
+    size_t total;
+    template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
+};
+
+namespace {
+
+constexpr int kB = 256;
+
+inline unsigned nblk(long long n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+// ---------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------
+
+// level 0 from the caller's operator: C = diag, -ax, -ay; U = -az at the centre
+__global__ void k_var_fine(const double *diag, const double *ax, const double *ay, const double *az, int nx, int ny,
+                           int nz, double *cc, double *ce, double *cn, double *uc, double *ue, double *uw, double *un,
+                           double *us)
+{
+    const long long n = static_cast<long long>(nx) * ny * nz;
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int i = static_cast<int>(p % nx), j = static_cast<int>((p / nx) % ny), k = static_cast<int>(p / nx / ny);
+    cc[p] = diag[p];
+    ce[p] = i + 1 < nx ? -ax[p] : 0.0;
+    cn[p] = j + 1 < ny ? -ay[p] : 0.0;
+    uc[p] = k + 1 < nz ? -az[p] : 0.0;
+    ue[p] = uw[p] = un[p] = us[p] = 0.0;
+}
+
+// Interpolation weights of the even fine blocks f along the outer index of a
+// level with nb blocks of nx x ny points (ns such operators stacked one after
+// another): wdn (from the block below) and wup (from the block above).  The
+// collapsed couplings of point p are a = -(column sum of the coupling from
+// block f-1 into p) and b = -(row sum of the coupling from p into block
+// f+1); with `op` and both positive the weights are a/(a+b) and b/(a+b), else
+// 1/2.  A block with one neighbour takes 1/2.  Planes couple 5-point
+// (E/W/N/S); lines are the case ny = 1 (3-point, un and us null).
+__global__ void k_var_weights(const double *uc, const double *ue, const double *uw, const double *un,
+                              const double *us, int nx, int ny, int nb, int ns, int op, double *wdn, double *wup)
+{
+    const long long m = static_cast<long long>(nx) * ny;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= m * nb * ns) return;
+    const int f = static_cast<int>((e / m) % nb);
+    if (f % 2) return;
+    const long long p = e % m;
+    const int i = static_cast<int>(p % nx), j = static_cast<int>(p / nx);
+    const bool has_dn = f >= 1, has_up = f + 1 < nb;
+    double wd = has_dn ? 0.5 : 0.0, wu = has_up ? 0.5 : 0.0;
+    if (op && has_dn && has_up) {
+        const long long d = e - m, u = e;    // coupling blocks f-1 -> f and f -> f+1, at p
+        double a = uc[d];
+        if (i > 0) a += ue[d - 1];
+        if (i + 1 < nx) a += uw[d + 1];
+        if (j > 0) a += un[d - nx];
+        if (j + 1 < ny) a += us[d + nx];
+        a = -a;
+        double b = uc[u] + ue[u] + uw[u];
+        if (ny > 1) b += un[u] + us[u];
+        b = -b;
+        if (a > 0.0 && b > 0.0) {
+            wd = a / (a + b);
+            wu = b / (a + b);
+        }
+    }
+    wdn[e] = wd;
+    wup[e] = wu;
+}
+
+// Views of a block operator with nb blocks of nx x ny points: C (symmetric
+// in-block: cc, ce, cn) and U (block f to f+1: uc, ue, uw, un, us).  Lines
+// are the case ny = 1 (cn, un, us unused).
+struct BlockOp {
+    const double *cc, *ce, *cn, *uc, *ue, *uw, *un, *us;
+    int nx, ny;
+    // C_f[p][q], q = p + (di, dj) with |di| + |dj| <= 1, inside the block
+    __device__ double C(long long base, int i, int j, int di, int dj) const
+    {
+        const long long p = base + static_cast<long long>(j) * nx + i;
+        if (di == 0 && dj == 0) return cc[p];
+        if (di == 1) return ce[p];
+        if (di == -1) return ce[p - 1];
+        if (dj == 1) return cn[p];
+        return cn[p - nx];
+    }
+    // U_f[p][q]: p in block f, q = p' + (di, dj) in block f+1
+    __device__ double U(long long base, int i, int j, int di, int dj) const
+    {
+        const long long p = base + static_cast<long long>(j) * nx + i;
+        if (di == 0 && dj == 0) return uc[p];
+        if (di == 1) return ue[p];
+        if (di == -1) return uw[p];
+        if (dj == 1) return un[p];
+        return us[p];
+    }
+    // U_f[q][p]: q = p + (di, dj) in block f, p' in block f+1 (the transposed coupling)
+    __device__ double Ut(long long base, int i, int j, int di, int dj) const
+    {
+        return U(base, i + di, j + dj, -di, -dj);
+    }
+};
+
+// Galerkin P^T A P of a block-tridiagonal operator under the per-point
+// semicoarsening prolongation: coarse block K sits on fine block f1 = 2K+1,
+// fine f0 = 2K takes wup[f0] of coarse K, fine f2 = 2K+2 takes wdn[f2] of K
+// (and wup[f2] of K+1).  With W the diagonal weight matrices:
+//   C^c_K = W0 C_f0 W0 + C_f1 + W2 C_f2 W2 + W0 U_f0 + U_f0^T W0 + U_f1 W2 + W2 U_f1^T
+//   U^c_K = U_f1 W2' + W2 C_f2 W2' + W2 U_f2            (W0 = wup[f0], W2 = wdn[f2], W2' = wup[f2])
+// terms of missing fine blocks dropped.  One thread per coarse point.
+__global__ void k_var_galerkin(BlockOp F, const double *wdn, const double *wup, int nb, int ns, double *cc,
+                               double *ce, double *cn, double *uc, double *ue, double *uw, double *un, double *us)
+{
+    const int nx = F.nx, ny = F.ny;
+    const long long m = static_cast<long long>(nx) * ny;
+    const int nc = nb / 2;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= m * nc * ns) return;
+    const long long sbase = (e / (m * nc)) * m * nb;   // the stacked operator's fine blocks
+    const int K = static_cast<int>((e / m) % nc);
+    const long long p = e % m;
+    const int i = static_cast<int>(p % nx), j = static_cast<int>(p / nx);
+    const int f0 = 2 * K, f1 = 2 * K + 1, f2 = 2 * K + 2, f3 = 2 * K + 3;
+    const bool h2 = f2 < nb, h3 = f3 < nb;
+    const long long b0 = sbase + f0 * m, b1 = sbase + f1 * m, b2 = sbase + f2 * m;
+    auto in = [&](int di, int dj) { return i + di >= 0 && i + di < nx && j + dj >= 0 && j + dj < ny; };
+    auto w = [&](const double *wt, long long base, int di, int dj) {
+        return wt[base + static_cast<long long>(j + dj) * nx + i + di];
+    };
+    // C^c at q = p, p+x, p+y
+    const int dq[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+    double outc[3];
+    for (int t = 0; t < 3; ++t) {
+        const int di = dq[t][0], dj = dq[t][1];
+        if (!in(di, dj)) {
+            outc[t] = 0.0;
+            continue;
+        }
+        const double w0p = w(wup, b0, 0, 0), w0q = w(wup, b0, di, dj);
+        double v = w0p * F.C(b0, i, j, di, dj) * w0q + F.C(b1, i, j, di, dj);
+        v += w0p * F.U(b0, i, j, di, dj) + F.Ut(b0, i, j, di, dj) * w0q;
+        if (h2) {
+            const double w2p = w(wdn, b2, 0, 0), w2q = w(wdn, b2, di, dj);
+            v += w2p * F.C(b2, i, j, di, dj) * w2q;
+            v += F.U(b1, i, j, di, dj) * w2q + w2p * F.Ut(b1, i, j, di, dj);
+        }
+        outc[t] = v;
+    }
+    cc[e] = outc[0];
+    ce[e] = outc[1];
+    if (cn) cn[e] = outc[2];
+    // U^c at q = p', p'+x, p'-x, p'+y, p'-y
+    const int du[5][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+    double outu[5];
+    for (int t = 0; t < 5; ++t) {
+        const int di = du[t][0], dj = du[t][1];
+        outu[t] = 0.0;
+        if (!h3 || !in(di, dj)) continue;
+        const double w2p = w(wdn, b2, 0, 0), wq = w(wup, b2, di, dj);
+        outu[t] = F.U(b1, i, j, di, dj) * wq + w2p * F.C(b2, i, j, di, dj) * wq + w2p * F.U(b2, i, j, di, dj);
+    }
+    uc[e] = outu[0];
+    ue[e] = outu[1];
+    uw[e] = outu[2];
+    if (un) {
+        un[e] = outu[3];
+        us[e] = outu[4];
+    }
+}
+
+// 2D level 0 of every plane of a 3D level: L_j = the x-part of C_k on line j,
+// V_j = C_k's coupling of line j to line j+1 (diagonal)
+__global__ void k_var_plane0(const double *cc, const double *ce, const double *cn, long long n, double *lc, double *le,
+                             double *vc, double *ve, double *vw)
+{
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    lc[p] = cc[p];
+    le[p] = ce[p];
+    vc[p] = cn[p];
+    ve[p] = vw[p] = 0.0;
+}
+
+// LU factors of every line block: invm[i] = 1/m_i, g[i] = le_i / m_i with
+// m_0 = lc_0, m_{i+1} = lc_{i+1} - le_i g_i (the blocks are SPD: no pivoting)
+__global__ void k_var_factor(const double *lc, const double *le, long long nlines, int nx, double *invm, double *g)
+{
+    const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nlines) return;
+    const long long b = t * nx;
+    double m = lc[b];
+    for (int i = 0; i < nx; ++i) {
+        const double im = 1.0 / m;
+        invm[b + i] = im;
+        const double gi = i + 1 < nx ? le[b + i] * im : 0.0;
+        g[b + i] = gi;
+        if (i + 1 < nx) m = lc[b + i + 1] - le[b + i] * gi;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle kernels
+// ---------------------------------------------------------------------------
+
+struct Lines {                    // a 2D level of all planes of a 3D level
+    const double *lc, *le, *vc, *ve, *vw, *invm, *g;
+    int nx, ny;
+};
+
+// (Q x)_j[i] on line j of a plane's 2D level: L_j x_j + V_{j-1}^T x_{j-1} + V_j x_{j+1}
+__device__ inline double q_line(const Lines &Q, long long cb, const double *x, long long xb, int j, int i)
+{
+    const int nx = Q.nx;
+    const long long c = cb + static_cast<long long>(j) * nx + i, xc = xb + static_cast<long long>(j) * nx + i;
+    double v = Q.lc[c] * x[xc];
+    if (i > 0) v += Q.le[c - 1] * x[xc - 1];
+    if (i + 1 < nx) v += Q.le[c] * x[xc + 1];
+    if (j > 0) {
+        const long long d = c - nx, xd = xc - nx;
+        v += Q.vc[d] * x[xd];
+        if (i > 0) v += Q.ve[d - 1] * x[xd - 1];
+        if (i + 1 < nx) v += Q.vw[d + 1] * x[xd + 1];
+    }
+    if (j + 1 < Q.ny) {
+        const long long xu = xc + nx;
+        v += Q.vc[c] * x[xu];
+        if (i + 1 < nx) v += Q.ve[c] * x[xu + 1];
+        if (i > 0) v += Q.vw[c] * x[xu - 1];
+    }
+    return v;
+}
+
+// Zebra half-sweep over the lines of one colour, for np planes at once:
+// x_j += L_j^{-1} (b - Q x)_j.  One wave per line; lane l owns the E points
+// l*E .. l*E+E-1.  Plane pb of the batch is plane k0 + ks*pb of the level's
+// coefficient arrays.
+template <int E>
+__global__ __launch_bounds__(kB) void k_var_relax(Lines Q, const double *b, double *x, int np, int colour, int k0,
+                                                  int ks)
+{
+    const int lane = threadIdx.x & 63;
+    const long long wv = static_cast<long long>(blockIdx.x) * (kB / 64) + (threadIdx.x >> 6);
+    const int nlc = (Q.ny - colour + 1) / 2;
+    if (wv >= static_cast<long long>(nlc) * np) return;   // whole waves exit together
+    const int pb = static_cast<int>(wv / nlc);
+    const int j = colour + 2 * static_cast<int>(wv % nlc);
+    const int nx = Q.nx;
+    const long long cb = static_cast<long long>(k0 + ks * pb) * Q.ny * nx;
+    const long long xb = static_cast<long long>(pb) * Q.ny * nx;
+    const long long cl = cb + static_cast<long long>(j) * nx, xl = xb + static_cast<long long>(j) * nx;
+    double y[E], im[E], gg[E];
+    // residual and the forward Thomas recurrence y_i = (r_i - le_{i-1} y_{i-1}) / m_i
+    // as affine maps y -> A y + B composed over the lane's points
+    double A = 1.0, B = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        if (i < nx) {
+            const double r = b[xl + i] - q_line(Q, cb, x, xb, j, i);
+            im[e] = Q.invm[cl + i];
+            gg[e] = Q.g[cl + i];
+            const double a = i > 0 ? -Q.le[cl + i - 1] * im[e] : 0.0;
+            y[e] = r * im[e];
+            B = a * B + y[e];
+            A = a * A;
+        } else {
+            im[e] = gg[e] = y[e] = 0.0;
+            A = 0.0;
+            B = 0.0;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double Ap = __shfl_up(A, off, 64), Bp = __shfl_up(B, off, 64);
+        if (lane >= off) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    double yin = __shfl_up(B, 1, 64);
+    if (lane == 0) yin = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        if (i < nx) {
+            const double a = i > 0 ? -Q.le[cl + i - 1] * im[e] : 0.0;
+            y[e] = a * yin + y[e];
+            yin = y[e];
+        }
+    }
+    // backward u_i = y_i - g_i u_{i+1}, composed from the top
+    A = 1.0;
+    B = 0.0;
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e) {
+        const int i = lane * E + e;
+        if (i < nx) {
+            B = -gg[e] * B + y[e];
+            A = -gg[e] * A;
+        } else {
+            A = 0.0;
+            B = 0.0;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double Ap = __shfl_down(A, off, 64), Bp = __shfl_down(B, off, 64);
+        if (lane + off < 64) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    double uin = __shfl_down(B, 1, 64);
+    if (lane == 63) uin = 0.0;
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e) {
+        const int i = lane * E + e;
+        if (i < nx) {
+            const double u = y[e] - gg[e] * uin;
+            uin = u;
+            y[e] = u;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        if (i < nx) x[xl + i] += y[e];
+    }
+}
+
+// b_c = P^T (b - Q x) for np planes: coarse line J takes fine line 2J+1,
+// ydn[2J+2] of line 2J+2 and yup[2J] of line 2J
+__global__ void k_var_restrict2(Lines Q, const double *ydn, const double *yup, const double *b, const double *x,
+                                double *bc, int np, int k0, int ks)
+{
+    const int nx = Q.nx, ny = Q.ny, nyc = ny / 2;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= static_cast<long long>(np) * nyc * nx) return;
+    const int i = static_cast<int>(e % nx);
+    const int J = static_cast<int>((e / nx) % nyc);
+    const int pb = static_cast<int>(e / nx / nyc);
+    const long long cb = static_cast<long long>(k0 + ks * pb) * ny * nx, xb = static_cast<long long>(pb) * ny * nx;
+    auto r = [&](int j) { return b[xb + static_cast<long long>(j) * nx + i] - q_line(Q, cb, x, xb, j, i); };
+    double v = r(2 * J + 1) + yup[cb + static_cast<long long>(2 * J) * nx + i] * r(2 * J);
+    if (2 * J + 2 < ny) v += ydn[cb + static_cast<long long>(2 * J + 2) * nx + i] * r(2 * J + 2);
+    bc[e] = v;
+}
+
+// x += P x_c for np planes
+__global__ void k_var_prolong2(const double *ydn, const double *yup, int nx, int ny, const double *xc, double *x,
+                               int np, int k0, int ks)
+{
+    const int nyc = ny / 2;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= static_cast<long long>(np) * ny * nx) return;
+    const int i = static_cast<int>(e % nx);
+    const int j = static_cast<int>((e / nx) % ny);
+    const int pb = static_cast<int>(e / nx / ny);
+    const long long cb = static_cast<long long>(k0 + ks * pb) * ny * nx;
+    const long long xcb = static_cast<long long>(pb) * nyc * nx;
+    double v;
+    if (j % 2) {
+        v = xc[xcb + static_cast<long long>(j / 2) * nx + i];
+    } else {
+        const long long c = cb + static_cast<long long>(j) * nx + i;
+        v = 0.0;
+        if (j / 2 - 1 >= 0) v += ydn[c] * xc[xcb + static_cast<long long>(j / 2 - 1) * nx + i];
+        if (j / 2 < nyc) v += yup[c] * xc[xcb + static_cast<long long>(j / 2) * nx + i];
+    }
+    x[e] += v;
+}
+
+struct Planes {                   // a 3D level
+    BlockOp op;
+    int nz;
+};
+
+// (A_l x)_k at point p of plane k: C_k x_k + U_{k-1}^T x_{k-1} + U_k x_{k+1}
+__device__ inline double a_plane(const Planes &A, const double *x, int k, int i, int j)
+{
+    const BlockOp &o = A.op;
+    const int nx = o.nx, ny = o.ny;
+    const long long m = static_cast<long long>(nx) * ny;
+    const long long p = k * m + static_cast<long long>(j) * nx + i;
+    double v = o.cc[p] * x[p];
+    if (i > 0) v += o.ce[p - 1] * x[p - 1];
+    if (i + 1 < nx) v += o.ce[p] * x[p + 1];
+    if (j > 0) v += o.cn[p - nx] * x[p - nx];
+    if (j + 1 < ny) v += o.cn[p] * x[p + nx];
+    if (k > 0) {   // U_{k-1}^T: entries of the rows of plane k-1 that reach p
+        const long long d = p - m;
+        v += o.uc[d] * x[d];
+        if (i > 0) v += o.ue[d - 1] * x[d - 1];
+        if (i + 1 < nx) v += o.uw[d + 1] * x[d + 1];
+        if (j > 0) v += o.un[d - nx] * x[d - nx];
+        if (j + 1 < ny) v += o.us[d + nx] * x[d + nx];
+    }
+    if (k + 1 < A.nz) {
+        const long long u = p + m;
+        v += o.uc[p] * x[u];
+        if (i + 1 < nx) v += o.ue[p] * x[u + 1];
+        if (i > 0) v += o.uw[p] * x[u - 1];
+        if (j + 1 < ny) v += o.un[p] * x[u + nx];
+        if (j > 0) v += o.us[p] * x[u - nx];
+    }
+    return v;
+}
+
+// residual of the planes of one colour into the 2D batch buffer
+__global__ void k_var_resid3(Planes A, const double *b, const double *x, int colour, double *r)
+{
+    const int nx = A.op.nx, ny = A.op.ny;
+    const long long m = static_cast<long long>(nx) * ny;
+    const int npl = (A.nz - colour + 1) / 2;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= npl * m) return;
+    const int pb = static_cast<int>(e / m);
+    const int k = colour + 2 * pb;
+    const int i = static_cast<int>(e % nx), j = static_cast<int>((e % m) / nx);
+    r[e] = b[k * m + e % m] - a_plane(A, x, k, i, j);
+}
+
+// x_k += y_pb for the planes of one colour
+__global__ void k_var_correct3(double *x, const double *y, long long m, int nz, int colour)
+{
+    const int npl = (nz - colour + 1) / 2;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= npl * m) return;
+    const int k = colour + 2 * static_cast<int>(e / m);
+    x[k * m + e % m] += y[e];
+}
+
+__global__ void k_var_restrict3(Planes A, const double *wdn, const double *wup, const double *b, const double *x,
+                                double *bc)
+{
+    const int nx = A.op.nx, ny = A.op.ny, nzc = A.nz / 2;
+    const long long m = static_cast<long long>(nx) * ny;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nzc * m) return;
+    const int K = static_cast<int>(e / m);
+    const long long p = e % m;
+    const int i = static_cast<int>(p % nx), j = static_cast<int>(p / nx);
+    auto r = [&](int k) { return b[k * m + p] - a_plane(A, x, k, i, j); };
+    double v = r(2 * K + 1) + wup[2 * K * m + p] * r(2 * K);
+    if (2 * K + 2 < A.nz) v += wdn[(2 * K + 2) * m + p] * r(2 * K + 2);
+    bc[e] = v;
+}
+
+__global__ void k_var_prolong3(const double *wdn, const double *wup, long long m, int nz, const double *xc, double *x)
+{
+    const int nzc = nz / 2;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nz * m) return;
+    const int k = static_cast<int>(e / m);
+    const long long p = e % m;
+    double v;
+    if (k % 2) {
+        v = xc[(k / 2) * m + p];
+    } else {
+        v = 0.0;
+        if (k / 2 - 1 >= 0) v += wdn[e] * xc[(k / 2 - 1) * m + p];
+        if (k / 2 < nzc) v += wup[e] * xc[(k / 2) * m + p];
+    }
+    x[e] += v;
+}
+
+__global__ void k_var_copy(const double *src, double *dst, long long n)
+{
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = src[e];
+}
+
+// ---------------------------------------------------------------------------
+// Krylov passes with the fine operator (the same partial-sum layout and
+// fixed reduction grid as the constant-coefficient passes)
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ inline double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+// (A v)_c of the fine operator with v given pointwise by vf(c)
+template <typename F>
+__device__ inline double a_fine(const Planes &A, F vf, long long c)
+{
+    const BlockOp &o = A.op;
+    const int nx = o.nx, ny = o.ny;
+    const long long m = static_cast<long long>(nx) * ny;
+    const int i = static_cast<int>(c % nx), j = static_cast<int>((c / nx) % ny), k = static_cast<int>(c / m);
+    double v = o.cc[c] * vf(c);
+    if (i > 0) v += o.ce[c - 1] * vf(c - 1);
+    if (i + 1 < nx) v += o.ce[c] * vf(c + 1);
+    if (j > 0) v += o.cn[c - nx] * vf(c - nx);
+    if (j + 1 < ny) v += o.cn[c] * vf(c + nx);
+    if (k > 0) v += o.uc[c - m] * vf(c - m);
+    if (k + 1 < A.nz) v += o.uc[c] * vf(c + m);
+    return v;
+}
+
+__global__ __launch_bounds__(kB) void k_var_matvec(Planes A, const double *x, double *y, long long n, long long ld)
+{
+    const int r = blockIdx.y;
+    const double *xr = x + r * ld;
+    double *yr = y + r * ld;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x)
+        yr[c] = a_fine(A, [&](long long q) { return xr[q]; }, c);
+}
+
+__global__ __launch_bounds__(kB) void k_var_init_resid(Planes A, const double *b, const double *x, double *r,
+                                                       int x_zero, long long n, double *partials)
+{
+    __shared__ double lds[kB / 64];
+    double rr = 0.0, bb = 0.0;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const double bv = b[c];
+        const double rv = x_zero ? bv : bv - a_fine(A, [&](long long q) { return x[q]; }, c);
+        r[c] = rv;
+        rr += rv * rv;
+        bb += bv * bv;
+    }
+    rr = block_sum(rr, lds);
+    bb = block_sum(bb, lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = rr;
+        partials[kRedBlocks + blockIdx.x] = bb;
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_var_update_p_q(Planes A, const double *s, const double *p_old, double *p_new,
+                                                       double *q, const KScalars *sc, long long n, double *partials)
+{
+    __shared__ double lds[kB / 64];
+    const double beta = sc->beta;
+    auto pv = [&](long long c) { return beta == 0.0 ? s[c] : s[c] + beta * p_old[c]; };
+    double pq = 0.0;
+    for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+         c += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const double p0 = pv(c);
+        const double qv = a_fine(A, pv, c);
+        p_new[c] = p0;
+        q[c] = qv;
+        pq += p0 * qv;
+    }
+    pq = block_sum(pq, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = pq;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+int levels_of(int n)
+{
+    int L = 1;
+    while (n > 1) {
+        n /= 2;
+        ++L;
+    }
+    return L;
+}
+
+// Offsets of the hierarchy inside the workspace (from byte 0)
+void layout(VarHier &H)
+{
+    size_t off = 0;
+    auto take = [&](size_t count) {
+        const size_t r = off;
+        off = al(off + count * 8);
+        return r;
+    };
+    const size_t m = static_cast<size_t>(H.nx) * H.ny;
+    H.ny2.clear();
+    for (int v = H.ny;; v /= 2) {
+        H.ny2.push_back(v);
+        if (v == 1) break;
+    }
+    H.lev.assign(levels_of(H.nz), VarLevel3{});
+    int nzl = H.nz;
+    for (size_t l = 0; l < H.lev.size(); ++l, nzl /= 2) {
+        VarLevel3 &L = H.lev[l];
+        L.nz = nzl;
+        const size_t n = m * nzl;
+        L.cc = take(n);
+        L.ce = take(n);
+        L.cn = take(n);
+        L.uc = take(n);
+        L.ue = take(n);
+        L.uw = take(n);
+        L.un = take(n);
+        L.us = take(n);
+        L.wdn = take(n);
+        L.wup = take(n);
+        L.x = l > 0 ? take(n) : 0;
+        L.b = l > 0 ? take(n) : 0;
+        for (int v : H.ny2) {
+            const size_t n2 = static_cast<size_t>(nzl) * v * H.nx;
+            L.lc.push_back(take(n2));
+            L.le.push_back(take(n2));
+            L.vc.push_back(take(n2));
+            L.ve.push_back(take(n2));
+            L.vw.push_back(take(n2));
+            L.ydn.push_back(take(n2));
+            L.yup.push_back(take(n2));
+            L.invm.push_back(take(n2));
+            L.g.push_back(take(n2));
+        }
+    }
+    // batch buffers: the planes of one colour of the finest level
+    const size_t npmax = static_cast<size_t>((H.nz + 1) / 2);
+    H.bx2.clear();
+    H.bb2.clear();
+    for (int v : H.ny2) {
+        H.bx2.push_back(take(npmax * v * H.nx));
+        H.bb2.push_back(take(npmax * v * H.nx));
+    }
+    H.total = off;
+}
+
+BlockOp block_op(const VarHier &H, const VarLevel3 &L)
+{
+    return BlockOp{H.at<double>(L.cc), H.at<double>(L.ce), H.at<double>(L.cn), H.at<double>(L.uc),
+                   H.at<double>(L.ue), H.at<double>(L.uw), H.at<double>(L.un), H.at<double>(L.us),
+                   H.nx,                H.ny};
+}
+
+Planes planes_of(const VarHier &H, int l) { return Planes{block_op(H, H.lev[l]), H.lev[l].nz}; }
+
+Lines lines_of(const VarHier &H, int l, int l2)
+{
+    const VarLevel3 &L = H.lev[l];
+    return Lines{H.at<double>(L.lc[l2]), H.at<double>(L.le[l2]),   H.at<double>(L.vc[l2]), H.at<double>(L.ve[l2]),
+                 H.at<double>(L.vw[l2]), H.at<double>(L.invm[l2]), H.at<double>(L.g[l2]),  H.nx,
+                 H.ny2[l2]};
+}
+
+void build(VarHier &H, const double *diag, const double *ax, const double *ay, const double *az, hipStream_t st)
+{
+    const long long m = static_cast<long long>(H.nx) * H.ny;
+    {
+        VarLevel3 &L = H.lev[0];
+        hipLaunchKernelGGL(k_var_fine, dim3(nblk(m * H.nz, kB)), dim3(kB), 0, st, diag, ax, ay, az, H.nx, H.ny, H.nz,
+                           H.at<double>(L.cc), H.at<double>(L.ce), H.at<double>(L.cn), H.at<double>(L.uc),
+                           H.at<double>(L.ue), H.at<double>(L.uw), H.at<double>(L.un), H.at<double>(L.us));
+    }
+    for (size_t l = 0; l + 1 < H.lev.size(); ++l) {
+        VarLevel3 &F = H.lev[l], &Cl = H.lev[l + 1];
+        const BlockOp o = block_op(H, F);
+        hipLaunchKernelGGL(k_var_weights, dim3(nblk(m * F.nz, kB)), dim3(kB), 0, st, o.uc, o.ue, o.uw, o.un, o.us,
+                           H.nx, H.ny, F.nz, 1, H.interp, H.at<double>(F.wdn), H.at<double>(F.wup));
+        hipLaunchKernelGGL(k_var_galerkin, dim3(nblk(m * Cl.nz, kB)), dim3(kB), 0, st, o, H.at<double>(F.wdn),
+                           H.at<double>(F.wup), F.nz, 1, H.at<double>(Cl.cc), H.at<double>(Cl.ce), H.at<double>(Cl.cn),
+                           H.at<double>(Cl.uc), H.at<double>(Cl.ue), H.at<double>(Cl.uw), H.at<double>(Cl.un),
+                           H.at<double>(Cl.us));
+    }
+    // 2D hierarchies of every plane of every 3D level.  A plane's 2D level is
+    // a block-tridiagonal operator over lines (blocks of nx points: the line
+    // blocks L_j in the centre/east slots, the couplings V_j in the
+    // centre/east/west slots); the planes of a 3D level are stacked.
+    for (size_t l = 0; l < H.lev.size(); ++l) {
+        VarLevel3 &L = H.lev[l];
+        const long long n = m * L.nz;
+        hipLaunchKernelGGL(k_var_plane0, dim3(nblk(n, kB)), dim3(kB), 0, st, H.at<double>(L.cc), H.at<double>(L.ce),
+                           H.at<double>(L.cn), n, H.at<double>(L.lc[0]), H.at<double>(L.le[0]), H.at<double>(L.vc[0]),
+                           H.at<double>(L.ve[0]), H.at<double>(L.vw[0]));
+        for (size_t l2 = 0; l2 < H.ny2.size(); ++l2) {
+            const int nyl = H.ny2[l2];
+            const long long nlines = static_cast<long long>(L.nz) * nyl;
+            hipLaunchKernelGGL(k_var_factor, dim3(nblk(nlines, 64)), dim3(64), 0, st, H.at<double>(L.lc[l2]),
+                               H.at<double>(L.le[l2]), nlines, H.nx, H.at<double>(L.invm[l2]), H.at<double>(L.g[l2]));
+            if (l2 + 1 == H.ny2.size()) break;
+            const int nyc = H.ny2[l2 + 1];
+            const BlockOp o{H.at<double>(L.lc[l2]), H.at<double>(L.le[l2]), nullptr, H.at<double>(L.vc[l2]),
+                            H.at<double>(L.ve[l2]), H.at<double>(L.vw[l2]), nullptr,   nullptr, H.nx, 1};
+            hipLaunchKernelGGL(k_var_weights, dim3(nblk(nlines * H.nx, kB)), dim3(kB), 0, st, o.uc, o.ue, o.uw,
+                               nullptr, nullptr, H.nx, 1, nyl, L.nz, H.interp, H.at<double>(L.ydn[l2]),
+                               H.at<double>(L.yup[l2]));
+            hipLaunchKernelGGL(k_var_galerkin, dim3(nblk(static_cast<long long>(L.nz) * nyc * H.nx, kB)), dim3(kB), 0,
+                               st, o, H.at<double>(L.ydn[l2]), H.at<double>(L.yup[l2]), nyl, L.nz,
+                               H.at<double>(L.lc[l2 + 1]), H.at<double>(L.le[l2 + 1]), nullptr,
+                               H.at<double>(L.vc[l2 + 1]), H.at<double>(L.ve[l2 + 1]), H.at<double>(L.vw[l2 + 1]),
+                               nullptr, nullptr);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle schedule (host)
+// ---------------------------------------------------------------------------
+
+void relax(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, hipStream_t st)
+{
+    const Lines Q = lines_of(H, l, l2);
+    const long long waves = static_cast<long long>((Q.ny - colour + 1) / 2) * np;
+    if (waves <= 0) return;
+    const dim3 grid(nblk(waves, kB / 64)), block(kB);
+    const double *b = H.at<double>(H.bb2[l2]);
+    double *x = H.at<double>(H.bx2[l2]);
+    switch ((H.nx + 63) / 64) {
+    case 1: hipLaunchKernelGGL(k_var_relax<1>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    case 2: hipLaunchKernelGGL(k_var_relax<2>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    case 3: hipLaunchKernelGGL(k_var_relax<3>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    case 4: hipLaunchKernelGGL(k_var_relax<4>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    case 5: hipLaunchKernelGGL(k_var_relax<5>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    case 6: hipLaunchKernelGGL(k_var_relax<6>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    case 7: hipLaunchKernelGGL(k_var_relax<7>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    default: hipLaunchKernelGGL(k_var_relax<8>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    }
+}
+
+// One 2D V-cycle, for np planes at once (plane pb of the batch is plane
+// k0 + ks*pb of 3D level l): right-hand sides in bb2[l2], result in bx2[l2].
+void vcycle2(const VarHier &H, int l, int l2, int np, int k0, int ks, hipStream_t st)
+{
+    const int ny = H.ny2[l2];
+    const long long n2 = static_cast<long long>(np) * ny * H.nx;
+    double *x = H.at<double>(H.bx2[l2]);
+    launch_fill(x, 0.0, static_cast<size_t>(n2), st);
+    if (ny == 1) {   // coarsest 2D level: one exact line solve
+        relax(H, l, l2, np, 0, k0, ks, st);
+        return;
+    }
+    const int first = H.order == 0 ? 0 : 1, second = 1 - first;
+    for (int t = 0; t < H.ipre; ++t) {
+        relax(H, l, l2, np, first, k0, ks, st);
+        relax(H, l, l2, np, second, k0, ks, st);
+    }
+    const VarLevel3 &L = H.lev[l];
+    const Lines Q = lines_of(H, l, l2);
+    const long long nc = static_cast<long long>(np) * H.ny2[l2 + 1] * H.nx;
+    hipLaunchKernelGGL(k_var_restrict2, dim3(nblk(nc, kB)), dim3(kB), 0, st, Q, H.at<double>(L.ydn[l2]),
+                       H.at<double>(L.yup[l2]), H.at<double>(H.bb2[l2]), x, H.at<double>(H.bb2[l2 + 1]), np, k0, ks);
+    vcycle2(H, l, l2 + 1, np, k0, ks, st);
+    hipLaunchKernelGGL(k_var_prolong2, dim3(nblk(n2, kB)), dim3(kB), 0, st, H.at<double>(L.ydn[l2]),
+                       H.at<double>(L.yup[l2]), H.nx, ny, H.at<double>(H.bx2[l2 + 1]), x, np, k0, ks);
+    for (int t = 0; t < H.ipost; ++t) {
+        relax(H, l, l2, np, second, k0, ks, st);
+        relax(H, l, l2, np, first, k0, ks, st);
+    }
+}
+
+// zebra half-sweep over the planes of one colour: x_k += V2_k((b - A x)_k)
+void sweep3(const VarHier &H, int l, int colour, const double *b, double *x, hipStream_t st)
+{
+    const VarLevel3 &L = H.lev[l];
+    const int np = (L.nz - colour + 1) / 2;
+    if (np <= 0) return;
+    const long long m = static_cast<long long>(H.nx) * H.ny;
+    hipLaunchKernelGGL(k_var_resid3, dim3(nblk(np * m, kB)), dim3(kB), 0, st, planes_of(H, l), b, x, colour,
+                       H.at<double>(H.bb2[0]));
+    vcycle2(H, l, 0, np, colour, 2, st);
+    hipLaunchKernelGGL(k_var_correct3, dim3(nblk(np * m, kB)), dim3(kB), 0, st, x, H.at<double>(H.bx2[0]), m, L.nz,
+                       colour);
+}
+
+void vcycle3(const VarHier &H, int l, const double *b, double *x, hipStream_t st)
+{
+    const VarLevel3 &L = H.lev[l];
+    const long long m = static_cast<long long>(H.nx) * H.ny;
+    if (L.nz == 1) {   // coarsest 3D level: one plane solve
+        hipLaunchKernelGGL(k_var_copy, dim3(nblk(m, kB)), dim3(kB), 0, st, b, H.at<double>(H.bb2[0]), m);
+        vcycle2(H, l, 0, 1, 0, 1, st);
+        hipLaunchKernelGGL(k_var_copy, dim3(nblk(m, kB)), dim3(kB), 0, st, H.at<double>(H.bx2[0]), x, m);
+        return;
+    }
+    launch_fill(x, 0.0, static_cast<size_t>(m * L.nz), st);
+    const int first = H.order == 0 ? 0 : 1, second = 1 - first;
+    for (int t = 0; t < H.pre; ++t) {
+        sweep3(H, l, first, b, x, st);
+        sweep3(H, l, second, b, x, st);
+    }
+    const VarLevel3 &C = H.lev[l + 1];
+    hipLaunchKernelGGL(k_var_restrict3, dim3(nblk(m * C.nz, kB)), dim3(kB), 0, st, planes_of(H, l),
+                       H.at<double>(L.wdn), H.at<double>(L.wup), b, x, H.at<double>(C.b));
+    vcycle3(H, l + 1, H.at<double>(C.b), H.at<double>(C.x), st);
+    hipLaunchKernelGGL(k_var_prolong3, dim3(nblk(m * L.nz, kB)), dim3(kB), 0, st, H.at<double>(L.wdn),
+                       H.at<double>(L.wup), m, L.nz, H.at<double>(C.x), x);
+    for (int t = 0; t < H.post; ++t) {
+        sweep3(H, l, second, b, x, st);
+        sweep3(H, l, first, b, x, st);
+    }
+}
+
+}  // namespace
+
+size_t var_workspace_bytes(int nx, int ny, int nz)
+{
+    VarHier H{};
+    H.nx = nx;
+    H.ny = ny;
+    H.nz = nz;
+    layout(H);
+    return H.total;
+}
+
+VarHier *var_create(int nx, int ny, int nz, const smg_opts *o, int interp, char *ws, const double *diag,
+                    const double *ax, const double *ay, const double *az, hipStream_t st)
+{
+    VarHier *H = new (std::nothrow) VarHier();
+    if (!H) return nullptr;
+    H->nx = nx;
+    H->ny = ny;
+    H->nz = nz;
+    H->N = static_cast<size_t>(nx) * ny * nz;
+    H->pre = o->pre;
+    H->post = o->post;
+    H->ipre = o->inner_pre < 0 ? o->pre : o->inner_pre;
+    H->ipost = o->inner_post < 0 ? o->post : o->inner_post;
+    H->order = o->order;
+    H->interp = interp;
+    H->ws = ws;
+    layout(*H);
+    build(*H, diag, ax, ay, az, st);
+    return H;
+}
+
+void var_destroy(VarHier *H) { delete H; }
+
+void var_vcycle(VarHier *H, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
+{
+    for (int c = 0; c < nrhs; ++c) vcycle3(*H, 0, r + c * ld, s + c * ld, st);
+}
+
+void var_matvec(VarHier *H, const double *x, double *y, int nrhs, long long ld, hipStream_t st)
+{
+    const long long n = static_cast<long long>(H->N);
+    const unsigned gx = std::min<unsigned>(nblk(n, kB), 2048);
+    hipLaunchKernelGGL(k_var_matvec, dim3(gx, nrhs), dim3(kB), 0, st, planes_of(*H, 0), x, y, n, ld);
+}
+
+void var_init_resid(VarHier *H, const double *b, const double *x, double *r, int x_zero, double *partials,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_var_init_resid, dim3(kRedBlocks), dim3(kB), 0, st, planes_of(*H, 0), b, x, r, x_zero,
+                       static_cast<long long>(H->N), partials);
+}
+
+void var_update_p_q(VarHier *H, const double *s, const double *p_old, double *p_new, double *q, const KScalars *sc,
+                    double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_var_update_p_q, dim3(kRedBlocks), dim3(kB), 0, st, planes_of(*H, 0), s, p_old, p_new, q, sc,
+                       static_cast<long long>(H->N), partials);
+}
+
+int var_levels(const VarHier *H, int *nlev3, int *nlev2)
+{
+    *nlev3 = static_cast<int>(H->lev.size());
+    *nlev2 = static_cast<int>(H->ny2.size());
+    return SMG_OK;
+}
+
+// copies of the stored operators: 3D level l (8 arrays of nz_l*nx*ny: cc, ce,
+// cn, uc, ue, uw, un, us) or the 2D level l2 of every plane of it (5 arrays of
+// nz_l*ny_l2*nx: lc, le, vc, ve, vw), into a device buffer
+int var_export(const VarHier *H, int l, int l2, double *out, hipStream_t st)
+{
+    if (l < 0 || l >= static_cast<int>(H->lev.size()) || l2 < -1 || l2 >= static_cast<int>(H->ny2.size()))
+        return SMG_EINVAL;
+    const VarLevel3 &L = H->lev[l];
+    std::vector<size_t> src;
+    size_t n;
+    if (l2 < 0) {
+        src = {L.cc, L.ce, L.cn, L.uc, L.ue, L.uw, L.un, L.us};
+        n = static_cast<size_t>(L.nz) * H->nx * H->ny;
+    } else {
+        src = {L.lc[l2], L.le[l2], L.vc[l2], L.ve[l2], L.vw[l2]};
+        n = static_cast<size_t>(L.nz) * H->ny2[l2] * H->nx;
+    }
+    for (size_t a = 0; a < src.size(); ++a)
+        if (hipMemcpyAsync(out + a * n, H->at<double>(src[a]), n * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return SMG_EHIP;
+    return SMG_OK;
+}
+
+}  // namespace smg

@@ -108,6 +108,11 @@ def lib():
             L.lobpcg_solve.argtypes = [p, i32, p, p, p, p, C.c_size_t,
                                        C.POINTER(lobpcg_opts), C.POINTER(lobpcg_info), p]
         L.smg_autotune.argtypes = [p, p, p, i32, p, C.POINTER(smg_tune_info)]
+        L.smgv_workspace_bytes.argtypes = [i32, i32, i32, C.POINTER(smg_opts), i32, i32, C.POINTER(C.c_size_t)]
+        L.smgv_setup.argtypes = [i32, i32, i32, p, p, p, p, i32, C.POINTER(smg_opts), i32, p, C.c_size_t, p,
+                                 C.POINTER(p)]
+        L.smgv_levels.argtypes = [p, C.POINTER(i32), C.POINTER(i32)]
+        L.smgv_export.argtypes = [p, i32, i32, p, p]
         L.smg_delta.argtypes = [p, p, d, p, i32, p, C.POINTER(d), p]
         L.smg_delta_min.argtypes = [p, p, d, d, d, p, i32, p, C.POINTER(d), C.POINTER(d), p]
         L.smg_spectrum.argtypes = [p, p, i32, p, C.POINTER(d), C.POINTER(d), p]
@@ -243,6 +248,57 @@ class SMG:
                            C.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream(), C.byref(h)),
                "smg_setup")
         self.h = h
+
+    @classmethod
+    def variable(cls, shape, diag, ax, ay, az, pre=1, post=1, inner_pre=-1, inner_post=-1, order=0,
+                 interp="operator", max_nrhs=1, device="cuda"):
+        """SMG for the variable-coefficient 7-point operator (A x)_p = diag[p] x_p
+        - sum_e (a_e[p] x_{p+e} + a_e[p-e] x_{p-e}) (smgv_setup); diag, ax, ay, az
+        are float64 tensors (or arrays) of nx*ny*nz values, x fastest.
+        interp: "linear" or "operator" (operator-dependent) prolongation weights."""
+        L = lib()
+        G = object.__new__(cls)
+        G.shape = tuple(int(v) for v in shape)
+        G.n = G.shape[0] * G.shape[1] * G.shape[2]
+        G.grid = smg_grid(*G.shape, 1.0, 1.0, 1.0)
+        G.opts = smg_opts(pre, post, inner_pre, inner_post, order, PREC["f64"], 0)
+        G.max_nrhs = int(max_nrhs)
+        G.variable_coefficients = True
+        coef = []
+        for a in (diag, ax, ay, az):
+            t = torch.as_tensor(a, dtype=torch.float64).to(device).contiguous().reshape(-1)
+            if t.numel() != G.n:
+                raise SMGError(f"coefficient arrays need {G.n} values, got {t.numel()}")
+            coef.append(t)
+        ip = {"linear": 0, "operator": 1}[interp]
+        nbytes = C.c_size_t(0)
+        _check(L.smgv_workspace_bytes(*G.shape, C.byref(G.opts), ip, G.max_nrhs, C.byref(nbytes)),
+               "smgv_workspace_bytes")
+        G.ws_bytes = nbytes.value
+        G.ws = torch.empty(G.ws_bytes, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(L.smgv_setup(*G.shape, *[C.c_void_p(t.data_ptr()) for t in coef], ip, C.byref(G.opts), G.max_nrhs,
+                            C.c_void_p(G.ws.data_ptr()), G.ws_bytes, _stream(), C.byref(h)), "smgv_setup")
+        G.h = h
+        return G
+
+    def levels(self):
+        """(3D levels, 2D levels per plane) of a variable-coefficient hierarchy."""
+        a, b = C.c_int32(0), C.c_int32(0)
+        _check(lib().smgv_levels(self.h, C.byref(a), C.byref(b)), "smgv_levels")
+        return a.value, b.value
+
+    def export(self, level: int, level2: int = -1, nz_l: int | None = None, ny_l2: int | None = None):
+        """The stored operator of a variable-coefficient hierarchy (smgv_export) as a
+        float64 CPU tensor: (8, nz_l, ny, nx) for a 3D level, (5, nz_l, ny_l2, nx) for
+        the 2D level `level2` of its planes."""
+        nx, ny, _ = self.shape
+        narr = 8 if level2 < 0 else 5
+        rows = ny if level2 < 0 else ny_l2
+        out = torch.empty(narr * nz_l * rows * nx, dtype=torch.float64, device=self.ws.device)
+        _check(lib().smgv_export(self.h, int(level), int(level2), C.c_void_p(out.data_ptr()), _stream()),
+               "smgv_export")
+        return out.cpu().reshape(narr, nz_l, rows, nx)
 
     def __del__(self):
         h = getattr(self, "h", None)
