@@ -84,6 +84,7 @@ def other_configs(torch, dev, learned=True):
     res = lobpcg_configs(torch, dev)
     res.update(precision_configs(torch, dev))
     res["batch_48_uneven"] = batch_config(torch, dev)
+    res["varcoef_256"] = varcoef_config(torch, dev)
     if learned:
         res["learned_256"] = learned_config(torch, dev)
     return res
@@ -208,6 +209,51 @@ def batch_config(torch, dev):
             "grouped_launches_per_iteration": steps, "box_launches_per_iteration": launches,
             "iters_min": min(i.iters for i in infos), "iters_max": max(i.iters for i in infos),
             "all_converged": all(i.status == 0 for i in infos), "bitwise_equal_to_single_solves": bool(same)}
+
+
+def varcoef_config(torch, dev, n=256, kind="aniso_layers"):
+    """Variable coefficients at n^3 (unit cube): -div(kappa grad u) with z-layers
+    of 2..9 planes whose conductivity alternates between 1 and 1000, and 100:1
+    in-plane anisotropy in every other layer (synth.conductivity), b ~ U[-1,1)
+    seed 7.  FPCG to 1e-8 with SMG (1,0) and (1,1), operator-dependent and
+    linear interpolation; setup and V-cycle times."""
+    import synth
+    from paper_1212_6680_amd.smg import SMG
+    shape = (n, n, n)
+    c = ((n + 1.0) ** 2,) * 3
+    coef = [torch.from_numpy(a).to(dev) for a in synth.diffusion_stencil(shape, *synth.conductivity(shape, kind, 11), c=c)]
+    b = torch.from_numpy(synth.rhs(n, n, n, 7)).to(dev)
+    out = {"grid": n, "field": kind, "contrast": 1e3, "anisotropy": 100.0}
+    for interp in ("operator", "linear"):
+        for pp in ((1, 0), (1, 1)):
+            if interp == "linear" and pp == (1, 1):
+                continue
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G = SMG.variable(shape, *coef, *pp, interp=interp)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            x = torch.empty_like(b)
+            G.fpcg(b, x, max_iter=3, zero_x0=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = G.fpcg(b, x, zero_x0=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s = torch.empty_like(b)
+            G.apply(b, s)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(5):
+                G.apply(b, s)
+            torch.cuda.synchronize()
+            vc = (time.perf_counter() - t1) / 5
+            out[f"fpcg_{pp[0]}{pp[1]}_{interp}"] = {"s": dt, "iters": info.iters, "status": info.status,
+                                                    "true_rel_res": info.true_rel_res, "setup_s": setup,
+                                                    "vcycle_ms": 1e3 * vc, "vcycle_gdof_per_s": n ** 3 / vc / 1e9}
+            del G
+            torch.cuda.empty_cache()
+    return out
 
 
 def learned_config(torch, dev, npairs=2000, steps=2000):
@@ -345,7 +391,7 @@ def main():
                     help="skip the LOBPCG and mixed-precision workloads reported beside the headline")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for counter collection: a 512 MiB device copy, then one V-cycle")
-    ap.add_argument("--only", choices=["batch", "learned", "lobpcg", "precision"],
+    ap.add_argument("--only", choices=["batch", "learned", "lobpcg", "precision", "varcoef"],
                     help="run one of the other workloads alone and print its result (for profiling)")
     ap.add_argument("--learned-pairs", type=int, default=2000)
     ap.add_argument("--learned-steps", type=int, default=2000)
@@ -369,6 +415,8 @@ def main():
             out = learned_config(torch, dev, args.learned_pairs, args.learned_steps)
         elif args.only == "precision":
             out = precision_configs(torch, dev)
+        elif args.only == "varcoef":
+            out = varcoef_config(torch, dev)
         else:
             out = lobpcg_configs(torch, dev)
         print(json.dumps({"only": args.only, **out}))

@@ -289,100 +289,116 @@ __device__ inline double q_line(const Lines &Q, long long cb, const double *x, l
 }
 
 // Zebra half-sweep over the lines of one colour, for np planes at once:
-// x_j += L_j^{-1} (b - Q x)_j.  One wave per line; lane l owns the E points
-// l*E .. l*E+E-1.  Plane pb of the batch is plane k0 + ks*pb of the level's
-// coefficient arrays.
+// x_j += L_j^{-1} (b - Q x)_j.  One wave per line.  Plane pb of the batch is
+// plane k0 + ks*pb of the level's coefficient arrays.
+// Phase 1 (coalesced: lane handles points t*64 + lane): the residual r and
+// the forward Thomas coefficients alpha_i = -le_{i-1}/m_i, beta_i = r_i/m_i and
+// g_i go to LDS.  Phase 2 (lane l owns the E consecutive points l*E ..): the
+// recurrence y_i = alpha_i y_{i-1} + beta_i and then u_i = y_i - g_i u_{i+1} as
+// affine maps composed over the lane's points and combined across lanes by
+// shuffle scans; u overwrites beta.  Phase 3 (coalesced): x += u.  LDS rows
+// are padded to an odd stride per chunk so that the chunk reads spread over
+// the banks.
+constexpr int kRelaxWaves = kB / 64;
+__host__ __device__ constexpr int relax_stride(int E) { return E % 2 ? E : E + 1; }
+
 template <int E>
 __global__ __launch_bounds__(kB) void k_var_relax(Lines Q, const double *b, double *x, int np, int colour, int k0,
                                                   int ks)
 {
-    const int lane = threadIdx.x & 63;
-    const long long wv = static_cast<long long>(blockIdx.x) * (kB / 64) + (threadIdx.x >> 6);
+    constexpr int S = relax_stride(E);
+    constexpr int ROW = 64 * S;                 // LDS doubles per array per wave
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double *Rb = lds + w * 3 * ROW, *Al = Rb + ROW, *Gl = Al + ROW;
+    auto pos = [](int i) { return (i / E) * S + i % E; };
+    const long long wv = static_cast<long long>(blockIdx.x) * kRelaxWaves + w;
     const int nlc = (Q.ny - colour + 1) / 2;
-    if (wv >= static_cast<long long>(nlc) * np) return;   // whole waves exit together
-    const int pb = static_cast<int>(wv / nlc);
-    const int j = colour + 2 * static_cast<int>(wv % nlc);
+    const bool active = wv < static_cast<long long>(nlc) * np;   // whole waves
     const int nx = Q.nx;
-    const long long cb = static_cast<long long>(k0 + ks * pb) * Q.ny * nx;
-    const long long xb = static_cast<long long>(pb) * Q.ny * nx;
-    const long long cl = cb + static_cast<long long>(j) * nx, xl = xb + static_cast<long long>(j) * nx;
-    double y[E], im[E], gg[E];
-    // residual and the forward Thomas recurrence y_i = (r_i - le_{i-1} y_{i-1}) / m_i
-    // as affine maps y -> A y + B composed over the lane's points
-    double A = 1.0, B = 0.0;
+    int pb = 0, j = 0;
+    long long cb = 0, xb = 0, cl = 0, xl = 0;
+    if (active) {
+        pb = static_cast<int>(wv / nlc);
+        j = colour + 2 * static_cast<int>(wv % nlc);
+        cb = static_cast<long long>(k0 + ks * pb) * Q.ny * nx;
+        xb = static_cast<long long>(pb) * Q.ny * nx;
+        cl = cb + static_cast<long long>(j) * nx;
+        xl = xb + static_cast<long long>(j) * nx;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        if (i < nx) {
-            const double r = b[xl + i] - q_line(Q, cb, x, xb, j, i);
-            im[e] = Q.invm[cl + i];
-            gg[e] = Q.g[cl + i];
-            const double a = i > 0 ? -Q.le[cl + i - 1] * im[e] : 0.0;
-            y[e] = r * im[e];
-            B = a * B + y[e];
-            A = a * A;
-        } else {
-            im[e] = gg[e] = y[e] = 0.0;
-            A = 0.0;
-            B = 0.0;
+        for (int t = 0; t < E; ++t) {
+            const int i = t * 64 + lane;
+            double al = 0.0, be = 0.0, gi = 0.0;
+            if (i < nx) {
+                const double im = Q.invm[cl + i];
+                be = (b[xl + i] - q_line(Q, cb, x, xb, j, i)) * im;
+                al = i > 0 ? -Q.le[cl + i - 1] * im : 0.0;
+                gi = Q.g[cl + i];
+            }
+            Rb[pos(i)] = be;
+            Al[pos(i)] = al;
+            Gl[pos(i)] = gi;
         }
     }
+    __syncthreads();
+    if (active) {
+        // forward: y -> A y + B over the lane's points, then across lanes
+        double A = 1.0, B = 0.0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double Ap = __shfl_up(A, off, 64), Bp = __shfl_up(B, off, 64);
-        if (lane >= off) {
-            B = A * Bp + B;
-            A = A * Ap;
+        for (int e = 0; e < E; ++e) {
+            const int p = lane * S + e;
+            B = Al[p] * B + Rb[p];
+            A = Al[p] * A;
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double Ap = __shfl_up(A, off, 64), Bp = __shfl_up(B, off, 64);
+            if (lane >= off) {
+                B = A * Bp + B;
+                A = A * Ap;
+            }
+        }
+        double yin = __shfl_up(B, 1, 64);
+        if (lane == 0) yin = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = lane * S + e;
+            yin = Al[p] * yin + Rb[p];
+            Rb[p] = yin;
+        }
+        // backward: u_i = y_i - g_i u_{i+1}, composed from the top
+        A = 1.0;
+        B = 0.0;
+#pragma unroll
+        for (int e = E - 1; e >= 0; --e) {
+            const int p = lane * S + e;
+            B = -Gl[p] * B + Rb[p];
+            A = -Gl[p] * A;
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double Ap = __shfl_down(A, off, 64), Bp = __shfl_down(B, off, 64);
+            if (lane + off < 64) {
+                B = A * Bp + B;
+                A = A * Ap;
+            }
+        }
+        double uin = __shfl_down(B, 1, 64);
+        if (lane == 63) uin = 0.0;
+#pragma unroll
+        for (int e = E - 1; e >= 0; --e) {
+            const int p = lane * S + e;
+            uin = Rb[p] - Gl[p] * uin;
+            Rb[p] = uin;
         }
     }
-    double yin = __shfl_up(B, 1, 64);
-    if (lane == 0) yin = 0.0;
+    __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        if (i < nx) {
-            const double a = i > 0 ? -Q.le[cl + i - 1] * im[e] : 0.0;
-            y[e] = a * yin + y[e];
-            yin = y[e];
+        for (int t = 0; t < E; ++t) {
+            const int i = t * 64 + lane;
+            if (i < nx) x[xl + i] += Rb[pos(i)];
         }
-    }
-    // backward u_i = y_i - g_i u_{i+1}, composed from the top
-    A = 1.0;
-    B = 0.0;
-#pragma unroll
-    for (int e = E - 1; e >= 0; --e) {
-        const int i = lane * E + e;
-        if (i < nx) {
-            B = -gg[e] * B + y[e];
-            A = -gg[e] * A;
-        } else {
-            A = 0.0;
-            B = 0.0;
-        }
-    }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double Ap = __shfl_down(A, off, 64), Bp = __shfl_down(B, off, 64);
-        if (lane + off < 64) {
-            B = A * Bp + B;
-            A = A * Ap;
-        }
-    }
-    double uin = __shfl_down(B, 1, 64);
-    if (lane == 63) uin = 0.0;
-#pragma unroll
-    for (int e = E - 1; e >= 0; --e) {
-        const int i = lane * E + e;
-        if (i < nx) {
-            const double u = y[e] - gg[e] * uin;
-            uin = u;
-            y[e] = u;
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        if (i < nx) x[xl + i] += y[e];
     }
 }
 
@@ -767,18 +783,20 @@ void relax(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, 
     const Lines Q = lines_of(H, l, l2);
     const long long waves = static_cast<long long>((Q.ny - colour + 1) / 2) * np;
     if (waves <= 0) return;
-    const dim3 grid(nblk(waves, kB / 64)), block(kB);
+    const dim3 grid(nblk(waves, kRelaxWaves)), block(kB);
     const double *b = H.at<double>(H.bb2[l2]);
     double *x = H.at<double>(H.bx2[l2]);
-    switch ((H.nx + 63) / 64) {
-    case 1: hipLaunchKernelGGL(k_var_relax<1>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
-    case 2: hipLaunchKernelGGL(k_var_relax<2>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
-    case 3: hipLaunchKernelGGL(k_var_relax<3>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
-    case 4: hipLaunchKernelGGL(k_var_relax<4>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
-    case 5: hipLaunchKernelGGL(k_var_relax<5>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
-    case 6: hipLaunchKernelGGL(k_var_relax<6>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
-    case 7: hipLaunchKernelGGL(k_var_relax<7>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
-    default: hipLaunchKernelGGL(k_var_relax<8>, grid, block, 0, st, Q, b, x, np, colour, k0, ks); break;
+    const int E = (H.nx + 63) / 64;
+    const size_t lds = static_cast<size_t>(kRelaxWaves) * 3 * 64 * relax_stride(E) * sizeof(double);
+    switch (E) {
+    case 1: hipLaunchKernelGGL(k_var_relax<1>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 2: hipLaunchKernelGGL(k_var_relax<2>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 3: hipLaunchKernelGGL(k_var_relax<3>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 4: hipLaunchKernelGGL(k_var_relax<4>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 5: hipLaunchKernelGGL(k_var_relax<5>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 6: hipLaunchKernelGGL(k_var_relax<6>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 7: hipLaunchKernelGGL(k_var_relax<7>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    default: hipLaunchKernelGGL(k_var_relax<8>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
     }
 }
 
