@@ -302,104 +302,114 @@ __device__ inline double q_line(const Lines &Q, long long cb, const double *x, l
 constexpr int kRelaxWaves = kB / 64;
 __host__ __device__ constexpr int relax_stride(int E) { return E % 2 ? E : E + 1; }
 
+// ordering of one wave's LDS writes and reads across its lanes
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One line of a zebra half-sweep by one wave (the three phases above);
+// lds: this wave's 3 * 64 * relax_stride(E) doubles.
+template <int E>
+__device__ inline void relax_line(const Lines &Q, const double *b, double *x, long long cb, long long xb, int j,
+                                  double *lds)
+{
+    constexpr int S = relax_stride(E);
+    constexpr int ROW = 64 * S;
+    const int lane = threadIdx.x & 63;
+    double *Rb = lds, *Al = lds + ROW, *Gl = lds + 2 * ROW;
+    auto pos = [](int i) { return (i / E) * S + i % E; };
+    const int nx = Q.nx;
+    const long long cl = cb + static_cast<long long>(j) * nx, xl = xb + static_cast<long long>(j) * nx;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int i = t * 64 + lane;
+        double al = 0.0, be = 0.0, gi = 0.0;
+        if (i < nx) {
+            const double im = Q.invm[cl + i];
+            be = (b[xl + i] - q_line(Q, cb, x, xb, j, i)) * im;
+            al = i > 0 ? -Q.le[cl + i - 1] * im : 0.0;
+            gi = Q.g[cl + i];
+        }
+        Rb[pos(i)] = be;
+        Al[pos(i)] = al;
+        Gl[pos(i)] = gi;
+    }
+    wave_sync();
+    // forward: y -> A y + B over the lane's points, then across lanes
+    double A = 1.0, B = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = lane * S + e;
+        B = Al[p] * B + Rb[p];
+        A = Al[p] * A;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double Ap = __shfl_up(A, off, 64), Bp = __shfl_up(B, off, 64);
+        if (lane >= off) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    double yin = __shfl_up(B, 1, 64);
+    if (lane == 0) yin = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = lane * S + e;
+        yin = Al[p] * yin + Rb[p];
+        Rb[p] = yin;
+    }
+    // backward: u_i = y_i - g_i u_{i+1}, composed from the top
+    A = 1.0;
+    B = 0.0;
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e) {
+        const int p = lane * S + e;
+        B = -Gl[p] * B + Rb[p];
+        A = -Gl[p] * A;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double Ap = __shfl_down(A, off, 64), Bp = __shfl_down(B, off, 64);
+        if (lane + off < 64) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    double uin = __shfl_down(B, 1, 64);
+    if (lane == 63) uin = 0.0;
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e) {
+        const int p = lane * S + e;
+        uin = Rb[p] - Gl[p] * uin;
+        Rb[p] = uin;
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int i = t * 64 + lane;
+        if (i < nx) x[xl + i] += Rb[pos(i)];
+    }
+    wave_sync();   // the next line of this wave reuses the LDS rows
+}
+
 template <int E>
 __global__ __launch_bounds__(kB) void k_var_relax(Lines Q, const double *b, double *x, int np, int colour, int k0,
                                                   int ks)
 {
-    constexpr int S = relax_stride(E);
-    constexpr int ROW = 64 * S;                 // LDS doubles per array per wave
     extern __shared__ double lds[];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double *Rb = lds + w * 3 * ROW, *Al = Rb + ROW, *Gl = Al + ROW;
-    auto pos = [](int i) { return (i / E) * S + i % E; };
+    const int w = threadIdx.x >> 6;
     const long long wv = static_cast<long long>(blockIdx.x) * kRelaxWaves + w;
     const int nlc = (Q.ny - colour + 1) / 2;
-    const bool active = wv < static_cast<long long>(nlc) * np;   // whole waves
-    const int nx = Q.nx;
-    int pb = 0, j = 0;
-    long long cb = 0, xb = 0, cl = 0, xl = 0;
-    if (active) {
-        pb = static_cast<int>(wv / nlc);
-        j = colour + 2 * static_cast<int>(wv % nlc);
-        cb = static_cast<long long>(k0 + ks * pb) * Q.ny * nx;
-        xb = static_cast<long long>(pb) * Q.ny * nx;
-        cl = cb + static_cast<long long>(j) * nx;
-        xl = xb + static_cast<long long>(j) * nx;
-#pragma unroll
-        for (int t = 0; t < E; ++t) {
-            const int i = t * 64 + lane;
-            double al = 0.0, be = 0.0, gi = 0.0;
-            if (i < nx) {
-                const double im = Q.invm[cl + i];
-                be = (b[xl + i] - q_line(Q, cb, x, xb, j, i)) * im;
-                al = i > 0 ? -Q.le[cl + i - 1] * im : 0.0;
-                gi = Q.g[cl + i];
-            }
-            Rb[pos(i)] = be;
-            Al[pos(i)] = al;
-            Gl[pos(i)] = gi;
-        }
-    }
-    __syncthreads();
-    if (active) {
-        // forward: y -> A y + B over the lane's points, then across lanes
-        double A = 1.0, B = 0.0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int p = lane * S + e;
-            B = Al[p] * B + Rb[p];
-            A = Al[p] * A;
-        }
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double Ap = __shfl_up(A, off, 64), Bp = __shfl_up(B, off, 64);
-            if (lane >= off) {
-                B = A * Bp + B;
-                A = A * Ap;
-            }
-        }
-        double yin = __shfl_up(B, 1, 64);
-        if (lane == 0) yin = 0.0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int p = lane * S + e;
-            yin = Al[p] * yin + Rb[p];
-            Rb[p] = yin;
-        }
-        // backward: u_i = y_i - g_i u_{i+1}, composed from the top
-        A = 1.0;
-        B = 0.0;
-#pragma unroll
-        for (int e = E - 1; e >= 0; --e) {
-            const int p = lane * S + e;
-            B = -Gl[p] * B + Rb[p];
-            A = -Gl[p] * A;
-        }
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double Ap = __shfl_down(A, off, 64), Bp = __shfl_down(B, off, 64);
-            if (lane + off < 64) {
-                B = A * Bp + B;
-                A = A * Ap;
-            }
-        }
-        double uin = __shfl_down(B, 1, 64);
-        if (lane == 63) uin = 0.0;
-#pragma unroll
-        for (int e = E - 1; e >= 0; --e) {
-            const int p = lane * S + e;
-            uin = Rb[p] - Gl[p] * uin;
-            Rb[p] = uin;
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int t = 0; t < E; ++t) {
-            const int i = t * 64 + lane;
-            if (i < nx) x[xl + i] += Rb[pos(i)];
-        }
-    }
+    if (wv >= static_cast<long long>(nlc) * np) return;   // whole waves exit together
+    const int pb = static_cast<int>(wv / nlc);
+    const int j = colour + 2 * static_cast<int>(wv % nlc);
+    const long long cb = static_cast<long long>(k0 + ks * pb) * Q.ny * Q.nx;
+    const long long xb = static_cast<long long>(pb) * Q.ny * Q.nx;
+    relax_line<E>(Q, b, x, cb, xb, j, lds + w * 3 * 64 * relax_stride(E));
 }
 
 // b_c = P^T (b - Q x) for np planes: coarse line J takes fine line 2J+1,
