@@ -568,13 +568,34 @@ __global__ __launch_bounds__(256) void k_block_resid_dots(const double *AX, cons
     }
 }
 
-__global__ void k_coldot_reduce(const double *part, int nslices, int m, double *out)
+// out[c] = sum_z part[c][z]: one block per column, its threads summing the
+// slices z = t, t + 256, ... and the block combining them in a fixed order
+__global__ __launch_bounds__(256) void k_coldot_reduce(const double *part, int nslices, double *out)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m) return;
+    __shared__ double lds[4];
+    const int c = blockIdx.x;
     double s = 0.0;
-    for (int z = 0; z < nslices; ++z) s += part[c * nslices + z];
-    out[c] = s;
+    for (int z = threadIdx.x; z < nslices; z += blockDim.x) s += part[static_cast<long long>(c) * nslices + z];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+}
+
+// G[e] = sum_z part[z][e] for a small product (the narrow bases): one block
+// per entry, reduced like k_coldot_reduce
+__global__ __launch_bounds__(256) void k_gram_reduce_narrow(const double *part, int nz, int pq, double *G)
+{
+    __shared__ double lds[4];
+    const int e = blockIdx.x;
+    double s = 0.0;
+    for (int z = threadIdx.x; z < nz; z += blockDim.x) s += part[static_cast<long long>(z) * pq + e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) G[e] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
 // X[:, c] *= 1/sqrt(nrm2[c]) (and the same for AX when given)
@@ -682,8 +703,7 @@ struct Lob {
                     hipLaunchKernelGGL((k_gram_narrow<kNarrow, false>), dim3(nz), dim3(256), 0, st, U, V, ln, p, ln,
                                        sl, pt);
             }
-            hipLaunchKernelGGL(k_gram_reduce, dim3(nblk(static_cast<long long>(p) * q, 64)), dim3(64 * kRedGroups), 0, st,
-                               pt, nz, p, q, 16, 0, at<double>(L.G));
+            hipLaunchKernelGGL(k_gram_reduce_narrow, dim3(p * q), dim3(256), 0, st, pt, nz, p * q, at<double>(L.G));
             return;
         }
         if (s && p <= kTriMax) {   // narrow: all upper 16-blocks per block, slices of N
@@ -822,7 +842,7 @@ struct Lob {
         const long long slice = (static_cast<long long>(N) + ns - 1) / ns;
         hipLaunchKernelGGL(k_coldot_partial, dim3(ns, mcols), dim3(256), 0, st, U, V, static_cast<long long>(N),
                            static_cast<long long>(N), slice, part, ns);
-        hipLaunchKernelGGL(k_coldot_reduce, dim3(nblk(mcols, 64)), dim3(64), 0, st, part, ns, mcols, out);
+        hipLaunchKernelGGL(k_coldot_reduce, dim3(mcols), dim3(256), 0, st, part, ns, out);
     }
 
     void normalize(double *X, double *AX, int mcols)
@@ -1045,7 +1065,7 @@ int lobpcg_solve(smg_handle *h, int32_t m, double *X, double *lambda, double *re
             double *cp = lb.at<double>(lb.L.cpart);
             hipLaunchKernelGGL(k_block_resid_dots, dim3(ns, m), dim3(256), 0, st, AS, S, theta_d, R, ld, ld, slice, cp,
                                ns, m);
-            hipLaunchKernelGGL(k_coldot_reduce, dim3(nblk(2 * m, 64)), dim3(64), 0, st, cp, ns, 2 * m, cout);
+            hipLaunchKernelGGL(k_coldot_reduce, dim3(2 * m), dim3(256), 0, st, cp, ns, cout);
         }
         std::vector<double> nr(2 * m);
         if (hipMemcpyAsync(nr.data(), cout, 2 * m * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
