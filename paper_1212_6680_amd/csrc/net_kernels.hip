@@ -296,16 +296,17 @@ __global__ __launch_bounds__(256) void k_in16_bf16(In16Args a)
 // out_scale * (acc + b).  w: the layer's bf16 weights W[t][ci] as channel
 // pairs, kept in LDS; each thread computes SRY voxels along y.
 template <int EPI>
-__global__ __launch_bounds__(256) void k_out16_bf16(Out16Args a)
+__global__ __launch_bounds__(256) void k_out16_bf16(Out16Args a, const u32x4 *__restrict__ wg)
 {
     __shared__ u32x4 lds[3 * 2 * SPLANE];
-    __shared__ u32x4 wl[27 * 2];
     constexpr int ITEMS = 2 * SPLANE, PER = (ITEMS + 255) / 256;
     const int tx = threadIdx.x % STX, ty = threadIdx.x / STX;
     const int x0 = blockIdx.x * STX, y0 = blockIdx.y * STY;
     const int z0 = blockIdx.z * a.zc, z1 = min(z0 + a.zc, a.nz);
     const u32x4 *in = reinterpret_cast<const u32x4 *>(a.in);
-    if (threadIdx.x < 27 * 2) wl[threadIdx.x] = reinterpret_cast<const u32x4 *>(a.w)[threadIdx.x];
+    // the weights are the same for every lane: read per tap plane through the
+    // scalar cache (wg is a read-only kernel argument) rather than from LDS,
+    // which the activations need
     auto fetch = [&](int zi, u32x4 *reg) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
@@ -346,7 +347,13 @@ __global__ __launch_bounds__(256) void k_out16_bf16(Out16Args a)
 #pragma unroll
         for (int r = 0; r < SRY; ++r) acc[r] = 0.f;
 #pragma unroll 1
-        for (int dz = 0; dz < 3; ++dz)
+        for (int dz = 0; dz < 3; ++dz) {
+            u32x4 wz[9][2];
+#pragma unroll
+            for (int t9 = 0; t9 < 9; ++t9) {
+                wz[t9][0] = wg[2 * (9 * dz + t9)];
+                wz[t9][1] = wg[2 * (9 * dz + t9) + 1];
+            }
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
@@ -358,8 +365,7 @@ __global__ __launch_bounds__(256) void k_out16_bf16(Out16Args a)
                     for (int dy = 0; dy < 3; ++dy) {
                         const int r = yy - dy;
                         if (r >= 0 && r < SRY) {
-                            const int t = 9 * dz + 3 * dy + dx;
-                            const u32x4 w0 = wl[2 * t], w1 = wl[2 * t + 1];
+                            const u32x4 w0 = wz[3 * dy + dx][0], w1 = wz[3 * dy + dx][1];
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 acc[r] = dot2(v0[e], w0[e], acc[r]);
@@ -368,6 +374,7 @@ __global__ __launch_bounds__(256) void k_out16_bf16(Out16Args a)
                         }
                     }
                 }
+        }
 #pragma unroll
         for (int r = 0; r < SRY; ++r) {
             const int gy = y0 + SRY * ty + r;
@@ -776,9 +783,9 @@ void launch_out16_bf16(const Out16Args &a0, int epi, hipStream_t st)
     a.zc = single_zc(a.nx, a.ny, a.nz, &gz);
     const dim3 grid((a.nx + STX - 1) / STX, (a.ny + STY - 1) / STY, gz);
     if (epi == 2)
-        hipLaunchKernelGGL(k_out16_bf16<2>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_out16_bf16<2>, grid, dim3(256), 0, st, a, reinterpret_cast<const u32x4 *>(a.w));
     else
-        hipLaunchKernelGGL(k_out16_bf16<3>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_out16_bf16<3>, grid, dim3(256), 0, st, a, reinterpret_cast<const u32x4 *>(a.w));
 }
 
 template <typename T, typename A, int CIN, int COUT, int INM, int EPI>
