@@ -44,8 +44,8 @@ KERNEL_NAMES = {
     "chain2": "k2_chain (2D prolongation chain + 3D correction)",
     "up2": "k2_up (fused prolongation + post-smoothing)",
     "chain3": "k3_chain (3D prolongation chain)",
-    "resid3": "k_resid3 (3D colour residual)",
-    "restrict3": "k_restrict3 (3D residual + restriction)",
+    "resid3": "k_resid3v (3D colour residual)",
+    "restrict3": "k_restrict3_march / k_restrict3 (3D residual + restriction)",
     "prolong3": "k_prolong3", "line_relax": "k_line_relax", "restrict2": "k_restrict2",
     "prolong2": "k_prolong2", "correct3": "k_correct3",
 }
@@ -102,6 +102,7 @@ def precision_configs(torch, dev):
     x64 = None
     for prec in ("f64", "f32", "bf16"):
         G = SMG(shape, c, 1, 0, precision=prec)
+        tune = G.autotune(b, reps=2)
         x = torch.empty_like(b)
         G.fpcg(b, x, rtol=1e-8, max_iter=3, zero_x0=True)
         torch.cuda.synchronize()
@@ -112,8 +113,29 @@ def precision_configs(torch, dev):
         if prec == "f64":
             x64 = x.clone()
         err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+        # the V-cycle alone, and per kernel family: launches, ms and algorithmic
+        # bytes per V-cycle (values stored in the precision's storage type)
+        s = torch.empty_like(b)
+        G.apply(b, s)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(10):
+            G.apply(b, s)
+        ev1.record()
+        torch.cuda.synchronize()
+        vms = ev0.elapsed_time(ev1) / 10
+        fams = {}
+        for fam in ("down2", "coarse2", "chain2", "chain3", "resid3", "restrict3"):
+            nl, ms, by = G.profile_kernel(fam, b, reps=3)
+            if nl:
+                fams[fam] = {"launches": nl, "ms": round(ms, 4), "mb": round(by / 1e6, 1),
+                             "gbs": round(by / (ms * 1e-3) / 1e9, 1)}
         res[f"fpcg_384_smg_{prec}"] = {"s": dt, "iters": info.iters, "status": info.status,
-                                       "true_rel_res": info.true_rel_res, "rel_err_vs_f64_solution": err}
+                                       "true_rel_res": info.true_rel_res, "rel_err_vs_f64_solution": err,
+                                       "vcycle_ms": vms, "vcycle_gdof_per_s": n ** 3 / (vms * 1e-3) / 1e9,
+                                       "schedule": {"l0": tune.l0, "march_waves": tune.march_waves},
+                                       "kernels_per_vcycle": fams}
         del G
     del b, x, x64
     torch.cuda.empty_cache()
@@ -494,6 +516,22 @@ def main():
                          "gbs": by / (ms * 1e-3) / 1e9}
     dom = max(fams, key=lambda f: fams[f]["ms"])
     d = fams[dom]
+
+    # the same V-cycle summed per 3D level (z-semicoarsening keeps the odd
+    # planes: nz -> nz // 2); the last row is the prolongation chain that
+    # spans every level
+    rows = G.profile_levels(b, reps=3)
+    split = {f: G.profile_levels(b, reps=3, family=f) for f in fams}
+    per_level, nzl = [], n
+    for i, (nl, ms, by) in enumerate(rows):
+        if nl == 0:
+            continue
+        last = i == len(rows) - 1
+        per_level.append({"level": "chain3" if last else i, "nz": None if last else nzl, "launches": nl,
+                          "ms": round(ms, 4), "mb": round(by / 1e6, 2),
+                          "gbs": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                          "ms_by_family": {f: round(split[f][i][1], 4) for f in split if split[f][i][0]}})
+        nzl //= 2
     achieved = d["gbs"]
     traffic = read_traffic(dom, (tune.l0, tune.coarse_lds, tune.march_waves))
 
@@ -535,6 +573,7 @@ def main():
             "share_of_vcycle": d["ms"] / vcycle_ms,
         },
         "kernels_per_vcycle": {f: {k: round(v, 4) for k, v in fams[f].items()} for f in fams},
+        "levels_per_vcycle": per_level,
     }
 
     if not args.no_variants:

@@ -82,7 +82,10 @@ typedef struct smg_opts {
     int32_t order;                  /* 0: pre F then C (default); 1: pre C then F */
     int32_t precision;              /* SMG_PREC_* */
     int32_t kernel_mode;            /* 0: fused schedule where it applies (default);
-                                       1: one launch per stage (reference schedule) */
+                                       1: one launch per stage (reference schedule);
+                                       2: the fused schedule with its streaming
+                                          kernels at one point per thread (the
+                                          same arithmetic, for comparison) */
 } smg_opts;
 
 enum { SMG_STOP_2NORM = 0, SMG_STOP_CNORM = 1 };
@@ -289,8 +292,9 @@ int lobpcg_profile_gram(smg_handle *h, int32_t m, int32_t k, void *ws, size_t ws
  * The returned handle is used like smg_setup's with smg_apply, smg_matvec,
  * pcg_solve, fpcg_solve, psd_solve, lobpcg_solve and the Section 5
  * diagnostics; opts->precision must be SMG_PREC_F64 (kernel_mode is
- * ignored).  smg_autotune, smg_profile_kernel, the batched solver and the
- * learned post-smoother reject such handles (SMG_EINVAL).  The caller's
+ * ignored).  smg_autotune, smg_profile_kernel, smg_profile_levels, the
+ * batched solver and the learned post-smoother reject such handles
+ * (SMG_EINVAL).  The caller's
  * coefficient arrays are read during setup only. */
 enum { SMG_INTERP_LINEAR = 0, SMG_INTERP_OPERATOR = 1 };
 int smgv_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const smg_opts *o, int32_t interp, int32_t max_nrhs,
@@ -367,6 +371,23 @@ enum {
  * must read or write, counted once).  s is overwritten. */
 int smg_profile_kernel(smg_handle *h, int32_t family, const double *r, double *s, int32_t reps, void *stream,
                        int32_t *launches, double *kernel_ms, double *bytes);
+
+/* Measurement: the same V-cycles with every launch of kernel family `family`
+ * (every launch when family is -1) stamped, summed per 3D level of the
+ * z-semicoarsening hierarchy (Section 3).  Row l (0 = finest)
+ * holds the launches that work on level l: its zebra sweeps with their plane
+ * solves and colour residuals, its restriction to level l + 1, and its
+ * prolongation and post-smoothing when there are any; the last row (index
+ * nlev3) holds the single prolongation chain of a V-cycle without
+ * post-smoothing, which spans every level (empty otherwise).  On return
+ * *nrows = nlev3 + 1 and launches[i], kernel_ms[i] (summed durations per
+ * V-cycle) and bytes[i] (algorithmic bytes per V-cycle) are filled for each
+ * row.  The arrays are caller-owned, of max_rows entries; SMG_EINVAL when
+ * max_rows < nlev3 + 1, for a family outside -1 .. SMG_KERNEL_COUNT - 1, a
+ * variable-coefficient handle or a null pointer.
+ * s is overwritten. */
+int smg_profile_levels(smg_handle *h, int32_t family, const double *r, double *s, int32_t reps, void *stream,
+                       int32_t max_rows, int32_t *nrows, int32_t *launches, double *kernel_ms, double *bytes);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMaxSmooth = 8;
 constexpr int kMaxNx = 512;
+constexpr int kProfAll = -1;      // profile every kernel family at once
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -105,13 +106,16 @@ struct smg_handle {
     Layout L;
     KScalars *host_sc;            // pinned host mirror of the device scalars
     smg::VarHier *var = nullptr;  // variable-coefficient hierarchy (smgv_setup), else null
-    // per-kernel profiling: launches of family prof_family get dispatch-stamped
-    // events and their algorithmic bytes are summed
+    // per-kernel profiling: launches of family prof_family (every family when
+    // it is kProfAll) get dispatch-stamped events and their algorithmic bytes
+    // are summed; ev_lev / ev_bytes tag each stamped launch with its 3D level
     bool prof;
     int prof_family;
     std::vector<hipEvent_t> ev;
     int ev_used;
     double prof_bytes;
+    std::vector<int> ev_lev;
+    std::vector<double> ev_bytes;
     template <typename X> X *at(size_t off) const { return reinterpret_cast<X *>(ws + off); }
 };
 
@@ -128,7 +132,7 @@ int check_grid(const smg_grid *g, const smg_opts *o)
         return SMG_EINVAL;
     if (o->order != 0 && o->order != 1) return SMG_EINVAL;
     if (o->precision < SMG_PREC_F64 || o->precision > SMG_PREC_BF16) return SMG_EINVAL;
-    if (o->kernel_mode != 0 && o->kernel_mode != 1) return SMG_EINVAL;
+    if (o->kernel_mode < 0 || o->kernel_mode > 2) return SMG_EINVAL;
     return SMG_OK;
 }
 
@@ -177,7 +181,7 @@ void apply_fused_schedule(smg_handle *h, size_t coarse_budget, size_t strip_budg
     h->S_up = S < 1 ? 1 : (S > 16 ? 16 : static_cast<int>(S));
     h->coarse_budget = coarse_budget;
     h->strip_budget = strip_budget;
-    h->fused = h->o.kernel_mode == 0 && nl <= kMaxLev && h->nz.size() <= static_cast<size_t>(kMaxLev3) &&
+    h->fused = h->o.kernel_mode != 1 && nl <= kMaxLev && h->nz.size() <= static_cast<size_t>(kMaxLev3) &&
                h->coarse_lds > 0;
 }
 
@@ -349,13 +353,21 @@ struct VCycle {
     long long ps2(int l2) const { return static_cast<long long>(h->g.nx) * h->ny2[l2]; }
     long long rs2(int l2) const { return static_cast<long long>(h->P2) * ps2(l2); }
 
+    int cur_lev = 0;        // 3D level whose work is being launched (profiling tag)
+
+    // widest points-per-thread the streaming kernels may take (0: their own choice)
+    int vmax() const { return h->o.kernel_mode == 2 ? 1 : 0; }
+
     // Events for this launch when its family is being profiled; `values` is the
     // launch's algorithmic traffic in stored values (each read or written once).
     LaunchEv ev_for(int family, double values)
     {
-        if (!h->prof || family != h->prof_family || h->ev_used + 2 > static_cast<int>(h->ev.size()))
+        if (!h->prof || (h->prof_family != kProfAll && family != h->prof_family) ||
+            h->ev_used + 2 > static_cast<int>(h->ev.size()))
             return LaunchEv{};
         LaunchEv e{h->ev[h->ev_used], h->ev[h->ev_used + 1]};
+        h->ev_lev[h->ev_used / 2] = cur_lev;
+        h->ev_bytes[h->ev_used / 2] = values * sizeof(T);
         h->ev_used += 2;
         h->prof_bytes += values * sizeof(T);
         return e;
@@ -506,6 +518,7 @@ struct VCycle {
             }
             for (int l = 0; l <= lc; ++l) ch.ny2[l] = h->ny2[l];
             ch.nx = nx; ch.np = bt.np; ch.nrhs = nrhs; ch.lc = lc;
+            ch.vmax = vmax();
             double lines = (2.0 + accumulate) * h->ny2[0];
             for (int l = 1; l <= lc; ++l) lines += h->ny2[l];
             launch_chain2<T, A>(ch, st, ev_for(SMG_KERNEL_CHAIN2, lines * nx * bt.np * static_cast<double>(nrhs)));
@@ -559,6 +572,7 @@ struct VCycle {
         ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
         ra.pc = PC(l);
         ra.self_zero = self_zero;
+        ra.vmax = vmax();
         launch_resid3<T, A>(ra, st, ev_for(SMG_KERNEL_RESID3, resid3_values(nz, np, self_zero)));
         bt.b = ra.r; bt.bps = p; bt.brs = rs2(0);
         if (self_zero) {           // own planes still zero: write the solve in place
@@ -593,6 +607,7 @@ struct VCycle {
             ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
             ra.pc = PC(l);
             ra.self_zero = self_zero;
+            ra.vmax = vmax();
             launch_resid3<T, A>(ra, st, ev_for(SMG_KERNEL_RESID3, resid3_values(nz, np, self_zero)));
             bt.b = ra.r; bt.bps = p; bt.brs = rs2(0);
         }
@@ -609,6 +624,7 @@ struct VCycle {
             a.nz[l] = h->nz[l];
         }
         a.L = L; a.nx = h->g.nx; a.ny = h->g.ny;
+        a.vmax = vmax();
         double planes = h->nz[0];
         for (int l = 0; l <= L; ++l) planes += h->nz[l];
         launch_chain3<T, A>(a, nrhs, st, ev_for(SMG_KERNEL_CHAIN3, planes * pl() * nrhs));
@@ -616,6 +632,7 @@ struct VCycle {
 
     void v3(int l)
     {
+        cur_lev = l;
         const int nz = h->nz[l];
         if (nz == 1) {
             Batch bt{1, 1, 0, PC(l), X(l), pl(), LD(l), B(l), pl(), LD(l)};
@@ -638,11 +655,16 @@ struct VCycle {
         ra.cx = static_cast<A>(h->g.cx); ra.cy = static_cast<A>(h->g.cy);
         ra.pc = PC(l);
         ra.x_zero = x_zero;
+        ra.vmax = vmax();
         launch_restrict3<T, A>(ra, st, ev_for(SMG_KERNEL_RESTRICT3,
                                              ((x_zero ? 1.0 : 2.0) * nz + h->nz[l + 1]) * pl() * nrhs));
         v3(l + 1);
+        cur_lev = l;
         if (chain3()) {          // no post-smoothing: all prolongations in one pass
-            if (l == 0) chain3_all();
+            if (l == 0) {
+                cur_lev = static_cast<int>(h->nz.size());   // spans every level
+                chain3_all();
+            }
             return;
         }
         Prolong3Args<T, A> pa{};
@@ -1079,6 +1101,55 @@ int static_scratch(char **out)
 
 }  // namespace
 
+namespace {
+
+// Runs `reps` single-vector V-cycles with the launches of `family` (or every
+// launch, kProfAll) stamped by events; per V-cycle, sums the launches, their
+// durations and their algorithmic bytes into row 0, or with by_level into the
+// row of the launch's 3D level (nrows = levels + 1).
+int profile_run(smg_handle *h, int family, bool by_level, const double *r, double *s, int reps, hipStream_t st,
+                int nrows, int32_t *launches, double *kernel_ms, double *bytes)
+{
+    if (h->ev.empty()) {
+        h->ev.resize(2 * 4096);
+        for (auto &e : h->ev)
+            if (hipEventCreate(&e) != hipSuccess) return SMG_EHIP;
+    }
+    h->ev_lev.assign(h->ev.size() / 2, 0);
+    h->ev_bytes.assign(h->ev.size() / 2, 0.0);
+    for (int i = 0; i < nrows; ++i) {
+        launches[i] = 0;
+        kernel_ms[i] = 0.0;
+        bytes[i] = 0.0;
+    }
+    h->prof = true;
+    h->prof_family = family;
+    for (int rep = 0; rep < reps; ++rep) {
+        h->ev_used = 0;
+        h->prof_bytes = 0;
+        vcycle(h, r, s, 1, static_cast<long long>(h->N), st);
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            h->prof = false;
+            return SMG_EHIP;
+        }
+        for (int i = 0; i < h->ev_used; i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) != hipSuccess) {
+                h->prof = false;
+                return SMG_EHIP;
+            }
+            const int row = by_level ? std::min(h->ev_lev[i / 2], nrows - 1) : 0;
+            if (rep == 0) ++launches[row];
+            kernel_ms[row] += ms / reps;
+            bytes[row] += h->ev_bytes[i / 2] / reps;
+        }
+    }
+    h->prof = false;
+    return SMG_OK;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -1429,40 +1500,28 @@ int smg_profile_kernel(smg_handle *h, int32_t family, const double *r, double *s
 {
     if (!h || !r || !s || reps < 1 || !launches || !kernel_ms || !bytes || h->var) return SMG_EINVAL;
     if (family < 0 || family >= SMG_KERNEL_COUNT) return SMG_EINVAL;
-    hipStream_t st = as_stream(stream);
-    if (h->ev.empty()) {
-        h->ev.resize(2 * 4096);
-        for (auto &e : h->ev)
-            if (hipEventCreate(&e) != hipSuccess) return SMG_EHIP;
-    }
-    h->prof = true;
-    h->prof_family = family;
-    double ms_total = 0.0, bytes_total = 0.0;
-    int per_cycle = 0;
-    for (int rep = 0; rep < reps; ++rep) {
-        h->ev_used = 0;
-        h->prof_bytes = 0;
-        vcycle(h, r, s, 1, static_cast<long long>(h->N), st);
-        if (hipStreamSynchronize(st) != hipSuccess) {
-            h->prof = false;
-            return SMG_EHIP;
-        }
-        per_cycle = h->ev_used / 2;
-        for (int i = 0; i < h->ev_used; i += 2) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) != hipSuccess) {
-                h->prof = false;
-                return SMG_EHIP;
-            }
-            ms_total += ms;
-        }
-        bytes_total += h->prof_bytes;
-    }
-    h->prof = false;
-    *launches = per_cycle;
-    *kernel_ms = ms_total / reps;
-    *bytes = bytes_total / reps;
+    const int nrows = 1;
+    std::vector<int> cnt(nrows);
+    std::vector<double> ms(nrows), by(nrows);
+    const int rc =
+        profile_run(h, family, false, r, s, reps, as_stream(stream), nrows, cnt.data(), ms.data(), by.data());
+    if (rc != SMG_OK) return rc;
+    *launches = cnt[0];
+    *kernel_ms = ms[0];
+    *bytes = by[0];
     return SMG_OK;
+}
+
+int smg_profile_levels(smg_handle *h, int32_t family, const double *r, double *s, int32_t reps, void *stream,
+                       int32_t max_rows, int32_t *nrows, int32_t *launches, double *kernel_ms, double *bytes)
+{
+    if (!h || !r || !s || reps < 1 || !nrows || !launches || !kernel_ms || !bytes || h->var) return SMG_EINVAL;
+    if (family < -1 || family >= SMG_KERNEL_COUNT) return SMG_EINVAL;
+    const int rows = static_cast<int>(h->nz.size()) + 1;
+    if (max_rows < rows) return SMG_EINVAL;
+    *nrows = rows;
+    return profile_run(h, family < 0 ? kProfAll : family, true, r, s, reps, as_stream(stream), rows, launches,
+                       kernel_ms, bytes);
 }
 
 }  // extern "C"

@@ -102,6 +102,7 @@ def lib():
         L.smg_strerror.argtypes = [C.c_int]
         L.smg_strerror.restype = C.c_char_p
         L.smg_profile_kernel.argtypes = [p, i32, p, p, i32, p, C.POINTER(i32), C.POINTER(d), C.POINTER(d)]
+        L.smg_profile_levels.argtypes = [p, i32, p, p, i32, p, i32, C.POINTER(i32), p, p, p]
         if hasattr(L, "lobpcg_solve"):
             L.lobpcg_workspace_bytes.argtypes = [p, i32, C.POINTER(C.c_size_t)]
             L.lobpcg_profile_gram.argtypes = [p, i32, i32, p, C.c_size_t, i32, p, C.POINTER(d)]
@@ -506,6 +507,22 @@ class SMG:
         _check(lib().smg_profile_kernel(self.h, KERNELS[family], _dptr(r), _dptr(s), reps, _stream(),
                                         C.byref(nl), C.byref(ms), C.byref(by)), "smg_profile_kernel")
         return nl.value, ms.value, by.value
+
+    def profile_levels(self, r: torch.Tensor, reps: int = 3, family: str | None = None):
+        """Per 3D level (finest first, then the prolongation chain spanning every
+        level): (launches, kernel ms, algorithmic bytes) per V-cycle, of every
+        launch or of one kernel family."""
+        s = torch.empty_like(r)
+        rows = 64
+        nl = (C.c_int32 * rows)()
+        ms = (C.c_double * rows)()
+        by = (C.c_double * rows)()
+        nr = C.c_int32(0)
+        fam = -1 if family is None else KERNELS[family]
+        _check(lib().smg_profile_levels(self.h, fam, _dptr(r), _dptr(s), reps, _stream(), rows, C.byref(nr),
+                                        C.cast(nl, C.c_void_p), C.cast(ms, C.c_void_p), C.cast(by, C.c_void_p)),
+               "smg_profile_levels")
+        return [(nl[i], ms[i], by[i]) for i in range(nr.value)]
 
 
 def _tptr(t: torch.Tensor, dtype, n: int | None = None):

@@ -246,3 +246,57 @@ def test_workspace_prior_contents_do_not_matter(pp):
         outs.append((s, x, info.iters))
     assert torch.equal(outs[0][0], outs[1][0])
     assert torch.equal(outs[0][1], outs[1][1]) and outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("pp", [(1, 0), (1, 1)])
+def test_profile_levels_partitions_the_families(pp):
+    """The per-level profile stamps every launch once: its rows add up to the
+    per-family profiles' launches and algorithmic bytes, each row to its
+    per-family rows, the prolongation
+    chain row is used only without post-smoothing, and the profiled V-cycle
+    leaves the next V-cycle unchanged."""
+    from paper_1212_6680_amd.smg import KERNELS
+    shape = (64, 48, 40)
+    c = (2.0, 1.0, 3.0)
+    r = _dev(synth.rhs(*shape, seed=21))
+    G = _smg(shape, c, *pp)
+    rows = G.profile_levels(r, reps=2)
+    nz, nlev = shape[2], 1
+    while nz > 1:
+        nz //= 2
+        nlev += 1
+    assert len(rows) == nlev + 1
+    fam = [G.profile_kernel(f, r, reps=2) for f in KERNELS]
+    assert sum(x[0] for x in rows) == sum(x[0] for x in fam)
+    tot = sum(x[2] for x in fam)
+    assert abs(sum(x[2] for x in rows) - tot) <= 1e-9 * tot
+    assert all(x[0] >= 1 and x[1] > 0 for x in rows[:-1])
+    split = [G.profile_levels(r, reps=1, family=f) for f in KERNELS]
+    for i, row in enumerate(rows):
+        assert sum(f[i][0] for f in split) == row[0]
+        assert abs(sum(f[i][2] for f in split) - row[2]) <= 1e-9 * tot
+    assert (rows[-1][0] == 1) == (pp[1] == 0)
+    s = G.apply(r)
+    G.profile_levels(r, reps=1)
+    assert torch.equal(s, G.apply(r))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("shape,nrhs", [((256, 20, 12), 1), ((384, 30, 8), 1), ((128, 33, 17), 1),
+                                        ((96, 17, 9), 1), ((66, 10, 7), 1), ((130, 7, 5), 1),
+                                        ((33, 17, 9), 1), ((256, 12, 6), 3), ((192, 9, 10), 2)])
+@pytest.mark.parametrize("pp", [(1, 0), (1, 1)])
+def test_vector_streaming_kernels_match_one_point_per_thread(prec, shape, nrhs, pp):
+    """The residual, restriction and prolongation-chain kernels that give each
+    thread 2 or 4 consecutive points (8-byte accesses in FP32 and BF16) compute
+    bitwise what the same schedule computes at one point per thread
+    (kernel_mode 2), for widths that divide the row, ragged rows that fall back
+    and several right-hand sides."""
+    c = tuple((v + 1.0) ** 2 for v in shape)
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(5)
+    r = rng.uniform(-1, 1, size=(nrhs, n)) if nrhs > 1 else synth.rhs(*shape, seed=19)
+    rd = _dev(r)
+    a = _smg(shape, c, *pp, precision=prec, max_nrhs=nrhs, kernel_mode=0).apply(rd)
+    b = _smg(shape, c, *pp, precision=prec, max_nrhs=nrhs, kernel_mode=2).apply(rd)
+    assert torch.equal(a, b)
