@@ -852,19 +852,30 @@ __device__ inline Win coarser(Win f, int nc)
     return c;
 }
 
-// v (LDS, window wf of level l) = x_l(window wf) + P v_c (window wc of level l+1)
-template <typename A>
-__device__ inline A prolong_point(const A *vc, Win wc, int jj, int nc, int col)
+// v (LDS, window wf of level l) = x_l(window wf) + P v_c (window wc of level l+1),
+// for the V columns from col of a window whose lines are W values apart
+template <typename A, int V, int W>
+__device__ inline void prolong_point(A (&s)[V], const A *vc, Win wc, int jj, int nc, int col)
 {
-    A s = A(0);
+#pragma unroll
+    for (int e = 0; e < V; ++e) s[e] = A(0);
     if (jj & 1) {
-        s += vc[(((jj - 1) >> 1) - wc.lo) * kChainCols + col];
+        const A *u = vc + (((jj - 1) >> 1) - wc.lo) * W + col;
+#pragma unroll
+        for (int e = 0; e < V; ++e) s[e] += u[e];
     } else {
         const int Jc = jj >> 1;
-        if (Jc - 1 >= 0) s += A(0.5) * vc[(Jc - 1 - wc.lo) * kChainCols + col];
-        if (Jc < nc) s += A(0.5) * vc[(Jc - wc.lo) * kChainCols + col];
+        if (Jc - 1 >= 0) {
+            const A *u = vc + (Jc - 1 - wc.lo) * W + col;
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[e] += A(0.5) * u[e];
+        }
+        if (Jc < nc) {
+            const A *u = vc + (Jc - wc.lo) * W + col;
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[e] += A(0.5) * u[e];
+        }
     }
-    return s;
 }
 
 // Window lines (planes) per thread (4 rows of threads) of chain level l for a
@@ -880,13 +891,17 @@ __host__ __device__ constexpr int chain_off(int l)
 }
 static_assert(kChainRun == 32, "chain_rows assumes runs of 32 fine planes");
 
-template <typename T, typename A, bool ACC>
+// V: consecutive columns per thread (a block owns 64 V columns), read and
+// written as one aligned access; the launcher takes V > 1 only when every row
+// and plane offset is a multiple of V.
+template <typename T, typename A, bool ACC, int V>
 __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const Blk &blk)
 {
-    __shared__ A vs[2][kChainWin * kChainCols];
+    constexpr int W = kChainCols * V;
+    __shared__ A vs[2][kChainWin * W];
     constexpr int kRows0 = kChainRun / 4;       // fine lines per thread
     const int nx = a.nx;
-    const int ncol = (nx + kChainCols - 1) / kChainCols;
+    const int ncol = (nx + W - 1) / W;
     const int nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
     int bid = blk.x;
     const int ct = bid % ncol;
@@ -894,8 +909,9 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
     const int rt = bid % nrun;
     bid /= nrun;
     const int p = bid % a.np, r = bid / a.np;
-    const int col = threadIdx.x & (kChainCols - 1), row0 = threadIdx.x >> 6;   // 4 rows of 64
-    const int i = ct * kChainCols + col;
+    const int col = (threadIdx.x & (kChainCols - 1)) * V, row0 = threadIdx.x >> 6;   // 4 rows of 64 lanes
+    const int i = ct * W + col;
+    const int nok = i < nx ? min(V, nx - i) : 0;   // columns of this thread inside the row
     const Win w0{rt * kChainRun, min(a.ny2[0], rt * kChainRun + kChainRun) - 1};
     // windows of every level (uniform; recomputed from the fine run)
     auto win = [&](int l) {
@@ -903,32 +919,35 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
         for (int m = 0; m < l; ++m) wv = coarser(wv, a.ny2[m + 1]);
         return wv;
     };
-    auto level_row = [&](int l, const Win &wl, int jj) -> A {
+    auto level_row = [&](int l, const Win &wl, int jj, A (&v)[V]) {
         const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
-        return jj <= wl.hi && i < nx ? static_cast<A>(ldv(xl + static_cast<long long>(jj) * nx + i)) : A(0);
+        vld<T, A, V>(v, xl + static_cast<long long>(jj) * nx + i, jj <= wl.hi ? nok : 0);
     };
     // every global read of chain levels 1..kChainPre and of the fine run
-    // (x and the accumulated output), issued before the first barrier
-    A pre[chain_off(kChainPre + 1)];
+    // (x and the accumulated output), issued before the first barrier and
+    // held as stored until used
+    Held<T, V> pre[chain_off(kChainPre + 1)];
 #pragma unroll
     for (int l = 1; l <= kChainPre; ++l) {
         if (l > a.lc) break;
         const Win wl = win(l);
+        const T *xl = a.xc[l] + r * a.crs[l] + p * a.cps[l];
 #pragma unroll
-        for (int t = 0; t < chain_rows(l); ++t) pre[chain_off(l) + t] = level_row(l, wl, wl.lo + row0 + 4 * t);
+        for (int t = 0; t < chain_rows(l); ++t) {
+            const int jj = wl.lo + row0 + 4 * t;
+            hld<T, V>(pre[chain_off(l) + t], xl + static_cast<long long>(jj) * nx + i, jj <= wl.hi ? nok : 0);
+        }
     }
     const T *x0 = a.x0 + r * a.x0rs + p * a.x0ps;
     T *out = a.out + r * a.ors + p * a.ops;
-    A xf[kRows0], of[kRows0];
+    Held<T, V> xf[kRows0], of[kRows0];
 #pragma unroll
     for (int t = 0; t < kRows0; ++t) {
         const int jj = w0.lo + row0 + 4 * t;
-        xf[t] = of[t] = A(0);
-        if (jj <= w0.hi && i < nx) {
-            const long long o = static_cast<long long>(jj) * nx + i;
-            xf[t] = static_cast<A>(ldv(x0 + o));
-            if constexpr (ACC) of[t] = static_cast<A>(ldv(out + o));
-        }
+        const long long o = static_cast<long long>(jj) * nx + i;
+        const int n = jj <= w0.hi ? nok : 0;
+        hld<T, V>(xf[t], x0 + o, n);
+        if constexpr (ACC) hld<T, V>(of[t], out + o, n);
     }
     int cur = 0;
     bool first = true;   // the coarsest level is stored as it is
@@ -937,7 +956,12 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
         if (first) {
             for (int t = 0; t < nrows; ++t) {
                 const int jj = wl.lo + row0 + 4 * t;
-                if (jj <= wl.hi) vs[cur][(jj - wl.lo) * kChainCols + col] = xval(t, jj, wl);
+                if (jj <= wl.hi) {
+                    A v[V];
+                    xval(t, jj, wl, v);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) vs[cur][(jj - wl.lo) * W + col + e] = v[e];
+                }
             }
             first = false;
         } else {
@@ -945,88 +969,105 @@ __device__ __forceinline__ void k2_chain_body(const Chain2Args<T, A> &a, const B
             for (int t = 0; t < nrows; ++t) {
                 const int jj = wl.lo + row0 + 4 * t;
                 if (jj > wl.hi) break;
-                const A s = xval(t, jj, wl) + prolong_point(vs[cur], wc, jj, a.ny2[l + 1], col);
-                vs[cur ^ 1][(jj - wl.lo) * kChainCols + col] = s;
+                A v[V], pv[V];
+                xval(t, jj, wl, v);
+                prolong_point<A, V, W>(pv, vs[cur], wc, jj, a.ny2[l + 1], col);
+#pragma unroll
+                for (int e = 0; e < V; ++e) vs[cur ^ 1][(jj - wl.lo) * W + col + e] = v[e] + pv[e];
             }
             cur ^= 1;
         }
         __syncthreads();
     };
     for (int l = a.lc; l > kChainPre; --l)
-        step(l, kChainWin / 4, [&](int, int jj, const Win &wl) { return level_row(l, wl, jj); });
+        step(l, kChainWin / 4, [&](int, int jj, const Win &wl, A (&v)[V]) { level_row(l, wl, jj, v); });
 #pragma unroll
     for (int l = kChainPre; l >= 1; --l) {
         if (l > a.lc) continue;
-        step(l, chain_rows(l), [&](int t, int, const Win &) { return pre[chain_off(l) + t]; });
+        step(l, chain_rows(l), [&](int t, int, const Win &, A (&v)[V]) { unpack<T, A, V>(v, pre[chain_off(l) + t]); });
     }
-    if (i >= nx) return;   // after the last barrier
+    if (nok == 0) return;   // after the last barrier
     const Win wc = win(1);
 #pragma unroll
     for (int t = 0; t < kRows0; ++t) {
         const int jj = w0.lo + row0 + 4 * t;
         if (jj > w0.hi) break;
-        A s = xf[t] + prolong_point(vs[cur], wc, jj, a.ny2[1], col);
-        if constexpr (ACC) s += of[t];
-        stv(out + static_cast<long long>(jj) * nx + i, s);
+        A pv[V], v[V], o[V];
+        prolong_point<A, V, W>(pv, vs[cur], wc, jj, a.ny2[1], col);
+        unpack<T, A, V>(v, xf[t]);
+        if constexpr (ACC) unpack<T, A, V>(o, of[t]);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            v[e] = v[e] + pv[e];
+            if constexpr (ACC) v[e] += o[e];
+        }
+        vst<T, A, V>(out + static_cast<long long>(jj) * nx + i, v, nok);
     }
 }
 
 // ACC: the output is accumulated into (read back) rather than assigned; the
 // assigning kernel keeps no registers for the read-back
-template <typename T, typename A, bool ACC>
+template <typename T, typename A, bool ACC, int V>
 __global__ __launch_bounds__(256) void k2_chain(Chain2Args<T, A> a)
 {
-    k2_chain_body<T, A, ACC>(a, SMG_BLK_XCD);
+    k2_chain_body<T, A, ACC, V>(a, SMG_BLK_XCD);
 }
 
-template <typename T, typename A, bool ACC>
+template <typename T, typename A, bool ACC, int V>
 __global__ __launch_bounds__(256) void k2_chain_grp(const GroupEntry *tab, int n)
 {
     const Chain2Args<T, A> *a;
     Blk blk;
     if (!group_entry(tab, n, a, blk)) return;
-    k2_chain_body<T, A, ACC>(*a, blk);
+    k2_chain_body<T, A, ACC, V>(*a, blk);
 }
 
 
-template <typename T, typename A>
+// V: consecutive in-plane points per thread, as in the 2D chain
+template <typename T, typename A, int V>
 __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const Blk &blk)
 {
-    __shared__ A vs[2][kChainWin * kChainCols];
+    constexpr int W = kChainCols * V;
+    __shared__ A vs[2][kChainWin * W];
     constexpr int kRows0 = kChainRun / 4;       // fine planes per thread
     const long long pl = static_cast<long long>(a.nx) * a.ny;
-    const int ncol = static_cast<int>((pl + kChainCols - 1) / kChainCols);
+    const int ncol = static_cast<int>((pl + W - 1) / W);
     const int ct = blk.x % ncol;
     const int rt = blk.x / ncol;
     const int r = blk.y;
-    const int col = threadIdx.x & (kChainCols - 1), row0 = threadIdx.x >> 6;
-    const long long c = static_cast<long long>(ct) * kChainCols + col;
+    const int col = (threadIdx.x & (kChainCols - 1)) * V, row0 = threadIdx.x >> 6;
+    const long long c = static_cast<long long>(ct) * W + col;
+    const int nok = c < pl ? static_cast<int>(pl - c < V ? pl - c : V) : 0;
     const Win w0{rt * kChainRun, min(a.nz[0], rt * kChainRun + kChainRun) - 1};
     auto win = [&](int l) {
         Win wv = w0;
         for (int m = 0; m < l; ++m) wv = coarser(wv, a.nz[m + 1]);
         return wv;
     };
-    auto level_row = [&](int l, const Win &wl, int kk) -> A {
+    auto level_row = [&](int l, const Win &wl, int kk, A (&v)[V]) {
         const T *xl = a.x[l] + r * a.rs[l];
-        return kk <= wl.hi && c < pl ? static_cast<A>(ldv(xl + kk * pl + c)) : A(0);
+        vld<T, A, V>(v, xl + kk * pl + c, kk <= wl.hi ? nok : 0);
     };
     // every global read of chain levels 1..kChainPre and of the fine run,
-    // issued before the first barrier
-    A pre[chain_off(kChainPre + 1)];
+    // issued before the first barrier and held as stored until used
+    Held<T, V> pre[chain_off(kChainPre + 1)];
 #pragma unroll
     for (int l = 1; l <= kChainPre; ++l) {
         if (l > a.L) break;
         const Win wl = win(l);
+        const T *xl = a.x[l] + r * a.rs[l];
 #pragma unroll
-        for (int t = 0; t < chain_rows(l); ++t) pre[chain_off(l) + t] = level_row(l, wl, wl.lo + row0 + 4 * t);
+        for (int t = 0; t < chain_rows(l); ++t) {
+            const int kk = wl.lo + row0 + 4 * t;
+            hld<T, V>(pre[chain_off(l) + t], xl + kk * pl + c, kk <= wl.hi ? nok : 0);
+        }
     }
     T *x0 = a.x[0] + r * a.rs[0];
-    A xf[kRows0];
+    Held<T, V> xf[kRows0];
 #pragma unroll
     for (int t = 0; t < kRows0; ++t) {
         const int kk = w0.lo + row0 + 4 * t;
-        xf[t] = kk <= w0.hi && c < pl ? static_cast<A>(ldv(x0 + kk * pl + c)) : A(0);
+        hld<T, V>(xf[t], x0 + kk * pl + c, kk <= w0.hi ? nok : 0);
     }
     int cur = 0;
     bool first = true;   // the coarsest level is stored as it is
@@ -1035,7 +1076,12 @@ __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const B
         if (first) {
             for (int t = 0; t < nrows; ++t) {
                 const int kk = wl.lo + row0 + 4 * t;
-                if (kk <= wl.hi) vs[cur][(kk - wl.lo) * kChainCols + col] = xval(t, kk, wl);
+                if (kk <= wl.hi) {
+                    A v[V];
+                    xval(t, kk, wl, v);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) vs[cur][(kk - wl.lo) * W + col + e] = v[e];
+                }
             }
             first = false;
         } else {
@@ -1043,43 +1089,51 @@ __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const B
             for (int t = 0; t < nrows; ++t) {
                 const int kk = wl.lo + row0 + 4 * t;
                 if (kk > wl.hi) break;
-                const A s = xval(t, kk, wl) + prolong_point(vs[cur], wc, kk, a.nz[l + 1], col);
-                vs[cur ^ 1][(kk - wl.lo) * kChainCols + col] = s;
+                A v[V], pv[V];
+                xval(t, kk, wl, v);
+                prolong_point<A, V, W>(pv, vs[cur], wc, kk, a.nz[l + 1], col);
+#pragma unroll
+                for (int e = 0; e < V; ++e) vs[cur ^ 1][(kk - wl.lo) * W + col + e] = v[e] + pv[e];
             }
             cur ^= 1;
         }
         __syncthreads();
     };
     for (int l = a.L; l > kChainPre; --l)
-        step(l, kChainWin / 4, [&](int, int kk, const Win &wl) { return level_row(l, wl, kk); });
+        step(l, kChainWin / 4, [&](int, int kk, const Win &wl, A (&v)[V]) { level_row(l, wl, kk, v); });
 #pragma unroll
     for (int l = kChainPre; l >= 1; --l) {
         if (l > a.L) continue;
-        step(l, chain_rows(l), [&](int t, int, const Win &) { return pre[chain_off(l) + t]; });
+        step(l, chain_rows(l), [&](int t, int, const Win &, A (&v)[V]) { unpack<T, A, V>(v, pre[chain_off(l) + t]); });
     }
-    if (c >= pl) return;
+    if (nok == 0) return;
     const Win wc = win(1);
 #pragma unroll
     for (int t = 0; t < kRows0; ++t) {
         const int kk = w0.lo + row0 + 4 * t;
         if (kk > w0.hi) break;
-        stv(x0 + kk * pl + c, xf[t] + prolong_point(vs[cur], wc, kk, a.nz[1], col));
+        A pv[V], v[V];
+        prolong_point<A, V, W>(pv, vs[cur], wc, kk, a.nz[1], col);
+        unpack<T, A, V>(v, xf[t]);
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = v[e] + pv[e];
+        vst<T, A, V>(x0 + kk * pl + c, v, nok);
     }
 }
 
-template <typename T, typename A>
+template <typename T, typename A, int V>
 __global__ __launch_bounds__(256) void k3_chain(Chain3Args<T, A> a)
 {
-    k3_chain_body<T, A>(a, SMG_BLK_HW);
+    k3_chain_body<T, A, V>(a, SMG_BLK_HW);
 }
 
-template <typename T, typename A>
+template <typename T, typename A, int V>
 __global__ __launch_bounds__(256) void k3_chain_grp(const GroupEntry *tab, int n)
 {
     const Chain3Args<T, A> *a;
     Blk blk;
     if (!group_entry(tab, n, a, blk)) return;
-    k3_chain_body<T, A>(*a, blk);
+    k3_chain_body<T, A, V>(*a, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1288,19 +1342,47 @@ void launch_coarse2(const Coarse2Args<T, A> &a, size_t lds_bytes, hipStream_t st
                               dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds_bytes, st, a));
 }
 
+// Points per thread of the 2D chain: tile_vec's width when every row, plane
+// and right-hand-side offset is a multiple of it.
 template <typename T, typename A>
-void launch_chain2(const Chain2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
+int chain2_vec(const Chain2Args<T, A> &a)
 {
-    const long long ncol = (a.nx + kChainCols - 1) / kChainCols;
+    const int V = a.vmax == 1 ? 1 : tile_vec<T>(a.nx);
+    if (V == 1) return 1;
+    auto ok = [&](long long v) { return v % V == 0; };
+    auto aligned = [&](const void *q) { return reinterpret_cast<uintptr_t>(q) % (V * sizeof(T)) == 0; };
+    if (!ok(a.x0ps) || !ok(a.x0rs) || !ok(a.ops) || !ok(a.ors) || !aligned(a.x0) || !aligned(a.out)) return 1;
+    for (int l = 1; l <= a.lc; ++l)
+        if (!ok(a.cps[l]) || !ok(a.crs[l]) || !aligned(a.xc[l])) return 1;
+    return V;
+}
+
+template <typename T, typename A, int V>
+void launch_chain2_v(const Chain2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
+{
+    const long long ncol = (a.nx + kChainCols * V - 1) / (kChainCols * V);
     const long long nrun = (a.ny2[0] + kChainRun - 1) / kChainRun;
     const long long nblk = ncol * nrun * a.np * a.nrhs;
     if (nblk == 0) return;
     if (a.accumulate)
-        SMG_LAUNCH_G(ev, (k2_chain<T, A, true>), (k2_chain_grp<T, A, true>), dim3(static_cast<unsigned>(nblk)),
+        SMG_LAUNCH_G(ev, (k2_chain<T, A, true, V>), (k2_chain_grp<T, A, true, V>), dim3(static_cast<unsigned>(nblk)),
                      dim3(256), 0, st, a);
     else
-        SMG_LAUNCH_G(ev, (k2_chain<T, A, false>), (k2_chain_grp<T, A, false>), dim3(static_cast<unsigned>(nblk)),
-                     dim3(256), 0, st, a);
+        SMG_LAUNCH_G(ev, (k2_chain<T, A, false, V>), (k2_chain_grp<T, A, false, V>),
+                     dim3(static_cast<unsigned>(nblk)), dim3(256), 0, st, a);
+}
+
+template <typename T, typename A>
+void launch_chain2(const Chain2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
+{
+    const int v = chain2_vec(a);
+    if (v == 4) {
+        if constexpr (stream_vec<T>() >= 4) launch_chain2_v<T, A, 4>(a, st, ev);
+    } else if (v == 2) {
+        if constexpr (stream_vec<T>() >= 2) launch_chain2_v<T, A, 2>(a, st, ev);
+    } else {
+        launch_chain2_v<T, A, 1>(a, st, ev);
+    }
 }
 
 template <typename T, typename A>
@@ -1316,14 +1398,27 @@ void launch_up2(const Up2Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
                               dim3(static_cast<unsigned>(nblk)), dim3(kThreads), lds, st, a));
 }
 
+template <typename T, typename A, int V>
+void launch_chain3_v(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const LaunchEv &ev)
+{
+    const long long pl = static_cast<long long>(a.nx) * a.ny;
+    const long long ncol = (pl + kChainCols * V - 1) / (kChainCols * V);
+    const long long nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
+    SMG_LAUNCH_G(ev, (k3_chain<T, A, V>), (k3_chain_grp<T, A, V>), dim3(static_cast<unsigned>(ncol * nrun), nrhs),
+                 dim3(256), 0, st, a);
+}
+
 template <typename T, typename A>
 void launch_chain3(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const LaunchEv &ev)
 {
-    const long long pl = static_cast<long long>(a.nx) * a.ny;
-    const long long ncol = (pl + kChainCols - 1) / kChainCols;
-    const long long nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
-    SMG_LAUNCH_G(ev, (k3_chain<T, A>), (k3_chain_grp<T, A>), dim3(static_cast<unsigned>(ncol * nrun), nrhs), dim3(256), 0,
-                 st, a);
+    constexpr int V = stream_vec<T>();
+    bool vec = V > 1 && a.vmax != 1 && (static_cast<long long>(a.nx) * a.ny) % V == 0;
+    for (int l = 0; l <= a.L && vec; ++l)
+        vec = a.rs[l] % V == 0 && reinterpret_cast<uintptr_t>(a.x[l]) % (V * sizeof(T)) == 0;
+    if (vec)
+        launch_chain3_v<T, A, V>(a, nrhs, st, ev);
+    else
+        launch_chain3_v<T, A, 1>(a, nrhs, st, ev);
 }
 
 #define SMG_FUSED_INSTANTIATE(T, A)                                                                      \

@@ -72,6 +72,104 @@ __device__ inline void stv(double *p, double v) { *p = v; }
 __device__ inline void stv(float *p, float v) { *p = v; }
 __device__ inline void stv(bf16 *p, float v) { *p = f_to_bf16(v); }
 
+// a * b + c with one rounding, written out so that kernels instantiated for
+// different widths round identically (the compiler's own contraction of
+// a * b + c * d may pick either product)
+__device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// V consecutive stored values as one aligned access of V * sizeof(T) bytes.
+// The caller guarantees that p is aligned to V elements; n_ok is the number
+// of values from p that lie inside the row (or plane): when it is below V
+// the values are read one by one, the missing ones as zero, and only the
+// valid ones are written.
+template <typename T, int V>
+struct alignas(V * sizeof(T)) VecPack {
+    T e[V];
+};
+
+template <typename T, typename A, int V>
+__device__ inline void vld(A (&v)[V], const T *p, int n_ok)
+{
+    if constexpr (V == 1) {
+        v[0] = n_ok > 0 ? static_cast<A>(ldv(p)) : A(0);
+    } else if (n_ok >= V) {
+        const VecPack<T, V> pk = *reinterpret_cast<const VecPack<T, V> *>(p);
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = ldv(&pk.e[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = e < n_ok ? static_cast<A>(ldv(p + e)) : A(0);
+    }
+}
+
+template <typename T, typename A, int V>
+__device__ inline void vst(T *p, const A (&v)[V], int n_ok)
+{
+    if constexpr (V == 1) {
+        if (n_ok > 0) stv(p, v[0]);
+    } else if (n_ok >= V) {
+        VecPack<T, V> pk;
+#pragma unroll
+        for (int e = 0; e < V; ++e) stv(&pk.e[e], v[e]);
+        *reinterpret_cast<VecPack<T, V> *>(p) = pk;
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (e < n_ok) stv(p + e, v[e]);
+    }
+}
+
+// V stored values held in registers as they were read (BF16 stays packed two
+// to a register until it is used); zero bits read as zero in every type.
+template <typename T, int V>
+struct Held {
+    VecPack<T, V> p;
+};
+
+template <typename T, int V>
+__device__ inline void hld(Held<T, V> &h, const T *p, int n_ok)
+{
+    if (n_ok >= V) {
+        h.p = *reinterpret_cast<const VecPack<T, V> *>(p);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            if (e < n_ok)
+                h.p.e[e] = p[e];
+            else
+                h.p.e[e] = T{};
+        }
+    }
+}
+
+template <typename T, typename A, int V>
+__device__ inline void unpack(A (&v)[V], const Held<T, V> &h)
+{
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[e] = ldv(&h.p.e[e]);
+}
+
+// Points per thread of the streaming kernels: eight bytes of storage per lane
+// and access in every precision.
+template <typename T>
+constexpr int stream_vec() { return static_cast<int>(8 / sizeof(T)); }
+
+// Points per thread along x for the tiled streaming kernels (tiles of 64 V
+// points): the widest power of two up to the storage type's vector width
+// that divides nx and leaves at most an eighth of the tiles' points idle
+// (wider tiles with idle lanes cost more in registers than they save).
+template <typename T>
+inline int tile_vec(int nx)
+{
+    for (int v = stream_vec<T>(); v > 1; v /= 2) {
+        if (nx % v != 0) continue;
+        const int w = 64 * v, waste = (nx + w - 1) / w * w - nx;
+        if (8 * waste <= nx) return v;
+    }
+    return 1;
+}
+
 // Coefficients of one x-line of a 2D level: L_j = la*Tx + lb*I, coupling to
 // line j+1 V_j = va*Tx + vb*I, Thomas table index fac.
 template <typename A>
@@ -150,6 +248,7 @@ struct Resid3Args {
     A cx, cy;
     const PlaneCoef<A> *pc;
     int self_zero;
+    int vmax;               // widest points per thread allowed (0: no limit)
 };
 
 template <typename T, typename A>
@@ -168,6 +267,7 @@ struct Restrict3Args {
     const PlaneCoef<A> *pc;
     int x_zero;             // x is known to be zero: bc = P^T b
     int kchunk;             // coarse planes per block of the marching kernel (set by the launcher)
+    int vmax;               // widest points per thread allowed (0: no limit)
 };
 
 template <typename T, typename A>
@@ -223,6 +323,7 @@ struct Chain2Args {
     int nx, np, nrhs, lc;
     int ny2[kMaxLev];
     int accumulate;
+    int vmax;               // widest points per thread allowed (0: no limit)
 };
 
 template <typename T, typename A>
@@ -243,6 +344,7 @@ struct Chain3Args {
     long long rs[kMaxLev3];
     int nz[kMaxLev3];
     int L, nx, ny;
+    int vmax;               // widest points per thread allowed (0: no limit)
 };
 
 template <typename T, typename A>

@@ -7,9 +7,11 @@
 //                   right-hand side b_j - V_{j-1} x_{j-1} - V_j x_{j+1};
 //   k_restrict2   - 2D residual + restriction P_y^T (fused);
 //   k_prolong2    - 2D prolongation P_y + correction;
-//   k_resid3      - 3D residual of the planes of one colour (15-point);
+//   k_resid3v     - 3D residual of the planes of one colour (15-point),
+//                   V consecutive points of a row per thread;
 //   k_correct3    - x_k += y_k for the planes of one colour;
-//   k_restrict3   - 3D residual + restriction P_z^T (fused);
+//   k_restrict3   - 3D residual + restriction P_z^T (fused; k_restrict3_march
+//                   marches z with V points of a row per thread);
 //   k_prolong3    - 3D prolongation P_z + correction.
 // Every kernel is batched over planes and right-hand sides and is bound by
 // HBM bandwidth; the line solve needs no LDS: a line of nx <= 512 points
@@ -258,32 +260,81 @@ __device__ inline A resid3_point(const T *x, const T *b, const PlaneCoef<A> *pc,
     return v;
 }
 
-template <typename T, typename A>
-__device__ __forceinline__ void k_resid3_body(const Resid3Args<T, A> &a, const Blk &blk)
+// The colour residual r_k = b_k - (A_l x)_k on the planes of one colour, with
+// V consecutive points of a row per thread (the launcher takes V > 1 when nx
+// and every plane and right-hand-side offset are multiples of V, else V = 1):
+// the row is read as V-wide accesses and the x-neighbours inside it are
+// taken from the registers; the arithmetic per point does not depend on V.
+template <typename T, typename A, int V>
+__device__ inline void plane_op_v(A (&o)[V], A ma, A mb, A cx, A cy, const T *pl, int i, int j, int nx, int ny)
 {
-    const int c = blk.x * blockDim.x + threadIdx.x;
-    if (c >= a.nx * a.ny) return;
-    const int i = c % a.nx, j = c / a.nx;
+    const long long c = static_cast<long long>(j) * nx + i;
+    A v[V];
+    vld<T, A, V>(v, pl + c, V);
+    if (ma == A(0)) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) o[e] = mb * v[e];
+        return;
+    }
+    A yl[V], yr[V];
+    vld<T, A, V>(yl, pl + c - nx, j > 0 ? V : 0);
+    vld<T, A, V>(yr, pl + c + nx, j < ny - 1 ? V : 0);
+    const A xl0 = i > 0 ? static_cast<A>(ldv(pl + c - 1)) : A(0);
+    const A xrv = i + V < nx ? static_cast<A>(ldv(pl + c + V)) : A(0);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const A xl = e > 0 ? v[e - 1] : xl0;
+        const A xr = e < V - 1 ? v[e + 1] : xrv;
+        const A dx = A(2) * v[e] - xl - xr, dy = A(2) * v[e] - yl[e] - yr[e];
+        o[e] = fmadd(ma, fmadd(cx, dx, cy * dy), mb * v[e]);
+    }
+}
+
+template <typename T, typename A, int V>
+__device__ __forceinline__ void k_resid3v_body(const Resid3Args<T, A> &a, const Blk &blk)
+{
+    const long long c = (static_cast<long long>(blk.x) * blockDim.x + threadIdx.x) * V;
+    const long long pl = static_cast<long long>(a.nx) * a.ny;
+    if (c >= pl) return;
+    const int i = static_cast<int>(c % a.nx), j = static_cast<int>(c / a.nx);
     const int p = blk.y, r = blk.z;
     const int k = p * a.kmul + a.koff;
-    const A v = resid3_point<T, A>(a.x + r * a.xrs, a.b + r * a.brs, a.pc, a.cx, a.cy, a.nx, a.ny, a.nz, k, i, j,
-                                   a.self_zero != 0);
-    stv(a.r + r * a.rrs + p * a.rps + c, v);
+    const T *x = a.x + r * a.xrs;
+    A v[V], o[V];
+    vld<T, A, V>(v, a.b + r * a.brs + k * pl + c, V);
+    const PlaneCoef<A> ck = a.pc[k];
+    if (!a.self_zero) {
+        plane_op_v<T, A, V>(o, ck.ca, ck.cb, a.cx, a.cy, x + k * pl, i, j, a.nx, a.ny);
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] -= o[e];
+    }
+    if (k > 0) {
+        const PlaneCoef<A> cm = a.pc[k - 1];
+        plane_op_v<T, A, V>(o, cm.ua, cm.ub, a.cx, a.cy, x + (k - 1) * pl, i, j, a.nx, a.ny);
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] -= o[e];
+    }
+    if (k < a.nz - 1) {
+        plane_op_v<T, A, V>(o, ck.ua, ck.ub, a.cx, a.cy, x + (k + 1) * pl, i, j, a.nx, a.ny);
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] -= o[e];
+    }
+    vst<T, A, V>(a.r + r * a.rrs + p * a.rps + c, v, V);
 }
 
-template <typename T, typename A>
-__global__ __launch_bounds__(256) void k_resid3(Resid3Args<T, A> a)
+template <typename T, typename A, int V>
+__global__ __launch_bounds__(256) void k_resid3v(Resid3Args<T, A> a)
 {
-    k_resid3_body<T, A>(a, SMG_BLK_XCD);
+    k_resid3v_body<T, A, V>(a, SMG_BLK_XCD);
 }
 
-template <typename T, typename A>
-__global__ __launch_bounds__(256) void k_resid3_grp(const GroupEntry *tab, int n)
+template <typename T, typename A, int V>
+__global__ __launch_bounds__(256) void k_resid3v_grp(const GroupEntry *tab, int n)
 {
     const Resid3Args<T, A> *a;
     Blk blk;
     if (!group_entry(tab, n, a, blk)) return;
-    k_resid3_body<T, A>(*a, blk);
+    k_resid3v_body<T, A, V>(*a, blk);
 }
 
 template <typename T, typename A>
@@ -404,14 +455,18 @@ __global__ void k_convert_out(const T *src, long long lds, double *dst, long lon
 constexpr int kRTX = 64, kRTY = 4, kRThreads = kRTX * kRTY;
 static_assert(2 * (kRTX + kRTY) <= kRThreads, "every halo point needs a thread");
 
-template <typename T, typename A>
+// V: consecutive points per thread along x (the tile is 64 V wide); the
+// top and bottom halo rows are read V-wide like the tile, the side columns
+// point by point.  The arithmetic per point does not depend on V.
+template <typename T, typename A, int V>
 __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A> &a, const Blk &blk)
 {
-    __shared__ A tiles[2][(kRTY + 2) * (kRTX + 2)];   // alternate planes: one barrier per plane
+    constexpr int TW = kRTX * V, TS = TW + 2;   // tile width and LDS row stride (with halo)
+    __shared__ A tiles[2][(kRTY + 2) * TS];      // alternate planes: one barrier per plane
     const int tx = threadIdx.x % kRTX, ty = threadIdx.x / kRTX;
-    const int i = blk.x * kRTX + tx, j = blk.y * kRTY + ty;
+    const int i = blk.x * TW + tx * V, j = blk.y * kRTY + ty;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const bool in = i < nx && j < ny;
+    const int nok = j < ny && i < nx ? min(V, nx - i) : 0;
     const long long pl = static_cast<long long>(nx) * ny;
     const long long c2 = static_cast<long long>(j) * nx + i;
     const int r = blk.z / ((a.nzc + a.kchunk - 1) / a.kchunk);
@@ -419,49 +474,71 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
     const int K1 = min(a.nzc, K0 + a.kchunk);
     const T *x = a.x + r * a.xrs;
     const T *b = a.b + r * a.brs;
-    // this thread's halo point, if any
-    int hy = -1, hx = -1;
+    // this thread's halo points, if any: V of the top or bottom row, or one
+    // of the side columns
+    int hy = -1, hx = -1, hw = 0;
     const int t = threadIdx.x;
-    if (t < kRTX) { hy = 0; hx = t + 1; }
-    else if (t < 2 * kRTX) { hy = kRTY + 1; hx = t - kRTX + 1; }
-    else if (t < 2 * kRTX + kRTY) { hy = t - 2 * kRTX + 1; hx = 0; }
-    else if (t < 2 * kRTX + 2 * kRTY) { hy = t - 2 * kRTX - kRTY + 1; hx = kRTX + 1; }
-    const int hi = blk.x * kRTX + hx - 1, hj = blk.y * kRTY + hy - 1;
-    const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    if (t < kRTX) { hy = 0; hx = t * V + 1; hw = V; }
+    else if (t < 2 * kRTX) { hy = kRTY + 1; hx = (t - kRTX) * V + 1; hw = V; }
+    else if (t < 2 * kRTX + kRTY) { hy = t - 2 * kRTX + 1; hx = 0; hw = 1; }
+    else if (t < 2 * kRTX + 2 * kRTY) { hy = t - 2 * kRTX - kRTY + 1; hx = TW + 1; hw = 1; }
+    const int hi = blk.x * TW + hx - 1, hj = blk.y * kRTY + hy - 1;
+    const int hn = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny ? min(hw, nx - hi) : 0;
     const long long hc2 = static_cast<long long>(hj) * nx + hi;
-    const int cc = (ty + 1) * (kRTX + 2) + tx + 1;
+    const int cc = (ty + 1) * TS + tx * V + 1;
     const A cx = a.cx, cy = a.cy;
     // planes this block reads: x up to 2 K1 + 1, b up to 2 K1
     const int kx_last = min(nz - 1, 2 * K1 + 1), kb_last = min(nz - 1, 2 * K1);
-    // the next kPre planes of x (centre and halo point) and of b are loaded
+    // the next kPre planes of x (centre and halo points) and of b are loaded
     // ahead into small register rings, so that a step waits on a load issued
     // kPre steps before rather than on its own (two: a deeper ring costs
     // registers, and eight waves per SIMD hide more than the ring does)
     constexpr int kPre = 2;
-    auto load_x = [&](int k, A &xc, A &xh) {
+    // loaded planes are held as stored (BF16 packed) until a step uses them
+    auto load_x = [&](int k, Held<T, V> &xc, Held<T, V> &xh) {
         const bool live = k >= 0 && k <= kx_last && !a.x_zero;
-        xc = (in && live) ? static_cast<A>(ldv(x + k * pl + c2)) : A(0);
-        xh = (hin && live) ? static_cast<A>(ldv(x + k * pl + hc2)) : A(0);
+        hld<T, V>(xc, x + k * pl + c2, live ? nok : 0);
+        if constexpr (V == 1) {
+            hld<T, V>(xh, x + k * pl + hc2, live ? hn : 0);
+        } else {
+            if (hw == V)
+                hld<T, V>(xh, x + k * pl + hc2, live ? hn : 0);
+            else   // a side-column point: element 0 only
+                xh.p.e[0] = live && hn ? x[k * pl + hc2] : T{};
+        }
     };
-    auto load_b = [&](int k) { return in && k <= kb_last ? static_cast<A>(ldv(b + k * pl + c2)) : A(0); };
-    // window of planes kl-2, kl-1, kl: x and T2 x at this point
-    A xw0 = 0, xw1 = 0, xw2 = 0, tw0 = 0, tw1 = 0, tw2 = 0;
+    auto load_b = [&](int k, Held<T, V> &v) { hld<T, V>(v, b + k * pl + c2, k <= kb_last ? nok : 0); };
+    // window of planes kl-2, kl-1, kl: x and T2 x at this thread's points
+    A xw0[V], xw1[V], xw2[V], tw0[V], tw1[V], tw2[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) xw0[e] = xw1[e] = xw2[e] = tw0[e] = tw1[e] = tw2[e] = A(0);
     int kl = 2 * K0 - 2;   // next advance takes plane kl + 1
     int kb = 2 * K0;       // next residual plane
-    A xq[kPre], hq[kPre], bq[kPre];
+    Held<T, V> xq[kPre], hq[kPre], bq[kPre];
 #pragma unroll
     for (int q = 0; q < kPre; ++q) {
+        hq[q].p = VecPack<T, V>{};
         load_x(kl + 1 + q, xq[q], hq[q]);
-        bq[q] = load_b(kb + q);
+        load_b(kb + q, bq[q]);
     }
     int buf = 0;
     auto advance = [&]() {
         ++kl;
-        const A xc = xq[0];
+        A xc[V], xh[V];
+        unpack<T, A, V>(xc, xq[0]);
+        unpack<T, A, V>(xh, hq[0]);
         A *tile = tiles[buf];
         buf ^= 1;
-        tile[cc] = xc;
-        if (hy >= 0) tile[hy * (kRTX + 2) + hx] = hq[0];
+#pragma unroll
+        for (int e = 0; e < V; ++e) tile[cc + e] = xc[e];
+        if (hy >= 0) {
+            if (V > 1 && hw == V) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) tile[hy * TS + hx + e] = xh[e];
+            } else {
+                tile[hy * TS + hx] = xh[0];
+            }
+        }
 #pragma unroll
         for (int q = 0; q + 1 < kPre; ++q) {
             xq[q] = xq[q + 1];
@@ -471,49 +548,68 @@ __device__ __forceinline__ void k_restrict3_march_body(const Restrict3Args<T, A>
         // a tile is rewritten two planes later, after the next plane's barrier:
         // every read of it is done by then
         __syncthreads();
-        const A t2 = cx * (A(2) * xc - tile[cc - 1] - tile[cc + 1]) +
-                     cy * (A(2) * xc - tile[cc - (kRTX + 2)] - tile[cc + (kRTX + 2)]);
-        xw0 = xw1; xw1 = xw2; xw2 = xc;
-        tw0 = tw1; tw1 = tw2; tw2 = t2;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int ce = cc + e;
+            const A dx = A(2) * xc[e] - tile[ce - 1] - tile[ce + 1];
+            const A dy = A(2) * xc[e] - tile[ce - TS] - tile[ce + TS];
+            const A t2 = fmadd(cx, dx, cy * dy);
+            xw0[e] = xw1[e]; xw1[e] = xw2[e]; xw2[e] = xc[e];
+            tw0[e] = tw1[e]; tw1[e] = tw2[e]; tw2[e] = t2;
+        }
     };
     // residual of fine plane k = kb (0 <= k < nz); needs planes k-1, k, k+1 loaded
-    auto resid = [&](int k) {
+    auto resid = [&](int k, A (&v)[V]) {
         while (kl < k + 1) advance();
-        A v = bq[0];
+        unpack<T, A, V>(v, bq[0]);
 #pragma unroll
         for (int q = 0; q + 1 < kPre; ++q) bq[q] = bq[q + 1];
-        bq[kPre - 1] = load_b(++kb + kPre - 1);
+        load_b(++kb + kPre - 1, bq[kPre - 1]);
         const PlaneCoef<A> ck = a.pc[k];
-        v -= ck.ca * tw1 + ck.cb * xw1;
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] -= fmadd(ck.ca, tw1[e], ck.cb * xw1[e]);
         if (k > 0) {
             const PlaneCoef<A> cm = a.pc[k - 1];
-            v -= cm.ua * tw0 + cm.ub * xw0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[e] -= fmadd(cm.ua, tw0[e], cm.ub * xw0[e]);
         }
-        if (k < nz - 1) v -= ck.ua * tw2 + ck.ub * xw2;
-        return v;
+        if (k < nz - 1) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[e] -= fmadd(ck.ua, tw2[e], ck.ub * xw2[e]);
+        }
     };
-    A r_even = resid(2 * K0);
+    A r_even[V], r_odd[V], r_next[V], out[V];
+    resid(2 * K0, r_even);
     for (int K = K0; K < K1; ++K) {
-        const A r_odd = resid(2 * K + 1);
-        const A r_next = 2 * K + 2 < nz ? resid(2 * K + 2) : A(0);
-        if (in) stv(a.bc + r * a.crs + K * pl + c2, A(0.5) * r_even + r_odd + A(0.5) * r_next);
-        r_even = r_next;
+        resid(2 * K + 1, r_odd);
+        if (2 * K + 2 < nz) {
+            resid(2 * K + 2, r_next);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) r_next[e] = A(0);
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            out[e] = fmadd(A(0.5), r_next[e], fmadd(A(0.5), r_even[e], r_odd[e]));
+            r_even[e] = r_next[e];
+        }
+        vst<T, A, V>(a.bc + r * a.crs + K * pl + c2, out, nok);
     }
 }
 
-template <typename T, typename A>
+template <typename T, typename A, int V>
 __global__ __launch_bounds__(kRThreads) void k_restrict3_march(Restrict3Args<T, A> a)
 {
-    k_restrict3_march_body<T, A>(a, SMG_BLK_XCD);
+    k_restrict3_march_body<T, A, V>(a, SMG_BLK_XCD);
 }
 
-template <typename T, typename A>
+template <typename T, typename A, int V>
 __global__ __launch_bounds__(kRThreads) void k_restrict3_march_grp(const GroupEntry *tab, int n)
 {
     const Restrict3Args<T, A> *a;
     Blk blk;
     if (!group_entry(tab, n, a, blk)) return;
-    k_restrict3_march_body<T, A>(*a, blk);
+    k_restrict3_march_body<T, A, V>(*a, blk);
 }
 
 inline unsigned blocks_for(long long n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
@@ -566,8 +662,19 @@ template <typename T, typename A>
 void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     if (a.np == 0) return;
+    constexpr int V = stream_vec<T>();
+    if (V > 1 && a.vmax != 1) {
+        auto aligned = [](const void *q) { return reinterpret_cast<uintptr_t>(q) % (V * sizeof(T)) == 0; };
+        if (a.nx % V == 0 && a.xrs % V == 0 && a.brs % V == 0 && a.rrs % V == 0 && a.rps % V == 0 &&
+            aligned(a.x) && aligned(a.b) && aligned(a.r)) {
+            const long long pts = static_cast<long long>(a.nx) * a.ny / V;
+            const dim3 grid(blocks_for(pts, 256), a.np, a.nrhs);
+            SMG_LAUNCH_G(ev, (k_resid3v<T, A, V>), (k_resid3v_grp<T, A, V>), grid, dim3(256), 0, st, a);
+            return;
+        }
+    }
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.np, a.nrhs);
-    SMG_LAUNCH_G(ev, (k_resid3<T, A>), (k_resid3_grp<T, A>), grid, dim3(256), 0, st, a);
+    SMG_LAUNCH_G(ev, (k_resid3v<T, A, 1>), (k_resid3v_grp<T, A, 1>), grid, dim3(256), 0, st, a);
 }
 
 template <typename T, typename A>
@@ -578,20 +685,38 @@ void launch_correct3(const Correct3Args<T, A> &a, hipStream_t st, const LaunchEv
     SMG_LAUNCH(ev, (k_correct3<T, A>), grid, dim3(256), 0, st, a);
 }
 
+template <typename T, typename A, int V>
+void launch_restrict3_march(const Restrict3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
+{
+    const int gx = (a.nx + kRTX * V - 1) / (kRTX * V), gy = (a.ny + kRTY - 1) / kRTY;
+    // enough blocks to fill the chip; each marches kchunk coarse planes
+    int nzb = 2048 / (gx * gy * a.nrhs);
+    nzb = nzb < 1 ? 1 : (nzb > a.nzc ? a.nzc : nzb);
+    const int kchunk = (a.nzc + nzb - 1) / nzb;
+    nzb = (a.nzc + kchunk - 1) / kchunk;
+    const dim3 grid(gx, gy, nzb * a.nrhs);
+    Restrict3Args<T, A> am = a;
+    am.kchunk = kchunk;
+    SMG_LAUNCH_G(ev, (k_restrict3_march<T, A, V>), (k_restrict3_march_grp<T, A, V>), grid, dim3(kRThreads), 0, st,
+                 am);
+}
+
 template <typename T, typename A>
 void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
-    const int gx = (a.nx + kRTX - 1) / kRTX, gy = (a.ny + kRTY - 1) / kRTY;
     if (a.nzc >= 2) {
-        // enough blocks to fill the chip; each marches kchunk coarse planes
-        int nzb = 2048 / (gx * gy * a.nrhs);
-        nzb = nzb < 1 ? 1 : (nzb > a.nzc ? a.nzc : nzb);
-        const int kchunk = (a.nzc + nzb - 1) / nzb;
-        nzb = (a.nzc + kchunk - 1) / kchunk;
-        const dim3 grid(gx, gy, nzb * a.nrhs);
-        Restrict3Args<T, A> am = a;
-        am.kchunk = kchunk;
-        SMG_LAUNCH_G(ev, (k_restrict3_march<T, A>), (k_restrict3_march_grp<T, A>), grid, dim3(kRThreads), 0, st, am);
+        int v = a.vmax == 1 ? 1 : tile_vec<T>(a.nx);
+        auto aligned = [&](const void *q) { return reinterpret_cast<uintptr_t>(q) % (v * sizeof(T)) == 0; };
+        if (v > 1 && !(a.xrs % v == 0 && a.brs % v == 0 && a.crs % v == 0 && aligned(a.x) && aligned(a.b) &&
+                       aligned(a.bc)))
+            v = 1;
+        if (v == 4) {
+            if constexpr (stream_vec<T>() >= 4) launch_restrict3_march<T, A, 4>(a, st, ev);
+        } else if (v == 2) {
+            if constexpr (stream_vec<T>() >= 2) launch_restrict3_march<T, A, 2>(a, st, ev);
+        } else {
+            launch_restrict3_march<T, A, 1>(a, st, ev);
+        }
         return;
     }
     const dim3 grid(blocks_for(static_cast<long long>(a.nx) * a.ny, 256), a.nzc, a.nrhs);

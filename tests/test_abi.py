@@ -51,7 +51,9 @@ def test_workspace_query_and_invalid_arguments():
                 S.smg_grid(4, 4, 4, 0.0, 1, 1), S.smg_grid(4, 4, 4, 1, float("nan"), 1)]:
         assert _ws(bad, o)[0] == -1
     for bado in [S.smg_opts(-1, 0, -1, -1, 0, 0, 0), S.smg_opts(1, 9, -1, -1, 0, 0, 0),
-                 S.smg_opts(1, 0, -2, -1, 0, 0, 0), S.smg_opts(1, 0, -1, -1, 2, 0, 0), S.smg_opts(1, 0, -1, -1, 0, 3, 0), S.smg_opts(1, 0, -1, -1, 0, 0, 2)]:
+                 S.smg_opts(1, 0, -2, -1, 0, 0, 0), S.smg_opts(1, 0, -1, -1, 2, 0, 0),
+                 S.smg_opts(1, 0, -1, -1, 0, 3, 0), S.smg_opts(1, 0, -1, -1, 0, 0, 3),
+                 S.smg_opts(1, 0, -1, -1, 0, 0, -1)]:
         assert _ws(g, bado)[0] == -1
     assert _ws(g, o, 0)[0] == -1
 
