@@ -160,9 +160,9 @@ constexpr int stream_vec() { return static_cast<int>(8 / sizeof(T)); }
 // that divides nx and leaves at most an eighth of the tiles' points idle
 // (wider tiles with idle lanes cost more in registers than they save).
 template <typename T>
-inline int tile_vec(int nx)
+inline int tile_vec(int nx, int widest = stream_vec<T>())
 {
-    for (int v = stream_vec<T>(); v > 1; v /= 2) {
+    for (int v = widest; v > 1; v /= 2) {
         if (nx % v != 0) continue;
         const int w = 64 * v, waste = (nx + w - 1) / w * w - nx;
         if (8 * waste <= nx) return v;

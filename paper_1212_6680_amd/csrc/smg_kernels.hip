@@ -662,7 +662,8 @@ template <typename T, typename A>
 void launch_resid3(const Resid3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     if (a.np == 0) return;
-    constexpr int V = stream_vec<T>();
+    // few registers per point: 16-byte accesses in every precision
+    constexpr int V = static_cast<int>(16 / sizeof(T));
     if (V > 1 && a.vmax != 1) {
         auto aligned = [](const void *q) { return reinterpret_cast<uintptr_t>(q) % (V * sizeof(T)) == 0; };
         if (a.nx % V == 0 && a.xrs % V == 0 && a.brs % V == 0 && a.rrs % V == 0 && a.rps % V == 0 &&
@@ -705,15 +706,17 @@ template <typename T, typename A>
 void launch_restrict3(const Restrict3Args<T, A> &a, hipStream_t st, const LaunchEv &ev)
 {
     if (a.nzc >= 2) {
-        int v = a.vmax == 1 ? 1 : tile_vec<T>(a.nx);
+        // FP64 rows take 16-byte accesses (two points), narrower types 8 bytes
+        constexpr int kWidest = sizeof(T) == 8 ? 2 : stream_vec<T>();
+        int v = a.vmax == 1 ? 1 : tile_vec<T>(a.nx, kWidest);
         auto aligned = [&](const void *q) { return reinterpret_cast<uintptr_t>(q) % (v * sizeof(T)) == 0; };
         if (v > 1 && !(a.xrs % v == 0 && a.brs % v == 0 && a.crs % v == 0 && aligned(a.x) && aligned(a.b) &&
                        aligned(a.bc)))
             v = 1;
         if (v == 4) {
-            if constexpr (stream_vec<T>() >= 4) launch_restrict3_march<T, A, 4>(a, st, ev);
+            if constexpr (kWidest >= 4) launch_restrict3_march<T, A, 4>(a, st, ev);
         } else if (v == 2) {
-            if constexpr (stream_vec<T>() >= 2) launch_restrict3_march<T, A, 2>(a, st, ev);
+            if constexpr (kWidest >= 2) launch_restrict3_march<T, A, 2>(a, st, ev);
         } else {
             launch_restrict3_march<T, A, 1>(a, st, ev);
         }
