@@ -266,13 +266,18 @@ struct Lines {                    // a 2D level of all planes of a 3D level
 };
 
 // (Q x)_j[i] on line j of a plane's 2D level: L_j x_j + V_{j-1}^T x_{j-1} + V_j x_{j+1}
+// (OWN false: without L_j x_j, for a line whose x is still zero)
+template <bool OWN = true>
 __device__ inline double q_line(const Lines &Q, long long cb, const double *x, long long xb, int j, int i)
 {
     const int nx = Q.nx;
     const long long c = cb + static_cast<long long>(j) * nx + i, xc = xb + static_cast<long long>(j) * nx + i;
-    double v = Q.lc[c] * x[xc];
-    if (i > 0) v += Q.le[c - 1] * x[xc - 1];
-    if (i + 1 < nx) v += Q.le[c] * x[xc + 1];
+    double v = 0.0;
+    if constexpr (OWN) {
+        v = Q.lc[c] * x[xc];
+        if (i > 0) v += Q.le[c - 1] * x[xc - 1];
+        if (i + 1 < nx) v += Q.le[c] * x[xc + 1];
+    }
     if (j > 0) {
         const long long d = c - nx, xd = xc - nx;
         v += Q.vc[d] * x[xd];
@@ -310,9 +315,13 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Half-sweeps of a 2D level whose x starts at zero (no fill needed): the
+// first colour's lines solve L_j x_j = b_j (MODE 1), the second colour's
+// L_j x_j = b_j - V x of the neighbours (MODE 2); both assign x.  MODE 0 is
+// the correction x_j += L_j^{-1} (b - Q x)_j.
 // One line of a zebra half-sweep by one wave (the three phases above);
 // lds: this wave's 3 * 64 * relax_stride(E) doubles.
-template <int E>
+template <int E, int MODE>
 __device__ inline void relax_line(const Lines &Q, const double *b, double *x, long long cb, long long xb, int j,
                                   double *lds)
 {
@@ -329,7 +338,8 @@ __device__ inline void relax_line(const Lines &Q, const double *b, double *x, lo
         double al = 0.0, be = 0.0, gi = 0.0;
         if (i < nx) {
             const double im = Q.invm[cl + i];
-            be = (b[xl + i] - q_line(Q, cb, x, xb, j, i)) * im;
+            const double q = MODE == 1 ? 0.0 : MODE == 2 ? q_line<false>(Q, cb, x, xb, j, i) : q_line(Q, cb, x, xb, j, i);
+            be = (b[xl + i] - q) * im;
             al = i > 0 ? -Q.le[cl + i - 1] * im : 0.0;
             gi = Q.g[cl + i];
         }
@@ -391,12 +401,17 @@ __device__ inline void relax_line(const Lines &Q, const double *b, double *x, lo
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int i = t * 64 + lane;
-        if (i < nx) x[xl + i] += Rb[pos(i)];
+        if (i < nx) {
+            if (MODE == 0)
+                x[xl + i] += Rb[pos(i)];
+            else
+                x[xl + i] = Rb[pos(i)];
+        }
     }
     wave_sync();   // the next line of this wave reuses the LDS rows
 }
 
-template <int E>
+template <int E, int MODE>
 __global__ __launch_bounds__(kB) void k_var_relax(Lines Q, const double *b, double *x, int np, int colour, int k0,
                                                   int ks)
 {
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(kB) void k_var_relax(Lines Q, const double *b, doub
     const int j = colour + 2 * static_cast<int>(wv % nlc);
     const long long cb = static_cast<long long>(k0 + ks * pb) * Q.ny * Q.nx;
     const long long xb = static_cast<long long>(pb) * Q.ny * Q.nx;
-    relax_line<E>(Q, b, x, cb, xb, j, lds + w * 3 * 64 * relax_stride(E));
+    relax_line<E, MODE>(Q, b, x, cb, xb, j, lds + w * 3 * 64 * relax_stride(E));
 }
 
 // b_c = P^T (b - Q x) for np planes: coarse line J takes fine line 2J+1,
@@ -788,7 +803,8 @@ void build(VarHier &H, const double *diag, const double *ax, const double *ay, c
 // V-cycle schedule (host)
 // ---------------------------------------------------------------------------
 
-void relax(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, hipStream_t st)
+template <int MODE>
+void relax_mode(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, hipStream_t st)
 {
     const Lines Q = lines_of(H, l, l2);
     const long long waves = static_cast<long long>((Q.ny - colour + 1) / 2) * np;
@@ -799,15 +815,26 @@ void relax(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, 
     const int E = (H.nx + 63) / 64;
     const size_t lds = static_cast<size_t>(kRelaxWaves) * 3 * 64 * relax_stride(E) * sizeof(double);
     switch (E) {
-    case 1: hipLaunchKernelGGL(k_var_relax<1>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
-    case 2: hipLaunchKernelGGL(k_var_relax<2>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
-    case 3: hipLaunchKernelGGL(k_var_relax<3>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
-    case 4: hipLaunchKernelGGL(k_var_relax<4>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
-    case 5: hipLaunchKernelGGL(k_var_relax<5>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
-    case 6: hipLaunchKernelGGL(k_var_relax<6>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
-    case 7: hipLaunchKernelGGL(k_var_relax<7>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
-    default: hipLaunchKernelGGL(k_var_relax<8>, grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 1: hipLaunchKernelGGL((k_var_relax<1, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 2: hipLaunchKernelGGL((k_var_relax<2, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 3: hipLaunchKernelGGL((k_var_relax<3, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 4: hipLaunchKernelGGL((k_var_relax<4, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 5: hipLaunchKernelGGL((k_var_relax<5, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 6: hipLaunchKernelGGL((k_var_relax<6, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    case 7: hipLaunchKernelGGL((k_var_relax<7, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
+    default: hipLaunchKernelGGL((k_var_relax<8, MODE>), grid, block, lds, st, Q, b, x, np, colour, k0, ks); break;
     }
+}
+
+// mode: 0 correction; 1, 2 the two half-sweeps from a zero x (see relax_line)
+void relax(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, hipStream_t st, int mode = 0)
+{
+    if (mode == 1)
+        relax_mode<1>(H, l, l2, np, colour, k0, ks, st);
+    else if (mode == 2)
+        relax_mode<2>(H, l, l2, np, colour, k0, ks, st);
+    else
+        relax_mode<0>(H, l, l2, np, colour, k0, ks, st);
 }
 
 // One 2D V-cycle, for np planes at once (plane pb of the batch is plane
@@ -817,15 +844,17 @@ void vcycle2(const VarHier &H, int l, int l2, int np, int k0, int ks, hipStream_
     const int ny = H.ny2[l2];
     const long long n2 = static_cast<long long>(np) * ny * H.nx;
     double *x = H.at<double>(H.bx2[l2]);
-    launch_fill(x, 0.0, static_cast<size_t>(n2), st);
     if (ny == 1) {   // coarsest 2D level: one exact line solve
-        relax(H, l, l2, np, 0, k0, ks, st);
+        relax(H, l, l2, np, 0, k0, ks, st, 1);
         return;
     }
+    // x starts at zero: the first sweep assigns it (without pre-smoothing
+    // the prolongation adds to a zeroed x)
+    if (H.ipre == 0) launch_fill(x, 0.0, static_cast<size_t>(n2), st);
     const int first = H.order == 0 ? 0 : 1, second = 1 - first;
     for (int t = 0; t < H.ipre; ++t) {
-        relax(H, l, l2, np, first, k0, ks, st);
-        relax(H, l, l2, np, second, k0, ks, st);
+        relax(H, l, l2, np, first, k0, ks, st, t == 0 ? 1 : 0);
+        relax(H, l, l2, np, second, k0, ks, st, t == 0 ? 2 : 0);
     }
     const VarLevel3 &L = H.lev[l];
     const Lines Q = lines_of(H, l, l2);
