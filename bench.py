@@ -189,8 +189,16 @@ def lobpcg_configs(torch, dev):
         k = 3 * (m + guard)
         gms = G.profile_gram(m + guard, k, reps=5)
         tf = float(n ** 3) * k * (k + 1) / (gms * 1e-3) / 1e12
+        # the product reads the N x k basis once (8 N k bytes) for N k (k+1)
+        # flops: (k+1)/8 flop per byte against the machine balance 78.6 TFLOP/s
+        # / 8 TB/s, so narrow bases are bound by HBM and wide ones by the MFMAs
+        gbs = 8.0 * float(n ** 3) * k / (gms * 1e-3) / 1e9
+        bound = "hbm" if (k + 1) / 8.0 < 78.6e12 / (HBM_PEAK_GBS * 1e9) else "mfma"
         res[f"lobpcg_128_m{m}"]["gram"] = {"k": k, "ms": gms, "tflops": tf, "peak_tflops": 78.6,
-                                           "mfma_frac": tf / 78.6, "flops": "N k (k+1) (symmetric)"}
+                                           "mfma_frac": tf / 78.6, "hbm_gbs": gbs,
+                                           "hbm_frac": gbs / HBM_PEAK_GBS, "bound": bound,
+                                           "frac": gbs / HBM_PEAK_GBS if bound == "hbm" else tf / 78.6,
+                                           "flops": "N k (k+1) (symmetric)", "bytes": "8 N k"}
         del G, X
         torch.cuda.empty_cache()
     return res
