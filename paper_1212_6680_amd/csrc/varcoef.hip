@@ -469,6 +469,101 @@ __global__ void k_var_prolong2(const double *ydn, const double *yup, int nx, int
     x[e] += v;
 }
 
+// The upward half of a 2D cycle without post-smoothing in one pass: from the
+// coarsest level, v_l = x_l + P_l v_{l+1} with the per-point weights of
+// k_var_prolong2 (the same arithmetic per point), then the 3D correction of
+// k_var_correct3 (x_k += v_0 on plane k = k0 + ks*pb; assign: x_k = v_0).
+// A block owns 64 columns and a run of 32 fine lines of one plane; each
+// coarser level's window of lines is staged in LDS.
+constexpr int kVcCols = 64, kVcRun = 32, kVcWin = 24, kVcMaxLev = 16;
+
+struct VChainArgs {
+    const double *x[kVcMaxLev];                        // bx2 of each 2D level
+    const double *ydn[kVcMaxLev], *yup[kVcMaxLev];      // weights of each 2D level
+    int ny2[kVcMaxLev];
+    int nl, nx, np, k0, ks, assign;
+    double *x3;                                         // 3D x of the level
+    long long m;                                        // points per plane
+};
+
+struct VWin {
+    int lo, hi;
+};
+
+__device__ inline VWin vc_coarser(VWin f, int nc)
+{
+    VWin c;
+    c.lo = f.lo - 1 < 0 ? 0 : (f.lo - 1) >> 1;
+    c.hi = f.hi >> 1;
+    if (c.hi > nc - 1) c.hi = nc - 1;
+    return c;
+}
+
+// P v_c at fine line jj, column i (weights at c), window wc of the coarse level
+__device__ inline double vc_prolong(const double *vc, VWin wc, int jj, int nyc, int col, const double *ydn,
+                                    const double *yup, long long c)
+{
+    if (jj & 1) return vc[((jj - 1) / 2 - wc.lo) * kVcCols + col];
+    double v = 0.0;
+    if (jj / 2 - 1 >= 0) v += ydn[c] * vc[(jj / 2 - 1 - wc.lo) * kVcCols + col];
+    if (jj / 2 < nyc) v += yup[c] * vc[(jj / 2 - wc.lo) * kVcCols + col];
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_var_chain2(VChainArgs a)
+{
+    __shared__ double vs[2][kVcWin * kVcCols];
+    const int nx = a.nx;
+    const int ncol = (nx + kVcCols - 1) / kVcCols;
+    const int nrun = (a.ny2[0] + kVcRun - 1) / kVcRun;
+    int bid = blockIdx.x;
+    const int ct = bid % ncol;
+    bid /= ncol;
+    const int rt = bid % nrun;
+    const int pb = bid / nrun;
+    const int col = threadIdx.x & (kVcCols - 1), row0 = threadIdx.x >> 6;   // 4 rows of 64
+    const int i = ct * kVcCols + col;
+    const bool in = i < nx;
+    const int k = a.k0 + a.ks * pb;
+    const VWin w0{rt * kVcRun, min(a.ny2[0], rt * kVcRun + kVcRun) - 1};
+    auto win = [&](int l) {
+        VWin wv = w0;
+        for (int q = 0; q < l; ++q) wv = vc_coarser(wv, a.ny2[q + 1]);
+        return wv;
+    };
+    // x of level l at line jj of plane pb (batch-packed), weights at plane k
+    auto xrow = [&](int l, int jj) {
+        return in ? a.x[l][(static_cast<long long>(pb) * a.ny2[l] + jj) * nx + i] : 0.0;
+    };
+    auto wc_of = [&](int l, int jj) { return (static_cast<long long>(k) * a.ny2[l] + jj) * nx + i; };
+    int cur = 0;
+    for (int l = a.nl - 1; l >= 1; --l) {
+        const VWin wl = win(l);
+        if (l == a.nl - 1) {   // the coarsest level as it is
+            for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4) vs[cur][(jj - wl.lo) * kVcCols + col] = xrow(l, jj);
+        } else {
+            const VWin wc = win(l + 1);
+            for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4) {
+                const double s = in ? vc_prolong(vs[cur], wc, jj, a.ny2[l + 1], col, a.ydn[l], a.yup[l], wc_of(l, jj))
+                                    : 0.0;
+                vs[cur ^ 1][(jj - wl.lo) * kVcCols + col] = xrow(l, jj) + s;
+            }
+            cur ^= 1;
+        }
+        __syncthreads();
+    }
+    if (!in) return;   // after the last barrier
+    const VWin wc = win(1);
+    for (int jj = w0.lo + row0; jj <= w0.hi; jj += 4) {
+        const double v = xrow(0, jj) + vc_prolong(vs[cur], wc, jj, a.ny2[1], col, a.ydn[0], a.yup[0], wc_of(0, jj));
+        double *dst = a.x3 + k * a.m + static_cast<long long>(jj) * nx + i;
+        if (a.assign)
+            *dst = v;
+        else
+            *dst += v;
+    }
+}
+
 struct Planes {                   // a 3D level
     BlockOp op;
     int nz;
@@ -839,7 +934,9 @@ void relax(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, 
 
 // One 2D V-cycle, for np planes at once (plane pb of the batch is plane
 // k0 + ks*pb of 3D level l): right-hand sides in bb2[l2], result in bx2[l2].
-void vcycle2(const VarHier &H, int l, int l2, int np, int k0, int ks, hipStream_t st)
+// down_only: the downward half only (pre-smoothing, restriction, coarsest
+// solve); the prolongations are left to chain_up.
+void vcycle2(const VarHier &H, int l, int l2, int np, int k0, int ks, hipStream_t st, bool down_only = false)
 {
     const int ny = H.ny2[l2];
     const long long n2 = static_cast<long long>(np) * ny * H.nx;
@@ -861,7 +958,8 @@ void vcycle2(const VarHier &H, int l, int l2, int np, int k0, int ks, hipStream_
     const long long nc = static_cast<long long>(np) * H.ny2[l2 + 1] * H.nx;
     hipLaunchKernelGGL(k_var_restrict2, dim3(nblk(nc, kB)), dim3(kB), 0, st, Q, H.at<double>(L.ydn[l2]),
                        H.at<double>(L.yup[l2]), H.at<double>(H.bb2[l2]), x, H.at<double>(H.bb2[l2 + 1]), np, k0, ks);
-    vcycle2(H, l, l2 + 1, np, k0, ks, st);
+    vcycle2(H, l, l2 + 1, np, k0, ks, st, down_only);
+    if (down_only) return;
     hipLaunchKernelGGL(k_var_prolong2, dim3(nblk(n2, kB)), dim3(kB), 0, st, H.at<double>(L.ydn[l2]),
                        H.at<double>(L.yup[l2]), H.nx, ny, H.at<double>(H.bx2[l2 + 1]), x, np, k0, ks);
     for (int t = 0; t < H.ipost; ++t) {
@@ -869,6 +967,35 @@ void vcycle2(const VarHier &H, int l, int l2, int np, int k0, int ks, hipStream_
         relax(H, l, l2, np, first, k0, ks, st);
     }
 }
+
+// The upward half of the 2D cycles of np planes (after vcycle2 down_only)
+// and their 3D correction: x_k += v_0 (assign: x_k = v_0), k = k0 + ks*pb.
+void chain_up(const VarHier &H, int l, int np, int k0, int ks, double *x, int assign, hipStream_t st)
+{
+    const VarLevel3 &L = H.lev[l];
+    VChainArgs a{};
+    a.nl = static_cast<int>(H.ny2.size());
+    for (int l2 = 0; l2 < a.nl; ++l2) {
+        a.x[l2] = H.at<double>(H.bx2[l2]);
+        a.ny2[l2] = H.ny2[l2];
+        if (l2 + 1 < a.nl) {
+            a.ydn[l2] = H.at<double>(L.ydn[l2]);
+            a.yup[l2] = H.at<double>(L.yup[l2]);
+        }
+    }
+    a.nx = H.nx;
+    a.np = np;
+    a.k0 = k0;
+    a.ks = ks;
+    a.assign = assign;
+    a.x3 = x;
+    a.m = static_cast<long long>(H.nx) * H.ny;
+    const int ncol = (H.nx + kVcCols - 1) / kVcCols, nrun = (H.ny2[0] + kVcRun - 1) / kVcRun;
+    hipLaunchKernelGGL(k_var_chain2, dim3(static_cast<unsigned>(ncol) * nrun * np), dim3(256), 0, st, a);
+}
+
+// the chain replaces the per-level prolongations when nothing follows them
+bool chained(const VarHier &H) { return H.ipost == 0 && H.ny2.size() > 1 && H.ny2.size() <= kVcMaxLev; }
 
 // zebra half-sweep over the planes of one colour: x_k += V2_k((b - A x)_k)
 void sweep3(const VarHier &H, int l, int colour, const double *b, double *x, hipStream_t st)
@@ -879,6 +1006,11 @@ void sweep3(const VarHier &H, int l, int colour, const double *b, double *x, hip
     const long long m = static_cast<long long>(H.nx) * H.ny;
     hipLaunchKernelGGL(k_var_resid3, dim3(nblk(np * m, kB)), dim3(kB), 0, st, planes_of(H, l), b, x, colour,
                        H.at<double>(H.bb2[0]));
+    if (chained(H)) {
+        vcycle2(H, l, 0, np, colour, 2, st, true);
+        chain_up(H, l, np, colour, 2, x, 0, st);
+        return;
+    }
     vcycle2(H, l, 0, np, colour, 2, st);
     hipLaunchKernelGGL(k_var_correct3, dim3(nblk(np * m, kB)), dim3(kB), 0, st, x, H.at<double>(H.bx2[0]), m, L.nz,
                        colour);
@@ -890,6 +1022,11 @@ void vcycle3(const VarHier &H, int l, const double *b, double *x, hipStream_t st
     const long long m = static_cast<long long>(H.nx) * H.ny;
     if (L.nz == 1) {   // coarsest 3D level: one plane solve
         hipLaunchKernelGGL(k_var_copy, dim3(nblk(m, kB)), dim3(kB), 0, st, b, H.at<double>(H.bb2[0]), m);
+        if (chained(H)) {
+            vcycle2(H, l, 0, 1, 0, 1, st, true);
+            chain_up(H, l, 1, 0, 1, x, 1, st);
+            return;
+        }
         vcycle2(H, l, 0, 1, 0, 1, st);
         hipLaunchKernelGGL(k_var_copy, dim3(nblk(m, kB)), dim3(kB), 0, st, H.at<double>(H.bx2[0]), x, m);
         return;
