@@ -25,15 +25,17 @@
 //   * x-line solves use per-line LU factors of L_j.  One wave solves one line
 //     of up to 512 points: each lane holds E consecutive points, composes the
 //     affine maps of the forward (and then backward) Thomas recurrence over
-//     them, and the 64 lanes combine their maps by a shuffle scan.
+//     them, and the 64 lanes combine their maps by DPP scans.
 // Storage, all FP64, x fastest within a plane, planes (or lines) outermost.
 // The hierarchy lives in the caller's workspace; the host schedules one
-// launch per stage (no fused schedule), looping over right-hand sides.
+// launch per stage, looping over right-hand sides, except that without
+// post-smoothing the upward half of each 2D cycle is one chain kernel.
 #include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
 
+#include "line_ops.hpp"
 #include "smg_internal.h"
 
 namespace smg {
@@ -61,6 +63,7 @@ struct VarHier {
 namespace {
 
 constexpr int kB = 256;
+constexpr int kVcMaxLev = 16;   // 2D levels of the chained kernel (ny <= 2^15)
 
 inline unsigned nblk(long long n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
@@ -301,9 +304,9 @@ __device__ inline double q_line(const Lines &Q, long long cb, const double *x, l
 // g_i go to LDS.  Phase 2 (lane l owns the E consecutive points l*E ..): the
 // recurrence y_i = alpha_i y_{i-1} + beta_i and then u_i = y_i - g_i u_{i+1} as
 // affine maps composed over the lane's points and combined across lanes by
-// shuffle scans; u overwrites beta.  Phase 3 (coalesced): x += u.  LDS rows
-// are padded to an odd stride per chunk so that the chunk reads spread over
-// the banks.
+// DPP scans (scan_fwd, scan_bwd); u overwrites beta.  Phase 3 (coalesced):
+// x += u.  LDS rows are padded to an odd stride per chunk so that the chunk
+// reads spread over the banks.
 constexpr int kRelaxWaves = kB / 64;
 __host__ __device__ constexpr int relax_stride(int E) { return E % 2 ? E : E + 1; }
 
@@ -313,6 +316,77 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Scans of affine maps x -> A x + B across the 64 lanes of a wave on DPP, for
+// per-line coefficients (no precomputed products): within each 16-lane row
+// by shifts 1, 2, 4, 8 (lanes without a source compose with the identity),
+// then across rows.  Composition of a map with the one before it:
+// (A, B) o (A', B') = (A A', A B' + B).
+template <int CTRL, int ROWS>
+__device__ inline double dpp_rows_id(double old, double v)
+{
+    const long long o = __double_as_longlong(old), s = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(o), static_cast<int>(s), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(o >> 32), static_cast<int>(s >> 32), CTRL, ROWS, 0xf,
+                                               false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// inclusive prefix: lane l ends with the composition of lanes l, l-1, .., 0
+__device__ inline void scan_fwd(double &A, double &B)
+{
+    using namespace lineops;
+#define SMG_VSTEP(CTRL)                                  \
+    {                                                    \
+        const double Ap = dpp<CTRL>(1.0, A);             \
+        const double Bp = dpp0<CTRL>(B);                 \
+        B = A * Bp + B;                                  \
+        A = A * Ap;                                      \
+    }
+    SMG_VSTEP(kRowShr + 1)
+    SMG_VSTEP(kRowShr + 2)
+    SMG_VSTEP(kRowShr + 4)
+    SMG_VSTEP(kRowShr + 8)
+#undef SMG_VSTEP
+    {   // rows 1 and 3 from lane 15 of the row before
+        const double Ap = dpp_rows_id<kRowBcast15, 0xA>(1.0, A), Bp = dpp_rows_id<kRowBcast15, 0xA>(0.0, B);
+        B = A * Bp + B;
+        A = A * Ap;
+    }
+    {   // rows 2 and 3 from lane 31
+        const double Ap = dpp_rows_id<kRowBcast31, 0xC>(1.0, A), Bp = dpp_rows_id<kRowBcast31, 0xC>(0.0, B);
+        B = A * Bp + B;
+        A = A * Ap;
+    }
+}
+
+// suffix: lane l ends with its map composed with those of lanes l+1 .. 63
+// applied to zero beyond the last lane (only B is needed afterwards)
+__device__ inline void scan_bwd(double &A, double &B, int lane)
+{
+    using namespace lineops;
+#define SMG_VSTEP(CTRL)                                  \
+    {                                                    \
+        const double Ap = dpp<CTRL>(1.0, A);             \
+        const double Bp = dpp0<CTRL>(B);                 \
+        B = A * Bp + B;                                  \
+        A = A * Ap;                                      \
+    }
+    SMG_VSTEP(kRowShl + 1)
+    SMG_VSTEP(kRowShl + 2)
+    SMG_VSTEP(kRowShl + 4)
+    SMG_VSTEP(kRowShl + 8)
+#undef SMG_VSTEP
+    // each row's total map sits at its first lane; u entering row r from the
+    // right is rows r+1 .. 3 applied to zero
+    const double a1 = readlane(A, 16), b1 = readlane(B, 16);
+    const double a2 = readlane(A, 32), b2 = readlane(B, 32);
+    const double b3 = readlane(B, 48);
+    const double u2 = b3, u1 = a2 * u2 + b2, u0 = a1 * u1 + b1;
+    const int row = lane >> 4;
+    const double u = row == 3 ? 0.0 : row == 2 ? u2 : row == 1 ? u1 : u0;
+    B = A * u + B;
 }
 
 // Half-sweeps of a 2D level whose x starts at zero (no fill needed): the
@@ -356,16 +430,8 @@ __device__ inline void relax_line(const Lines &Q, const double *b, double *x, lo
         B = Al[p] * B + Rb[p];
         A = Al[p] * A;
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double Ap = __shfl_up(A, off, 64), Bp = __shfl_up(B, off, 64);
-        if (lane >= off) {
-            B = A * Bp + B;
-            A = A * Ap;
-        }
-    }
-    double yin = __shfl_up(B, 1, 64);
-    if (lane == 0) yin = 0.0;
+    scan_fwd(A, B);
+    double yin = lineops::dpp0<lineops::kWaveShr1>(B);   // y at the last point of lane - 1 (0 for lane 0)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = lane * S + e;
@@ -381,16 +447,8 @@ __device__ inline void relax_line(const Lines &Q, const double *b, double *x, lo
         B = -Gl[p] * B + Rb[p];
         A = -Gl[p] * A;
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double Ap = __shfl_down(A, off, 64), Bp = __shfl_down(B, off, 64);
-        if (lane + off < 64) {
-            B = A * Bp + B;
-            A = A * Ap;
-        }
-    }
-    double uin = __shfl_down(B, 1, 64);
-    if (lane == 63) uin = 0.0;
+    scan_bwd(A, B, lane);
+    double uin = lineops::dpp0<lineops::kWaveShl1>(B);   // u at the first point of lane + 1 (0 for lane 63)
 #pragma unroll
     for (int e = E - 1; e >= 0; --e) {
         const int p = lane * S + e;
@@ -475,7 +533,7 @@ __global__ void k_var_prolong2(const double *ydn, const double *yup, int nx, int
 // k_var_correct3 (x_k += v_0 on plane k = k0 + ks*pb; assign: x_k = v_0).
 // A block owns 64 columns and a run of 32 fine lines of one plane; each
 // coarser level's window of lines is staged in LDS.
-constexpr int kVcCols = 64, kVcRun = 32, kVcWin = 24, kVcMaxLev = 16;
+constexpr int kVcCols = 64, kVcRun = 32, kVcWin = 24;
 
 struct VChainArgs {
     const double *x[kVcMaxLev];                        // bx2 of each 2D level
@@ -932,6 +990,9 @@ void relax(const VarHier &H, int l, int l2, int np, int colour, int k0, int ks, 
         relax_mode<0>(H, l, l2, np, colour, k0, ks, st);
 }
 
+// the chain replaces the per-level prolongations when nothing follows them
+bool chained(const VarHier &H) { return H.ipost == 0 && H.ny2.size() > 1 && H.ny2.size() <= kVcMaxLev; }
+
 // One 2D V-cycle, for np planes at once (plane pb of the batch is plane
 // k0 + ks*pb of 3D level l): right-hand sides in bb2[l2], result in bx2[l2].
 // down_only: the downward half only (pre-smoothing, restriction, coarsest
@@ -993,9 +1054,6 @@ void chain_up(const VarHier &H, int l, int np, int k0, int ks, double *x, int as
     const int ncol = (H.nx + kVcCols - 1) / kVcCols, nrun = (H.ny2[0] + kVcRun - 1) / kVcRun;
     hipLaunchKernelGGL(k_var_chain2, dim3(static_cast<unsigned>(ncol) * nrun * np), dim3(256), 0, st, a);
 }
-
-// the chain replaces the per-level prolongations when nothing follows them
-bool chained(const VarHier &H) { return H.ipost == 0 && H.ny2.size() > 1 && H.ny2.size() <= kVcMaxLev; }
 
 // zebra half-sweep over the planes of one colour: x_k += V2_k((b - A x)_k)
 void sweep3(const VarHier &H, int l, int colour, const double *b, double *x, hipStream_t st)
