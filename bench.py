@@ -129,11 +129,14 @@ def precision_configs(torch, dev):
         for fam in ("down2", "coarse2", "chain2", "chain3", "resid3", "restrict3"):
             nl, ms, by = G.profile_kernel(fam, b, reps=3)
             if nl:
+                gbs = by / (ms * 1e-3) / 1e9
                 fams[fam] = {"launches": nl, "ms": round(ms, 4), "mb": round(by / 1e6, 1),
-                             "gbs": round(by / (ms * 1e-3) / 1e9, 1)}
+                             "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
+        vbytes = sum(f["mb"] for f in fams.values()) * 1e6
         res[f"fpcg_384_smg_{prec}"] = {"s": dt, "iters": info.iters, "status": info.status,
                                        "true_rel_res": info.true_rel_res, "rel_err_vs_f64_solution": err,
                                        "vcycle_ms": vms, "vcycle_gdof_per_s": n ** 3 / (vms * 1e-3) / 1e9,
+                                       "vcycle_hbm_frac": vbytes / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                        "schedule": {"l0": tune.l0, "march_waves": tune.march_waves},
                                        "kernels_per_vcycle": fams}
         del G

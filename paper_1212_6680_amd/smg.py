@@ -502,9 +502,12 @@ class SMG:
 
     def profile_kernel(self, family: str, r: torch.Tensor, reps: int = 3):
         """(launches per V-cycle, kernel ms per V-cycle, algorithmic bytes per V-cycle) of one kernel family."""
+        if family not in KERNELS:
+            raise SMGError(f"unknown kernel family {family!r}")
+        rp = _dptr(r, self.n)
         s = torch.empty_like(r)
         nl, ms, by = C.c_int32(0), C.c_double(0), C.c_double(0)
-        _check(lib().smg_profile_kernel(self.h, KERNELS[family], _dptr(r), _dptr(s), reps, _stream(),
+        _check(lib().smg_profile_kernel(self.h, KERNELS[family], rp, _dptr(s, self.n), reps, _stream(),
                                         C.byref(nl), C.byref(ms), C.byref(by)), "smg_profile_kernel")
         return nl.value, ms.value, by.value
 
@@ -512,6 +515,9 @@ class SMG:
         """Per 3D level (finest first, then the prolongation chain spanning every
         level): (launches, kernel ms, algorithmic bytes) per V-cycle, of every
         launch or of one kernel family."""
+        if family is not None and family not in KERNELS:
+            raise SMGError(f"unknown kernel family {family!r}")
+        rp = _dptr(r, self.n)
         s = torch.empty_like(r)
         rows = 64
         nl = (C.c_int32 * rows)()
@@ -519,7 +525,7 @@ class SMG:
         by = (C.c_double * rows)()
         nr = C.c_int32(0)
         fam = -1 if family is None else KERNELS[family]
-        _check(lib().smg_profile_levels(self.h, fam, _dptr(r), _dptr(s), reps, _stream(), rows, C.byref(nr),
+        _check(lib().smg_profile_levels(self.h, fam, rp, _dptr(s, self.n), reps, _stream(), rows, C.byref(nr),
                                         C.cast(nl, C.c_void_p), C.cast(ms, C.c_void_p), C.cast(by, C.c_void_p)),
                "smg_profile_levels")
         return [(nl[i], ms[i], by[i]) for i in range(nr.value)]

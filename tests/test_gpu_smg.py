@@ -281,6 +281,21 @@ def test_profile_levels_partitions_the_families(pp):
     assert torch.equal(s, G.apply(r))
 
 
+def test_profile_arguments_are_checked():
+    """The profiling entry points take one vector of the grid's size and a
+    known family; anything else fails before a launch."""
+    from paper_1212_6680_amd.smg import SMGError
+    shape = (16, 12, 10)
+    G = _smg(shape, (1.0, 1.0, 1.0), 1, 0)
+    short = torch.zeros(int(np.prod(shape)) - 1, dtype=torch.float64, device="cuda")
+    ok = torch.zeros(int(np.prod(shape)), dtype=torch.float64, device="cuda")
+    for call in (lambda: G.profile_levels(short), lambda: G.profile_kernel("down2", short),
+                 lambda: G.profile_levels(ok, family="nonesuch"), lambda: G.profile_kernel("nonesuch", ok)):
+        with pytest.raises(SMGError):
+            call()
+    assert len(G.profile_levels(ok, reps=1)) == 5
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("shape,nrhs", [((256, 20, 12), 1), ((384, 30, 8), 1), ((128, 33, 17), 1),
                                         ((96, 17, 9), 1), ((66, 10, 7), 1), ((130, 7, 5), 1),
