@@ -6,6 +6,9 @@
 //   p/q       p_k = s_k + beta_k p_{k-1} into the other p buffer, q_k = A p_k from
 //             the same neighbour loads, and (p_k, q_k);
 //   x/r       x += alpha p, r -= alpha q, and ||r||^2.
+// When the FP64 V-cycle ends in the 3D prolongation chain (no post-smoothing),
+// that kernel takes the dots as it stores s_k and the dots pass is skipped;
+// finalize then sums its per-block partials (FinArgs::nparts).
 // Reductions are deterministic: a fixed grid of kRedBlocks blocks writes one
 // partial per block (wave shuffles, then LDS across the block's waves), and
 // a one-block finalize kernel sums the partials in a fixed order and advances
@@ -373,10 +376,10 @@ __device__ __forceinline__ void k_update_xr_body(const UpdXRArgs &a, const Blk &
 }
 SMG_GROUPED_KERNEL(k_update_xr, kRB, UpdXRArgs)
 
-__device__ inline double sum_partials(const double *p, double *lds)
+__device__ inline double sum_partials(const double *p, int np, double *lds)
 {
     double v = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += p[i];
+    for (int i = threadIdx.x; i < np; i += blockDim.x) v += p[i];
     return block_sum(v, lds);
 }
 
@@ -390,8 +393,9 @@ __device__ __forceinline__ void k_finalize_body(const FinArgs &a, const Blk &)
 {
     __shared__ double lds[kRB / 64];
     KScalars *sc = a.sc;
-    const double v0 = sum_partials(a.partials, lds);
-    const double v1 = (a.which <= 1) ? sum_partials(a.partials + kRedBlocks, lds) : 0.0;
+    const int np = a.nparts > 0 ? a.nparts : kRedBlocks;
+    const double v0 = sum_partials(a.partials, np, lds);
+    const double v1 = (a.which <= 1) ? sum_partials(a.partials + np, np, lds) : 0.0;
     if (threadIdx.x != 0) return;
     if (a.which == 0) {
         sc->rr = v0;
@@ -594,7 +598,7 @@ void launch_update_xr(double *x, double *r, const double *p, const double *q, co
 }
 
 void launch_finalize(int which, int method, int k, const double *partials, KScalars *sc, KScalars *host_copy,
-                     hipStream_t st)
+                     hipStream_t st, int nparts)
 {
     FinArgs a{};
     a.which = which;
@@ -602,6 +606,7 @@ void launch_finalize(int which, int method, int k, const double *partials, KScal
     a.k = k;
     a.partials = partials;
     a.sc = sc;
+    a.nparts = nparts;
     SMG_LAUNCH_G(LaunchEv{}, k_finalize, k_finalize_grp, dim3(1), dim3(kRB), 0, st, a);
     if (host_copy) (void)hipMemcpyAsync(host_copy, sc, sizeof(KScalars), hipMemcpyDeviceToHost, st);
 }

@@ -1106,18 +1106,50 @@ __device__ __forceinline__ void k3_chain_body(const Chain3Args<T, A> &a, const B
         if (l > a.L) continue;
         step(l, chain_rows(l), [&](int t, int, const Win &, A (&v)[V]) { unpack<T, A, V>(v, pre[chain_off(l) + t]); });
     }
-    if (nok == 0) return;
-    const Win wc = win(1);
+    constexpr bool kDots = std::is_same<T, double>::value;
+    const bool dots = kDots && a.dpart != nullptr;
+    double sr = 0.0, sq = 0.0;
+    if (nok > 0) {
+        const Win wc = win(1);
 #pragma unroll
-    for (int t = 0; t < kRows0; ++t) {
-        const int kk = w0.lo + row0 + 4 * t;
-        if (kk > w0.hi) break;
-        A pv[V], v[V];
-        prolong_point<A, V, W>(pv, vs[cur], wc, kk, a.nz[1], col);
-        unpack<T, A, V>(v, xf[t]);
+        for (int t = 0; t < kRows0; ++t) {
+            const int kk = w0.lo + row0 + 4 * t;
+            if (kk > w0.hi) break;
+            A pv[V], v[V];
+            prolong_point<A, V, W>(pv, vs[cur], wc, kk, a.nz[1], col);
+            unpack<T, A, V>(v, xf[t]);
 #pragma unroll
-        for (int e = 0; e < V; ++e) v[e] = v[e] + pv[e];
-        vst<T, A, V>(x0 + kk * pl + c, v, nok);
+            for (int e = 0; e < V; ++e) v[e] = v[e] + pv[e];
+            vst<T, A, V>(x0 + kk * pl + c, v, nok);
+            if constexpr (kDots) {
+                if (dots) {
+                    for (int e = 0; e < nok; ++e) {
+                        const long long g = kk * pl + c + e;
+                        sr = fmadd(v[e], a.dr[g], sr);
+                        if (a.want_sq) sq = fmadd(v[e], a.dq[g], sq);
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (kDots) {
+        // one partial per block: wave sums, then the four waves in order
+        if (!dots) return;
+        __shared__ double red[2][4];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            sr += __shfl_down(sr, off, 64);
+            sq += __shfl_down(sq, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = sr;
+            red[1][threadIdx.x >> 6] = sq;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.dpart[blk.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+            a.dpart[blk.gx + blk.x] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+        }
     }
 }
 
@@ -1406,6 +1438,12 @@ void launch_chain3_v(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const 
     const long long nrun = (a.nz[0] + kChainRun - 1) / kChainRun;
     SMG_LAUNCH_G(ev, (k3_chain<T, A, V>), (k3_chain_grp<T, A, V>), dim3(static_cast<unsigned>(ncol * nrun), nrhs),
                  dim3(256), 0, st, a);
+}
+
+long long chain3_blocks(int nx, int ny, int nz)
+{
+    const long long pl = static_cast<long long>(nx) * ny;
+    return ((pl + kChainCols - 1) / kChainCols) * ((nz + kChainRun - 1) / kChainRun);
 }
 
 template <typename T, typename A>

@@ -76,6 +76,7 @@ struct Layout {
     std::vector<size_t> x2, b2, y2;         // 2D batch buffers per 2D level
     size_t rlo, slo;                        // low-precision level-0 in/out
     size_t kr, ks, kp0, kp1, kq, part, sc;  // Krylov
+    size_t part3;                           // Krylov dots taken by the FP64 3D chain
     size_t total;
 };
 
@@ -315,6 +316,7 @@ Layout make_layout(const smg_grid &g, const smg_opts &o, int max_nrhs, const Tab
     L.kp1 = take(N * 8);
     L.kq = take(N * 8);
     L.part = take(2 * kRedBlocks * 8);
+    L.part3 = o.precision == SMG_PREC_F64 ? take(2 * static_cast<size_t>(chain3_blocks(g.nx, g.ny, g.nz)) * 8) : 0;
     L.sc = take(sizeof(KScalars));
     L.total = off;
     return L;
@@ -325,6 +327,14 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 // ---------------------------------------------------------------------------
 // V-cycle
 // ---------------------------------------------------------------------------
+
+// Krylov inner products (s, r) and, with want_sq, (s, q) that a cycle ending in
+// the FP64 3D chain takes while it stores s (one right-hand side).
+struct VcDots {
+    const double *r, *q;
+    int want_sq;
+};
+
 template <typename T, typename A>
 struct VCycle {
     smg_handle *h;
@@ -333,6 +343,8 @@ struct VCycle {
     T *x0;
     const T *b0;
     long long ld0;
+    const VcDots *dots = nullptr;   // Krylov dots to take with the output, if the schedule can
+    bool dots_done = false;
 
     struct Batch {          // a set of planes handled by one batched 2D cycle
         int np, kmul, koff;
@@ -625,6 +637,13 @@ struct VCycle {
         }
         a.L = L; a.nx = h->g.nx; a.ny = h->g.ny;
         a.vmax = vmax();
+        if constexpr (sizeof(T) == 8) {
+            if (dots && nrhs == 1) {
+                a.dr = dots->r; a.dq = dots->q; a.want_sq = dots->want_sq;
+                a.dpart = h->at<double>(h->L.part3);
+                dots_done = true;
+            }
+        }
         double planes = h->nz[0];
         for (int l = 0; l <= L; ++l) planes += h->nz[l];
         launch_chain3<T, A>(a, nrhs, st, ev_for(SMG_KERNEL_CHAIN3, planes * pl() * nrhs));
@@ -681,14 +700,17 @@ struct VCycle {
 };
 
 template <typename T, typename A>
-void run_vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
+bool run_vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st,
+                const VcDots *dots)
 {
     VCycle<T, A> vc{h, st, nrhs, nullptr, nullptr, 0};
     if constexpr (sizeof(T) == 8) {
         vc.x0 = reinterpret_cast<T *>(s);
         vc.b0 = reinterpret_cast<const T *>(r);
         vc.ld0 = ld;
+        vc.dots = dots;
         vc.v3(0);
+        return vc.dots_done;
     } else {
         T *rlo = h->at<T>(h->L.rlo), *slo = h->at<T>(h->L.slo);
         launch_convert_in<T>(r, ld, rlo, static_cast<long long>(h->N), h->N, nrhs, st);
@@ -697,19 +719,24 @@ void run_vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long l
         vc.ld0 = static_cast<long long>(h->N);
         vc.v3(0);
         launch_convert_out<T>(slo, static_cast<long long>(h->N), s, ld, h->N, nrhs, st);
+        return false;
     }
 }
 
-void vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
+// s = B r.  With dots, the cycle may also leave the Krylov partials (s, r) and
+// (s, q) for the finalize step; it returns whether it did (they are then in
+// part3, chain3_blocks per quantity), else the caller takes them itself.
+bool vcycle(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st,
+            const VcDots *dots = nullptr)
 {
     if (h->var) {
         var_vcycle(h->var, r, s, nrhs, ld, st);
-        return;
+        return false;
     }
     switch (h->o.precision) {
-    case SMG_PREC_F64: run_vcycle<double, double>(h, r, s, nrhs, ld, st); break;
-    case SMG_PREC_F32: run_vcycle<float, float>(h, r, s, nrhs, ld, st); break;
-    default: run_vcycle<bf16, float>(h, r, s, nrhs, ld, st); break;
+    case SMG_PREC_F64: return run_vcycle<double, double>(h, r, s, nrhs, ld, st, dots);
+    case SMG_PREC_F32: return run_vcycle<float, float>(h, r, s, nrhs, ld, st, dots);
+    default: return run_vcycle<bf16, float>(h, r, s, nrhs, ld, st, dots);
     }
 }
 
@@ -798,6 +825,19 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         else
             launch_copy(in, out, n, st);
     };
+    // s_k = B r_k for iteration kk.  Without a correction hook the cycle may
+    // take the iteration's (s, r) and (s, q) as it stores s; returns whether it
+    // did (the partials are then in part3, nparts3 per quantity).
+    double *part3 = h->L.part3 ? h->at<double>(h->L.part3) : nullptr;
+    const int nparts3 = part3 ? static_cast<int>(chain3_blocks(g.nx, g.ny, g.nz)) : 0;
+    auto precond_k = [&](int kk) {
+        if (o->precond != SMG_PRECOND_SMG || !part3 || (hook && hook->active)) {
+            precond(r, s);
+            return false;
+        }
+        const VcDots d{r, q, method == 1 && kk > 0};
+        return vcycle(h, r, s, 1, static_cast<long long>(n), st, &d);
+    };
     // ||x* - x||_A^2 with the diagnostic scratch (e = x* - x, then A e)
     double *de = diag ? o->diag_work : nullptr, *dw = diag ? o->diag_work + n : nullptr;
     // the operator's passes: the 7-point model stencil, or the handle's
@@ -874,14 +914,18 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
         if (o->err_a) o->err_a[0] = ea0 > 0.0 ? 1.0 : 0.0;
     }
     int k = 0, status = SMG_NOT_CONVERGED;
-    bool queued = false;   // this iteration's V-cycle is already on the stream
-    bool cconv = false;    // C-norm test met
+    bool queued = false;        // this iteration's V-cycle is already on the stream
+    bool queued_dots = false;   // ... and it took the iteration's dots
+    bool cconv = false;         // C-norm test met
     for (; k < o->max_iter; ++k) {
         if (!cstop && !(rel > o->rtol)) break;
-        if (queued)
+        bool fused_dots;
+        if (queued) {
             queued = false;
-        else
-            precond(r, s);
+            fused_dots = queued_dots;
+        } else {
+            fused_dots = precond_k(k);
+        }
         const double *su = s;
         bool dots_done = false;
         if (hook && hook->active) {
@@ -901,8 +945,12 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
             }
         }
         if (!dots_done) {
-            launch_dots_sr_sq(s, r, q, method == 1 && k > 0, n, part, st);
-            launch_finalize(1, method, k, part, sc, want_c ? hs : nullptr, st);
+            if (fused_dots) {
+                launch_finalize(1, method, k, part3, sc, want_c ? hs : nullptr, st, nparts3);
+            } else {
+                launch_dots_sr_sq(s, r, q, method == 1 && k > 0, n, part, st);
+                launch_finalize(1, method, k, part, sc, want_c ? hs : nullptr, st);
+            }
         }
         if (want_c) {
             // (s_k, r_k) on the host: the C-norm ratio and its stopping test
@@ -947,7 +995,7 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
                            k + 1 < o->max_iter && pred > 4.0 * o->rtol;
         if (ahead) {
             if (hipEventRecord(done.e, st) != hipSuccess) return finish(SMG_EHIP);
-            vcycle(h, r, s, 1, static_cast<long long>(n), st);
+            queued_dots = precond_k(k + 1);
             queued = true;
             if (hipEventSynchronize(done.e) != hipSuccess || hipGetLastError() != hipSuccess)
                 return finish(SMG_EHIP);

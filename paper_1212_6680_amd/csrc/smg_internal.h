@@ -345,6 +345,12 @@ struct Chain3Args {
     int nz[kMaxLev3];
     int L, nx, ny;
     int vmax;               // widest points per thread allowed (0: no limit)
+    // Optional Krylov dots taken while the fine level is stored (FP64, one
+    // right-hand side): per block, (s, dr) into dpart[b] and (s, dq) (0 unless
+    // want_sq) into dpart[chain3_blocks + b]; dpart null skips them.
+    const double *dr, *dq;
+    double *dpart;
+    int want_sq;
 };
 
 template <typename T, typename A>
@@ -357,6 +363,8 @@ template <typename T, typename A>
 void launch_up2(const Up2Args<T, A> &a, hipStream_t st, const LaunchEv &ev = LaunchEv{});
 template <typename T, typename A>
 void launch_chain3(const Chain3Args<T, A> &a, int nrhs, hipStream_t st, const LaunchEv &ev = LaunchEv{});
+// blocks of one FP64 3D chain launch over an nx x ny x nz level (one right-hand side)
+long long chain3_blocks(int nx, int ny, int nz);
 int fused_waves();   // waves per workgroup of the strip and coarse kernels
 
 // Launchers (smg_kernels.hip) ---------------------------------------------
@@ -429,7 +437,8 @@ struct FinArgs {
     const double *partials;
     KScalars *sc;
     double rtol;
-    int max_iter, pad;
+    int max_iter;
+    int nparts;             // partials per quantity (0: kRedBlocks)
 };
 struct CopyArgs {
     const double *src;
@@ -454,8 +463,9 @@ void launch_update_xr(double *x, double *r, const double *p, const double *q, co
                       double *partials, hipStream_t st);
 // finalize: stage 2 of the reductions and the scalar recurrence.
 // which: 0 = init (rr, bb), 1 = beta (sr, sq), 2 = alpha (pq), 3 = rr
+// nparts: partials per quantity when they come from another grid (0: kRedBlocks)
 void launch_finalize(int which, int method, int k, const double *partials, KScalars *sc, KScalars *host_copy,
-                     hipStream_t st);
+                     hipStream_t st, int nparts = 0);
 // batched mode of finalize: stopping test on the device (see KScalars)
 void launch_finalize_batched(int which, int method, const double *partials, KScalars *sc, double rtol, int max_iter,
                              hipStream_t st);
