@@ -192,9 +192,14 @@ void iteration_launches(smg_handle *h, const KrylovView &v, double *x, int parit
 {
     double *pa = parity ? v.pb : v.pa, *pb = parity ? v.pa : v.pb;
     const smg_grid &g = v.g;
-    vcycle_apply(h, v.r, v.s, 1, static_cast<long long>(v.n), st);
-    launch_dots_sr_sq(v.s, v.r, v.q, 1, v.n, v.part, st);
-    launch_finalize_batched(1, 1, v.part, v.sc, 0.0, 0, st);
+    const double *dp = v.part;
+    int np = 0;
+    if (!vcycle_dots(h, v.r, v.s, v.q, 1, st, &dp, &np)) {
+        dp = v.part;
+        np = 0;
+        launch_dots_sr_sq(v.s, v.r, v.q, 1, v.n, v.part, st);
+    }
+    launch_finalize_batched(1, 1, dp, v.sc, 0.0, 0, st, np);
     launch_update_p_q(v.s, pa, pb, v.q, v.sc, g.nx, g.ny, g.nz, g.cx, g.cy, g.cz, v.part, st);
     launch_finalize_batched(2, 1, v.part, v.sc, 0.0, 0, st);
     launch_update_xr(x, v.r, pb, v.q, v.sc, v.n, v.part, st);

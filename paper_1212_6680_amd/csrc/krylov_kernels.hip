@@ -612,13 +612,14 @@ void launch_finalize(int which, int method, int k, const double *partials, KScal
 }
 
 void launch_finalize_batched(int which, int method, const double *partials, KScalars *sc, double rtol, int max_iter,
-                             hipStream_t st)
+                             hipStream_t st, int nparts)
 {
     FinArgs a{};
     a.which = which;
     a.method = method;
     a.partials = partials;
     a.sc = sc;
+    a.nparts = nparts;
     a.batched = 1;
     a.rtol = rtol;
     a.max_iter = max_iter;

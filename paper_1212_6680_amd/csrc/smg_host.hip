@@ -828,15 +828,14 @@ int smg::krylov_run(smg_handle *h, int method, const double *b, double *x, const
     // s_k = B r_k for iteration kk.  Without a correction hook the cycle may
     // take the iteration's (s, r) and (s, q) as it stores s; returns whether it
     // did (the partials are then in part3, nparts3 per quantity).
-    double *part3 = h->L.part3 ? h->at<double>(h->L.part3) : nullptr;
-    const int nparts3 = part3 ? static_cast<int>(chain3_blocks(g.nx, g.ny, g.nz)) : 0;
+    const double *part3 = nullptr;
+    int nparts3 = 0;
     auto precond_k = [&](int kk) {
-        if (o->precond != SMG_PRECOND_SMG || !part3 || (hook && hook->active)) {
+        if (o->precond != SMG_PRECOND_SMG || (hook && hook->active)) {
             precond(r, s);
             return false;
         }
-        const VcDots d{r, q, method == 1 && kk > 0};
-        return vcycle(h, r, s, 1, static_cast<long long>(n), st, &d);
+        return vcycle_dots(h, r, s, q, method == 1 && kk > 0, st, &part3, &nparts3);
     };
     // ||x* - x||_A^2 with the diagnostic scratch (e = x* - x, then A e)
     double *de = diag ? o->diag_work : nullptr, *dw = diag ? o->diag_work + n : nullptr;
@@ -1065,6 +1064,16 @@ int smg::krylov_view(smg_handle *h, KrylovView *v)
 void smg::vcycle_apply(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st)
 {
     vcycle(h, r, s, nrhs, ld, st);
+}
+
+bool smg::vcycle_dots(smg_handle *h, const double *r, double *s, const double *q, int want_sq, hipStream_t st,
+                      const double **part, int *nparts)
+{
+    const VcDots d{r, q, want_sq};
+    if (!vcycle(h, r, s, 1, static_cast<long long>(h->N), st, h->L.part3 ? &d : nullptr)) return false;
+    *part = h->at<double>(h->L.part3);
+    *nparts = static_cast<int>(chain3_blocks(h->g.nx, h->g.ny, h->g.nz));
+    return true;
 }
 
 int smg_handle_max_nrhs(const smg_handle *h, int32_t *max_nrhs)

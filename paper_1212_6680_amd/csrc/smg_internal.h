@@ -468,7 +468,7 @@ void launch_finalize(int which, int method, int k, const double *partials, KScal
                      hipStream_t st, int nparts = 0);
 // batched mode of finalize: stopping test on the device (see KScalars)
 void launch_finalize_batched(int which, int method, const double *partials, KScalars *sc, double rtol, int max_iter,
-                             hipStream_t st);
+                             hipStream_t st, int nparts = 0);
 void launch_copy(const double *src, double *dst, size_t n, hipStream_t st);
 void launch_fill(double *dst, double v, size_t n, hipStream_t st);
 void launch_true_resid(const double *b, const double *x, double *tmp, int nx, int ny, int nz, double cx,
@@ -493,6 +493,12 @@ struct KrylovView {
 };
 int krylov_view(smg_handle *h, KrylovView *v);
 void vcycle_apply(smg_handle *h, const double *r, double *s, int nrhs, long long ld, hipStream_t st);
+// s = B r for one right-hand side of length N, also taking the Krylov dots
+// (s, r) and, with want_sq, (s, q) where the cycle ends in the FP64 3D chain:
+// then returns true with the partials' array and count per quantity for the
+// finalize step; false means s alone was computed.
+bool vcycle_dots(smg_handle *h, const double *r, double *s, const double *q, int want_sq, hipStream_t st,
+                 const double **part, int *nparts);
 }  // namespace smg
 
 // Handle queries shared by the library's translation units.
