@@ -376,11 +376,40 @@ __device__ __forceinline__ void k_update_xr_body(const UpdXRArgs &a, const Blk &
 }
 SMG_GROUPED_KERNEL(k_update_xr, kRB, UpdXRArgs)
 
-__device__ inline double sum_partials(const double *p, int np, double *lds)
+// Block sums of p[0, np) and, with two, p[np, 2 np), valid in thread 0.  Each
+// thread keeps U running sums over entries blockDim apart, advancing U
+// entries at a time, so a long array (the 3D chain's per-block partials) has
+// 2 U loads in flight per thread; entries past the last full step go to the
+// first sum.  The order is fixed, and for np <= (U - 1) blockDim every entry
+// goes to the first sum, as a plain strided loop would add them.
+__device__ inline void sum_partials(const double *p, int np, bool two, double *lds, double &v0, double &v1)
 {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) v += p[i];
-    return block_sum(v, lds);
+    constexpr int U = 16;
+    double a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = b[u] = 0.0;
+    const int bd = static_cast<int>(blockDim.x);
+    int i = threadIdx.x;
+    for (; i + (U - 1) * bd < np; i += U * bd) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] += p[i + u * bd];
+            if (two) b[u] += p[np + i + u * bd];
+        }
+    }
+    for (; i < np; i += bd) {
+        a[0] += p[i];
+        if (two) b[0] += p[np + i];
+    }
+#pragma unroll
+    for (int w = U / 2; w > 0; w /= 2)
+#pragma unroll
+        for (int u = 0; u < w; ++u) {
+            a[u] += a[u + w];
+            b[u] += b[u + w];
+        }
+    v0 = block_sum(a[0], lds);
+    v1 = two ? block_sum(b[0], lds) : 0.0;
 }
 
 // Stage 2 of the reductions and the scalar recurrence.  method: 0 = PCG (1),
@@ -394,8 +423,8 @@ __device__ __forceinline__ void k_finalize_body(const FinArgs &a, const Blk &)
     __shared__ double lds[kRB / 64];
     KScalars *sc = a.sc;
     const int np = a.nparts > 0 ? a.nparts : kRedBlocks;
-    const double v0 = sum_partials(a.partials, np, lds);
-    const double v1 = (a.which <= 1) ? sum_partials(a.partials + np, np, lds) : 0.0;
+    double v0, v1;
+    sum_partials(a.partials, np, a.which <= 1, lds, v0, v1);
     if (threadIdx.x != 0) return;
     if (a.which == 0) {
         sc->rr = v0;
