@@ -486,9 +486,15 @@ __global__ __launch_bounds__(kB) void k_var_relax(Lines Q, const double *b, doub
 }
 
 // b_c = P^T (b - Q x) for np planes: coarse line J takes fine line 2J+1,
-// ydn[2J+2] of line 2J+2 and yup[2J] of line 2J
+// ydn[2J+2] of line 2J+2 and yup[2J] of line 2J.
+// swept: 0, the residual as defined; 1 (2), x is one half-sweep pair from
+// zero with the even (odd) lines solved first.  Then the lines solved second
+// have zero residual (each was solved exactly against its final neighbours)
+// and a line solved first has r_j = -(V_{j-1}^T x_{j-1} + V_j x_{j+1}) (it
+// solved L_j x_j = b_j while its neighbours were zero), equal to the residual
+// as defined up to rounding and with far fewer reads.
 __global__ void k_var_restrict2(Lines Q, const double *ydn, const double *yup, const double *b, const double *x,
-                                double *bc, int np, int k0, int ks)
+                                double *bc, int np, int k0, int ks, int swept)
 {
     const int nx = Q.nx, ny = Q.ny, nyc = ny / 2;
     const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -498,8 +504,19 @@ __global__ void k_var_restrict2(Lines Q, const double *ydn, const double *yup, c
     const int pb = static_cast<int>(e / nx / nyc);
     const long long cb = static_cast<long long>(k0 + ks * pb) * ny * nx, xb = static_cast<long long>(pb) * ny * nx;
     auto r = [&](int j) { return b[xb + static_cast<long long>(j) * nx + i] - q_line(Q, cb, x, xb, j, i); };
-    double v = r(2 * J + 1) + yup[cb + static_cast<long long>(2 * J) * nx + i] * r(2 * J);
-    if (2 * J + 2 < ny) v += ydn[cb + static_cast<long long>(2 * J + 2) * nx + i] * r(2 * J + 2);
+    auto rn = [&](int j) { return -q_line<false>(Q, cb, x, xb, j, i); };
+    const double wu = yup[cb + static_cast<long long>(2 * J) * nx + i];
+    const bool up = 2 * J + 2 < ny;
+    double v;
+    if (swept == 1) {
+        v = wu * rn(2 * J);
+        if (up) v += ydn[cb + static_cast<long long>(2 * J + 2) * nx + i] * rn(2 * J + 2);
+    } else if (swept == 2) {
+        v = rn(2 * J + 1);
+    } else {
+        v = r(2 * J + 1) + wu * r(2 * J);
+        if (up) v += ydn[cb + static_cast<long long>(2 * J + 2) * nx + i] * r(2 * J + 2);
+    }
     bc[e] = v;
 }
 
@@ -1017,8 +1034,11 @@ void vcycle2(const VarHier &H, int l, int l2, int np, int k0, int ks, hipStream_
     const VarLevel3 &L = H.lev[l];
     const Lines Q = lines_of(H, l, l2);
     const long long nc = static_cast<long long>(np) * H.ny2[l2 + 1] * H.nx;
+    // one pre-smoothing pair from zero: the restriction needs the lines solved first only
+    const int swept = H.ipre == 1 ? (first == 0 ? 1 : 2) : 0;
     hipLaunchKernelGGL(k_var_restrict2, dim3(nblk(nc, kB)), dim3(kB), 0, st, Q, H.at<double>(L.ydn[l2]),
-                       H.at<double>(L.yup[l2]), H.at<double>(H.bb2[l2]), x, H.at<double>(H.bb2[l2 + 1]), np, k0, ks);
+                       H.at<double>(L.yup[l2]), H.at<double>(H.bb2[l2]), x, H.at<double>(H.bb2[l2 + 1]), np, k0, ks,
+                       swept);
     vcycle2(H, l, l2 + 1, np, k0, ks, st, down_only);
     if (down_only) return;
     hipLaunchKernelGGL(k_var_prolong2, dim3(nblk(n2, kB)), dim3(kB), 0, st, H.at<double>(L.ydn[l2]),
