@@ -645,17 +645,22 @@ struct Planes {                   // a 3D level
 };
 
 // (A_l x)_k at point p of plane k: C_k x_k + U_{k-1}^T x_{k-1} + U_k x_{k+1}
+// (OWN false: without C_k x_k, for a plane whose x is still zero)
+template <bool OWN = true>
 __device__ inline double a_plane(const Planes &A, const double *x, int k, int i, int j)
 {
     const BlockOp &o = A.op;
     const int nx = o.nx, ny = o.ny;
     const long long m = static_cast<long long>(nx) * ny;
     const long long p = k * m + static_cast<long long>(j) * nx + i;
-    double v = o.cc[p] * x[p];
-    if (i > 0) v += o.ce[p - 1] * x[p - 1];
-    if (i + 1 < nx) v += o.ce[p] * x[p + 1];
-    if (j > 0) v += o.cn[p - nx] * x[p - nx];
-    if (j + 1 < ny) v += o.cn[p] * x[p + nx];
+    double v = 0.0;
+    if constexpr (OWN) {
+        v = o.cc[p] * x[p];
+        if (i > 0) v += o.ce[p - 1] * x[p - 1];
+        if (i + 1 < nx) v += o.ce[p] * x[p + 1];
+        if (j > 0) v += o.cn[p - nx] * x[p - nx];
+        if (j + 1 < ny) v += o.cn[p] * x[p + nx];
+    }
     if (k > 0) {   // U_{k-1}^T: entries of the rows of plane k-1 that reach p
         const long long d = p - m;
         v += o.uc[d] * x[d];
@@ -675,7 +680,9 @@ __device__ inline double a_plane(const Planes &A, const double *x, int k, int i,
     return v;
 }
 
-// residual of the planes of one colour into the 2D batch buffer
+// residual of the planes of one colour into the 2D batch buffer; OWN false:
+// the colour's own planes of x are zero (not read)
+template <bool OWN>
 __global__ void k_var_resid3(Planes A, const double *b, const double *x, int colour, double *r)
 {
     const int nx = A.op.nx, ny = A.op.ny;
@@ -686,17 +693,29 @@ __global__ void k_var_resid3(Planes A, const double *b, const double *x, int col
     const int pb = static_cast<int>(e / m);
     const int k = colour + 2 * pb;
     const int i = static_cast<int>(e % nx), j = static_cast<int>((e % m) / nx);
-    r[e] = b[k * m + e % m] - a_plane(A, x, k, i, j);
+    r[e] = b[k * m + e % m] - a_plane<OWN>(A, x, k, i, j);
 }
 
-// x_k += y_pb for the planes of one colour
-__global__ void k_var_correct3(double *x, const double *y, long long m, int nz, int colour)
+// the planes of one colour of b into the 2D batch buffer (the residual of a zero x)
+__global__ void k_var_gather3(const double *b, long long m, int nz, int colour, double *r)
+{
+    const int npl = (nz - colour + 1) / 2;
+    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= npl * m) return;
+    r[e] = b[(colour + 2 * (e / m)) * m + e % m];
+}
+
+// x_k += y_pb for the planes of one colour (assign: x_k = y_pb)
+__global__ void k_var_correct3(double *x, const double *y, long long m, int nz, int colour, int assign)
 {
     const int npl = (nz - colour + 1) / 2;
     const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= npl * m) return;
     const int k = colour + 2 * static_cast<int>(e / m);
-    x[k * m + e % m] += y[e];
+    if (assign)
+        x[k * m + e % m] = y[e];
+    else
+        x[k * m + e % m] += y[e];
 }
 
 __global__ void k_var_restrict3(Planes A, const double *wdn, const double *wup, const double *b, const double *x,
@@ -1075,23 +1094,32 @@ void chain_up(const VarHier &H, int l, int np, int k0, int ks, double *x, int as
     hipLaunchKernelGGL(k_var_chain2, dim3(static_cast<unsigned>(ncol) * nrun * np), dim3(256), 0, st, a);
 }
 
-// zebra half-sweep over the planes of one colour: x_k += V2_k((b - A x)_k)
-void sweep3(const VarHier &H, int l, int colour, const double *b, double *x, hipStream_t st)
+// zebra half-sweep over the planes of one colour: x_k += V2_k((b - A x)_k).
+// zero: 0 general; 1 x is zero (its planes are not read: the right-hand sides
+// are b); 2 the colour's own planes of x are zero (not read).  With zero > 0
+// the colour's planes of x are assigned, so x needs no clearing beforehand.
+void sweep3(const VarHier &H, int l, int colour, const double *b, double *x, hipStream_t st, int zero = 0)
 {
     const VarLevel3 &L = H.lev[l];
     const int np = (L.nz - colour + 1) / 2;
     if (np <= 0) return;
     const long long m = static_cast<long long>(H.nx) * H.ny;
-    hipLaunchKernelGGL(k_var_resid3, dim3(nblk(np * m, kB)), dim3(kB), 0, st, planes_of(H, l), b, x, colour,
-                       H.at<double>(H.bb2[0]));
+    double *r = H.at<double>(H.bb2[0]);
+    const dim3 grid(nblk(np * m, kB));
+    if (zero == 1)
+        hipLaunchKernelGGL(k_var_gather3, grid, dim3(kB), 0, st, b, m, L.nz, colour, r);
+    else if (zero == 2)
+        hipLaunchKernelGGL(k_var_resid3<false>, grid, dim3(kB), 0, st, planes_of(H, l), b, x, colour, r);
+    else
+        hipLaunchKernelGGL(k_var_resid3<true>, grid, dim3(kB), 0, st, planes_of(H, l), b, x, colour, r);
+    const int assign = zero > 0 ? 1 : 0;
     if (chained(H)) {
         vcycle2(H, l, 0, np, colour, 2, st, true);
-        chain_up(H, l, np, colour, 2, x, 0, st);
+        chain_up(H, l, np, colour, 2, x, assign, st);
         return;
     }
     vcycle2(H, l, 0, np, colour, 2, st);
-    hipLaunchKernelGGL(k_var_correct3, dim3(nblk(np * m, kB)), dim3(kB), 0, st, x, H.at<double>(H.bx2[0]), m, L.nz,
-                       colour);
+    hipLaunchKernelGGL(k_var_correct3, grid, dim3(kB), 0, st, x, H.at<double>(H.bx2[0]), m, L.nz, colour, assign);
 }
 
 void vcycle3(const VarHier &H, int l, const double *b, double *x, hipStream_t st)
@@ -1109,11 +1137,13 @@ void vcycle3(const VarHier &H, int l, const double *b, double *x, hipStream_t st
         hipLaunchKernelGGL(k_var_copy, dim3(nblk(m, kB)), dim3(kB), 0, st, H.at<double>(H.bx2[0]), x, m);
         return;
     }
-    launch_fill(x, 0.0, static_cast<size_t>(m * L.nz), st);
+    // x starts at zero: the first sweep assigns every plane (without
+    // pre-smoothing the restriction reads a cleared x)
+    if (H.pre == 0) launch_fill(x, 0.0, static_cast<size_t>(m * L.nz), st);
     const int first = H.order == 0 ? 0 : 1, second = 1 - first;
     for (int t = 0; t < H.pre; ++t) {
-        sweep3(H, l, first, b, x, st);
-        sweep3(H, l, second, b, x, st);
+        sweep3(H, l, first, b, x, st, t == 0 ? 1 : 0);
+        sweep3(H, l, second, b, x, st, t == 0 ? 2 : 0);
     }
     const VarLevel3 &C = H.lev[l + 1];
     hipLaunchKernelGGL(k_var_restrict3, dim3(nblk(m * C.nz, kB)), dim3(kB), 0, st, planes_of(H, l),
