@@ -273,25 +273,36 @@ struct Lines {                    // a 2D level of all planes of a 3D level
 template <bool OWN = true>
 __device__ inline double q_line(const Lines &Q, long long cb, const double *x, long long xb, int j, int i)
 {
+    // Every operand is loaded at an index clamped into the plane, so all the
+    // loads are in flight together; a term past an edge is then skipped, and
+    // the sum keeps the stencil's order.
     const int nx = Q.nx;
     const long long c = cb + static_cast<long long>(j) * nx + i, xc = xb + static_cast<long long>(j) * nx + i;
+    const bool hw = i > 0, he = i + 1 < nx, hs = j > 0, hn = j + 1 < Q.ny;
+    const int dw = hw ? 1 : 0, de = he ? 1 : 0;
+    const long long ds = hs ? nx : 0, dn = hn ? nx : 0;
     double v = 0.0;
     if constexpr (OWN) {
-        v = Q.lc[c] * x[xc];
-        if (i > 0) v += Q.le[c - 1] * x[xc - 1];
-        if (i + 1 < nx) v += Q.le[c] * x[xc + 1];
+        const double l0 = Q.lc[c], lw = Q.le[c - dw], le = Q.le[c];
+        const double x0 = x[xc], xw = x[xc - dw], xe = x[xc + de];
+        v = l0 * x0;
+        if (hw) v += lw * xw;
+        if (he) v += le * xe;
     }
-    if (j > 0) {
-        const long long d = c - nx, xd = xc - nx;
-        v += Q.vc[d] * x[xd];
-        if (i > 0) v += Q.ve[d - 1] * x[xd - 1];
-        if (i + 1 < nx) v += Q.vw[d + 1] * x[xd + 1];
+    const long long d = c - ds, xd = xc - ds, xu = xc + dn;
+    const double sc = Q.vc[d], sw = Q.ve[d - dw], se = Q.vw[d + de];
+    const double xs0 = x[xd], xsw = x[xd - dw], xse = x[xd + de];
+    const double nc = Q.vc[c], ne = Q.ve[c], nw = Q.vw[c];
+    const double xn0 = x[xu], xne = x[xu + de], xnw = x[xu - dw];
+    if (hs) {
+        v += sc * xs0;
+        if (hw) v += sw * xsw;
+        if (he) v += se * xse;
     }
-    if (j + 1 < Q.ny) {
-        const long long xu = xc + nx;
-        v += Q.vc[c] * x[xu];
-        if (i + 1 < nx) v += Q.ve[c] * x[xu + 1];
-        if (i > 0) v += Q.vw[c] * x[xu - 1];
+    if (hn) {
+        v += nc * xn0;
+        if (he) v += ne * xne;
+        if (hw) v += nw * xnw;
     }
     return v;
 }
@@ -649,33 +660,45 @@ struct Planes {                   // a 3D level
 template <bool OWN = true>
 __device__ inline double a_plane(const Planes &A, const double *x, int k, int i, int j)
 {
+    // loads at clamped indices, all in flight together; terms past an edge
+    // skipped afterwards, in the stencil's order (as in q_line)
     const BlockOp &o = A.op;
     const int nx = o.nx, ny = o.ny;
     const long long m = static_cast<long long>(nx) * ny;
     const long long p = k * m + static_cast<long long>(j) * nx + i;
+    const bool hw = i > 0, he = i + 1 < nx, hs = j > 0, hn = j + 1 < ny, hd = k > 0, hu = k + 1 < A.nz;
+    const int dw = hw ? 1 : 0, de = he ? 1 : 0;
+    const long long ds = hs ? nx : 0, dn = hn ? nx : 0;
     double v = 0.0;
     if constexpr (OWN) {
-        v = o.cc[p] * x[p];
-        if (i > 0) v += o.ce[p - 1] * x[p - 1];
-        if (i + 1 < nx) v += o.ce[p] * x[p + 1];
-        if (j > 0) v += o.cn[p - nx] * x[p - nx];
-        if (j + 1 < ny) v += o.cn[p] * x[p + nx];
+        const double c0 = o.cc[p], cw = o.ce[p - dw], ce = o.ce[p], cs = o.cn[p - ds], cn = o.cn[p];
+        const double x0 = x[p], xw = x[p - dw], xe = x[p + de], xs = x[p - ds], xn = x[p + dn];
+        v = c0 * x0;
+        if (hw) v += cw * xw;
+        if (he) v += ce * xe;
+        if (hs) v += cs * xs;
+        if (hn) v += cn * xn;
     }
-    if (k > 0) {   // U_{k-1}^T: entries of the rows of plane k-1 that reach p
-        const long long d = p - m;
-        v += o.uc[d] * x[d];
-        if (i > 0) v += o.ue[d - 1] * x[d - 1];
-        if (i + 1 < nx) v += o.uw[d + 1] * x[d + 1];
-        if (j > 0) v += o.un[d - nx] * x[d - nx];
-        if (j + 1 < ny) v += o.us[d + nx] * x[d + nx];
+    // U_{k-1}^T: entries of the rows of plane k-1 that reach p
+    const long long d = p - (hd ? m : 0);
+    const double dc = o.uc[d], de_ = o.ue[d - dw], dw_ = o.uw[d + de], ds_ = o.un[d - ds], dn_ = o.us[d + dn];
+    const double yd0 = x[d], ydw = x[d - dw], yde = x[d + de], yds = x[d - ds], ydn = x[d + dn];
+    const long long u = p + (hu ? m : 0);
+    const double uc = o.uc[p], ue = o.ue[p], uw = o.uw[p], un = o.un[p], us = o.us[p];
+    const double yu0 = x[u], yue = x[u + de], yuw = x[u - dw], yun = x[u + dn], yus = x[u - ds];
+    if (hd) {
+        v += dc * yd0;
+        if (hw) v += de_ * ydw;
+        if (he) v += dw_ * yde;
+        if (hs) v += ds_ * yds;
+        if (hn) v += dn_ * ydn;
     }
-    if (k + 1 < A.nz) {
-        const long long u = p + m;
-        v += o.uc[p] * x[u];
-        if (i + 1 < nx) v += o.ue[p] * x[u + 1];
-        if (i > 0) v += o.uw[p] * x[u - 1];
-        if (j + 1 < ny) v += o.un[p] * x[u + nx];
-        if (j > 0) v += o.us[p] * x[u - nx];
+    if (hu) {
+        v += uc * yu0;
+        if (he) v += ue * yue;
+        if (hw) v += uw * yuw;
+        if (hn) v += un * yun;
+        if (hs) v += us * yus;
     }
     return v;
 }
