@@ -741,20 +741,34 @@ __global__ void k_var_correct3(double *x, const double *y, long long m, int nz, 
         x[k * m + e % m] += y[e];
 }
 
+// b_c = P^T (b - A x): coarse plane K takes fine plane 2K+1, wup of plane 2K
+// and wdn of plane 2K+2.  A thread owns one point of the plane and marches
+// through kRestrictRun coarse planes, so the residual of fine plane 2K+2 also
+// serves coarse plane K+1.
+constexpr int kRestrictRun = 8;
+
 __global__ void k_var_restrict3(Planes A, const double *wdn, const double *wup, const double *b, const double *x,
                                 double *bc)
 {
     const int nx = A.op.nx, ny = A.op.ny, nzc = A.nz / 2;
     const long long m = static_cast<long long>(nx) * ny;
-    const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= nzc * m) return;
-    const int K = static_cast<int>(e / m);
-    const long long p = e % m;
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= m) return;
+    const int K0 = static_cast<int>(blockIdx.y) * kRestrictRun, K1 = min(K0 + kRestrictRun, nzc);
     const int i = static_cast<int>(p % nx), j = static_cast<int>(p / nx);
     auto r = [&](int k) { return b[k * m + p] - a_plane(A, x, k, i, j); };
-    double v = r(2 * K + 1) + wup[2 * K * m + p] * r(2 * K);
-    if (2 * K + 2 < A.nz) v += wdn[(2 * K + 2) * m + p] * r(2 * K + 2);
-    bc[e] = v;
+    double r0 = r(2 * K0);
+    for (int K = K0; K < K1; ++K) {
+        const double r1 = r(2 * K + 1);
+        double v = r1 + wup[2 * K * m + p] * r0;
+        double r2 = 0.0;
+        if (2 * K + 2 < A.nz) {
+            r2 = r(2 * K + 2);
+            v += wdn[(2 * K + 2) * m + p] * r2;
+        }
+        bc[K * m + p] = v;
+        r0 = r2;
+    }
 }
 
 __global__ void k_var_prolong3(const double *wdn, const double *wup, long long m, int nz, const double *xc, double *x)
@@ -1169,7 +1183,8 @@ void vcycle3(const VarHier &H, int l, const double *b, double *x, hipStream_t st
         sweep3(H, l, second, b, x, st, t == 0 ? 2 : 0);
     }
     const VarLevel3 &C = H.lev[l + 1];
-    hipLaunchKernelGGL(k_var_restrict3, dim3(nblk(m * C.nz, kB)), dim3(kB), 0, st, planes_of(H, l),
+    hipLaunchKernelGGL(k_var_restrict3, dim3(nblk(m, kB), (C.nz + kRestrictRun - 1) / kRestrictRun), dim3(kB), 0,
+                       st, planes_of(H, l),
                        H.at<double>(L.wdn), H.at<double>(L.wup), b, x, H.at<double>(C.b));
     vcycle3(H, l + 1, H.at<double>(C.b), H.at<double>(C.x), st);
     hipLaunchKernelGGL(k_var_prolong3, dim3(nblk(m * L.nz, kB)), dim3(kB), 0, st, H.at<double>(L.wdn),
