@@ -585,14 +585,14 @@ __device__ inline VWin vc_coarser(VWin f, int nc)
     return c;
 }
 
-// P v_c at fine line jj, column i (weights at c), window wc of the coarse level
-__device__ inline double vc_prolong(const double *vc, VWin wc, int jj, int nyc, int col, const double *ydn,
-                                    const double *yup, long long c)
+// P v_c at fine line jj, column col, window wc of the coarse level, with the
+// fine line's weights wd (ydn) and wu (yup) at this column
+__device__ inline double vc_prolong(const double *vc, VWin wc, int jj, int nyc, int col, double wd, double wu)
 {
     if (jj & 1) return vc[((jj - 1) / 2 - wc.lo) * kVcCols + col];
     double v = 0.0;
-    if (jj / 2 - 1 >= 0) v += ydn[c] * vc[(jj / 2 - 1 - wc.lo) * kVcCols + col];
-    if (jj / 2 < nyc) v += yup[c] * vc[(jj / 2 - wc.lo) * kVcCols + col];
+    if (jj / 2 - 1 >= 0) v += wd * vc[(jj / 2 - 1 - wc.lo) * kVcCols + col];
+    if (jj / 2 < nyc) v += wu * vc[(jj / 2 - wc.lo) * kVcCols + col];
     return v;
 }
 
@@ -622,17 +622,41 @@ __global__ __launch_bounds__(256) void k_var_chain2(VChainArgs a)
         return in ? a.x[l][(static_cast<long long>(pb) * a.ny2[l] + jj) * nx + i] : 0.0;
     };
     auto wc_of = [&](int l, int jj) { return (static_cast<long long>(k) * a.ny2[l] + jj) * nx + i; };
+    // A level's rows of x and of its weights are all loaded before any of
+    // them is used, so their latencies overlap (a loop that loaded and used
+    // one row at a time waited a round trip per row).
+    constexpr int kRows = kVcWin / 4, kRows0 = kVcRun / 4;   // rows per thread
     int cur = 0;
     for (int l = a.nl - 1; l >= 1; --l) {
         const VWin wl = win(l);
+        double xr[kRows], wd[kRows], wu[kRows];
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) {
+            const int jj = wl.lo + row0 + 4 * t;
+            xr[t] = wd[t] = wu[t] = 0.0;
+            if (jj <= wl.hi) {
+                xr[t] = xrow(l, jj);
+                if (in && l < a.nl - 1) {
+                    wd[t] = a.ydn[l][wc_of(l, jj)];
+                    wu[t] = a.yup[l][wc_of(l, jj)];
+                }
+            }
+        }
         if (l == a.nl - 1) {   // the coarsest level as it is
-            for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4) vs[cur][(jj - wl.lo) * kVcCols + col] = xrow(l, jj);
+#pragma unroll
+            for (int t = 0; t < kRows; ++t) {
+                const int jj = wl.lo + row0 + 4 * t;
+                if (jj <= wl.hi) vs[cur][(jj - wl.lo) * kVcCols + col] = xr[t];
+            }
         } else {
             const VWin wc = win(l + 1);
-            for (int jj = wl.lo + row0; jj <= wl.hi; jj += 4) {
-                const double s = in ? vc_prolong(vs[cur], wc, jj, a.ny2[l + 1], col, a.ydn[l], a.yup[l], wc_of(l, jj))
-                                    : 0.0;
-                vs[cur ^ 1][(jj - wl.lo) * kVcCols + col] = xrow(l, jj) + s;
+#pragma unroll
+            for (int t = 0; t < kRows; ++t) {
+                const int jj = wl.lo + row0 + 4 * t;
+                if (jj <= wl.hi) {
+                    const double s = in ? vc_prolong(vs[cur], wc, jj, a.ny2[l + 1], col, wd[t], wu[t]) : 0.0;
+                    vs[cur ^ 1][(jj - wl.lo) * kVcCols + col] = xr[t] + s;
+                }
             }
             cur ^= 1;
         }
@@ -640,13 +664,28 @@ __global__ __launch_bounds__(256) void k_var_chain2(VChainArgs a)
     }
     if (!in) return;   // after the last barrier
     const VWin wc = win(1);
-    for (int jj = w0.lo + row0; jj <= w0.hi; jj += 4) {
-        const double v = xrow(0, jj) + vc_prolong(vs[cur], wc, jj, a.ny2[1], col, a.ydn[0], a.yup[0], wc_of(0, jj));
+    double xr[kRows0], wd[kRows0], wu[kRows0], old[kRows0];
+#pragma unroll
+    for (int t = 0; t < kRows0; ++t) {
+        const int jj = w0.lo + row0 + 4 * t;
+        xr[t] = wd[t] = wu[t] = old[t] = 0.0;
+        if (jj <= w0.hi) {
+            xr[t] = xrow(0, jj);
+            wd[t] = a.ydn[0][wc_of(0, jj)];
+            wu[t] = a.yup[0][wc_of(0, jj)];
+            if (!a.assign) old[t] = a.x3[k * a.m + static_cast<long long>(jj) * nx + i];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kRows0; ++t) {
+        const int jj = w0.lo + row0 + 4 * t;
+        if (jj > w0.hi) break;
+        const double v = xr[t] + vc_prolong(vs[cur], wc, jj, a.ny2[1], col, wd[t], wu[t]);
         double *dst = a.x3 + k * a.m + static_cast<long long>(jj) * nx + i;
         if (a.assign)
             *dst = v;
         else
-            *dst += v;
+            *dst = old[t] + v;
     }
 }
 
