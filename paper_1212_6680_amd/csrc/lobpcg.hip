@@ -357,7 +357,9 @@ struct RowSpan {
     int hi[kTriMax / 16];
 };
 
-template <int JB>
+// RG: 16-row groups per wave; a block owns 64 RG rows, so each staged slice of
+// C serves RG times as many rows.
+template <int JB, int RG = 1>
 __global__ __launch_bounds__(256) void k_block_update_wide(
     const double *U, long long ldu, int i_begin, int i_end,
                                                            const double *C, int mo, RowSpan span, double *Y,
@@ -366,20 +368,23 @@ __global__ __launch_bounds__(256) void k_block_update_wide(
     constexpr int W = 16 * JB;
     constexpr int RC = (kK * W + 255) / 256;     // C values per thread and stage
     __shared__ double Ct[2][kK][W + kLdsPad];
-    __shared__ double Ut[2][kK][kT + kLdsPad];
+    constexpr int TR = kT * RG;                  // rows per block
+    __shared__ double Ut[2][kK][TR + kLdsPad];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const long long n0 = static_cast<long long>(blockIdx.x) * kT;
+    const long long n0 = static_cast<long long>(blockIdx.x) * TR;
     const int jn = (mo + 15) / 16;
     const int mp = jn * 16;
-    v4d acc[JB];
+    v4d acc[RG][JB];
 #pragma unroll
-    for (int jt = 0; jt < JB; ++jt) acc[jt] = v4d{0, 0, 0, 0};
-    double ru[4], rc[RC];
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int jt = 0; jt < JB; ++jt) acc[g][jt] = v4d{0, 0, 0, 0};
+    double ru[4 * RG], rc[RC];
     auto fetch = [&](int i0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int e = tid + 256 * r;          // 16 x 64
-            const int ii = e >> 6, nn = e & 63;
+        for (int r = 0; r < 4 * RG; ++r) {
+            const int e = tid + 256 * r;          // 16 x TR
+            const int ii = e / TR, nn = e % TR;
             const long long ng = n0 + nn;
             ru[r] = (i0 + ii < i_end && ng < n) ? U[ng + (i0 + ii) * ldu] : 0.0;
         }
@@ -392,9 +397,9 @@ __global__ __launch_bounds__(256) void k_block_update_wide(
     };
     auto stash = [&](int st) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4 * RG; ++r) {
             const int e = tid + 256 * r;
-            Ut[st][e >> 6][e & 63] = ru[r];
+            Ut[st][e / TR][e % TR] = ru[r];
         }
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
@@ -413,12 +418,16 @@ __global__ __launch_bounds__(256) void k_block_update_wide(
 #pragma unroll
         for (int kk = 0; kk < kK / 4; ++kk) {
             const int kr = 4 * kk + (lane >> 4);
-            const double b = Ut[st][kr][16 * w + (lane & 15)];
+            double b[RG];
+#pragma unroll
+            for (int g = 0; g < RG; ++g) b[g] = Ut[st][kr][kT * g + 16 * w + (lane & 15)];
 #pragma unroll
             for (int jt = 0; jt < JB; ++jt) {
                 if (jt < jn && i0 < span.hi[jt] && i0 + kK > span.lo[jt]) {
                     const double a = Ct[st][kr][16 * jt + (lane & 15)];
-                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
+#pragma unroll
+                    for (int g = 0; g < RG; ++g)
+                        acc[g][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[g], acc[g][jt], 0, 0, 0);
                 }
             }
         }
@@ -426,14 +435,17 @@ __global__ __launch_bounds__(256) void k_block_update_wide(
         __syncthreads();
         st ^= 1;
     }
-    const long long nn = n0 + 16 * w + (lane & 15);
-    if (nn >= n) return;
 #pragma unroll
-    for (int jt = 0; jt < JB; ++jt) {
+    for (int g = 0; g < RG; ++g) {
+        const long long nn = n0 + kT * g + 16 * w + (lane & 15);
+        if (nn >= n) continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = 16 * jt + 4 * r + (lane >> 4);
-            if (j < mo) (j < jsplit ? Y + j * ldy : Y2 + (j - jsplit) * ldy)[nn] = acc[jt][r];
+        for (int jt = 0; jt < JB; ++jt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = 16 * jt + 4 * r + (lane >> 4);
+                if (j < mo) (j < jsplit ? Y + j * ldy : Y2 + (j - jsplit) * ldy)[nn] = acc[g][jt][r];
+            }
         }
     }
 }
@@ -806,17 +818,18 @@ struct Lob {
             if (i_end <= i_begin) i_begin = i_end = 0;   // C == 0: the kernel writes zeros
             i_begin -= i_begin % kK;
             const dim3 grid(nblk(static_cast<long long>(N), kT));
+            const dim3 grid2(nblk(static_cast<long long>(N), 2 * kT));
             const long long ln = static_cast<long long>(N);
             const double *Cd = at<double>(L.C);
             if (mo <= 32)
-                hipLaunchKernelGGL(k_block_update_wide<2>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln, Y2, jsplit);
+                hipLaunchKernelGGL((k_block_update_wide<2, 2>), grid2, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo,
+                                   sp, Y, ln, ln, Y2, jsplit);
             else if (mo <= 48)
-                hipLaunchKernelGGL(k_block_update_wide<3>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln, Y2, jsplit);
+                hipLaunchKernelGGL((k_block_update_wide<3, 2>), grid2, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo,
+                                   sp, Y, ln, ln, Y2, jsplit);
             else if (mo <= 128)
-                hipLaunchKernelGGL(k_block_update_wide<8>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln, Y2, jsplit);
+                hipLaunchKernelGGL((k_block_update_wide<8, 2>), grid2, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo,
+                                   sp, Y, ln, ln, Y2, jsplit);
             else if (mo <= 144)
                 hipLaunchKernelGGL(k_block_update_wide<9>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
                                    Y, ln, ln, Y2, jsplit);
