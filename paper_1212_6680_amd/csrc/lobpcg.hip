@@ -360,7 +360,7 @@ struct RowSpan {
 // RG: 16-row groups per wave; a block owns 64 RG rows, so each staged slice of
 // C serves RG times as many rows.
 template <int JB, int RG = 1>
-__global__ __launch_bounds__(256) void k_block_update_wide(
+__global__ __launch_bounds__(256, 2) void k_block_update_wide(
     const double *U, long long ldu, int i_begin, int i_end,
                                                            const double *C, int mo, RowSpan span, double *Y,
                                                            long long ldy, long long n, double *Y2, int jsplit)
@@ -831,8 +831,8 @@ struct Lob {
                 hipLaunchKernelGGL((k_block_update_wide<8, 2>), grid2, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo,
                                    sp, Y, ln, ln, Y2, jsplit);
             else if (mo <= 144)
-                hipLaunchKernelGGL(k_block_update_wide<9>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
-                                   Y, ln, ln, Y2, jsplit);
+                hipLaunchKernelGGL((k_block_update_wide<9, 2>), grid2, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo,
+                                   sp, Y, ln, ln, Y2, jsplit);
             else if (mo <= 208)
                 hipLaunchKernelGGL(k_block_update_wide<13>, grid, dim3(256), 0, st, U, ln, i_begin, i_end, Cd, mo, sp,
                                    Y, ln, ln, Y2, jsplit);
