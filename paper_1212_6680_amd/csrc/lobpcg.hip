@@ -141,9 +141,9 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double *U, long long
 // block takes a slice of rows and ALL 16 x 16 output blocks on or above the
 // diagonal (nb (nb + 1) / 2 of them, nb = ceil(k / 16)), dealt round-robin to
 // its 8 waves, so every block does the same work and no MFMA is spent on
-// padding beyond the last 16-block.  Slices of 16 rows (8 when U != V, to keep
-// both operands in the same LDS) are staged in two LDS stages with the next
-// slice read into registers meanwhile.  Writes part[z][i][j] for the upper
+// padding beyond the last 16-block.  Slices of 16 rows (of both operands when
+// U != V) are staged in two LDS stages with the next slice read into
+// registers meanwhile.  Writes part[z][i][j] for the upper
 // blocks only (the reduction mirrors).  An instance takes k <= 16 NB: its
 // accumulators and LDS scale with NB, so narrow products run more blocks per CU.
 constexpr int kTriMax = 224;                  // 14 blocks of 16
@@ -153,7 +153,7 @@ template <bool SAME, int NB>
 __global__ __launch_bounds__(64 * kTriWaves) void k_gram_tri(const double *U, const double *V, long long ld, int k, long long n,
                                                   long long slice, double *part)
 {
-    constexpr int KS = SAME ? 16 : 8;                    // rows per stage
+    constexpr int KS = 16;                               // rows per stage
     constexpr int NT = 64 * kTriWaves;
     constexpr int TM = 16 * NB;                          // widest k of this instance
     constexpr int PW = (NB * (NB + 1) / 2 + kTriWaves - 1) / kTriWaves;   // output blocks per wave
