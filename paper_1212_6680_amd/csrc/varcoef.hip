@@ -926,6 +926,85 @@ __global__ __launch_bounds__(kB) void k_var_update_p_q(Planes A, const double *s
     if (threadIdx.x == 0) partials[blockIdx.x] = pq;
 }
 
+// The same update with p staged per plane in an LDS tile (64 x 8 points and
+// their in-plane halo) while each block marches through a run of planes, so
+// every p value is formed once instead of once per neighbour that reads it.
+// q adds the operator's terms in a_fine's order (bitwise a_fine's q); the
+// partial (p, q) is per block, at most kRedBlocks blocks (block 0 zeroes the
+// unused slots).
+constexpr int kPTX = 64, kPTY = 8, kPThreads = kPTX * kPTY;
+
+__global__ __launch_bounds__(kPThreads) void k_var_update_p_q_tiled(Planes A, const double *s, const double *p_old,
+                                                                    double *p_new, double *q, const KScalars *sc,
+                                                                    int kchunk, double *partials)
+{
+    __shared__ double tile[(kPTY + 2) * (kPTX + 2)];
+    __shared__ double lds[kPThreads / 64];
+    const BlockOp &o = A.op;
+    const double beta = sc->beta;
+    const int nx = o.nx, ny = o.ny, nz = A.nz;
+    const int tx = threadIdx.x % kPTX, ty = threadIdx.x / kPTX;
+    const int i = blockIdx.x * kPTX + tx, j = blockIdx.y * kPTY + ty;
+    const bool in = i < nx && j < ny;
+    const long long m = static_cast<long long>(nx) * ny;
+    const long long c2 = static_cast<long long>(j) * nx + i;
+    const int k0 = blockIdx.z * kchunk, k1 = min(nz, k0 + kchunk);
+    auto pv = [&](long long c) { return beta == 0.0 ? s[c] : s[c] + beta * p_old[c]; };
+    // halo cell of this thread: the rows above and below the tile, then the
+    // columns left and right of it (no corners: the in-plane stencil has none)
+    const int t = threadIdx.x;
+    int hy = -1, hx = -1;
+    if (t < kPTX) {
+        hy = 0; hx = t + 1;
+    } else if (t < 2 * kPTX) {
+        hy = kPTY + 1; hx = t - kPTX + 1;
+    } else if (t < 2 * kPTX + kPTY) {
+        hy = t - 2 * kPTX + 1; hx = 0;
+    } else if (t < 2 * kPTX + 2 * kPTY) {
+        hy = t - 2 * kPTX - kPTY + 1; hx = kPTX + 1;
+    }
+    const int hi = blockIdx.x * kPTX + hx - 1, hj = blockIdx.y * kPTY + hy - 1;
+    const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+    const long long hc2 = static_cast<long long>(hj) * nx + hi;
+    const bool hw = i > 0, he = i + 1 < nx, hs = j > 0, hn = j + 1 < ny;
+    const long long dw = hw ? 1 : 0, ds = hs ? nx : 0;
+    double pm = (in && k0 > 0 && k0 < nz) ? pv((k0 - 1) * m + c2) : 0.0;
+    double pc = (in && k0 < nz) ? pv(k0 * m + c2) : 0.0;
+    double pq = 0.0;
+    constexpr int RW = kPTX + 2;
+    for (int k = k0; k < k1; ++k) {
+        const double pn = (in && k + 1 < nz) ? pv((k + 1) * m + c2) : 0.0;
+        tile[(ty + 1) * RW + tx + 1] = pc;
+        if (hy >= 0) tile[hy * RW + hx] = hin ? pv(k * m + hc2) : 0.0;
+        __syncthreads();
+        if (in) {
+            const long long c = k * m + c2, dd = k > 0 ? m : 0;
+            const int cc = (ty + 1) * RW + tx + 1;
+            const double c0 = o.cc[c], cw = o.ce[c - dw], ce = o.ce[c], cs = o.cn[c - ds], cn = o.cn[c],
+                         cd = o.uc[c - dd], cu = o.uc[c];
+            double v = c0 * pc;
+            if (hw) v += cw * tile[cc - 1];
+            if (he) v += ce * tile[cc + 1];
+            if (hs) v += cs * tile[cc - RW];
+            if (hn) v += cn * tile[cc + RW];
+            if (k > 0) v += cd * pm;
+            if (k + 1 < nz) v += cu * pn;
+            p_new[c] = pc;
+            q[c] = v;
+            pq += pc * v;
+        }
+        __syncthreads();
+        pm = pc;
+        pc = pn;
+    }
+    pq = block_sum(pq, lds);
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0) partials[bid] = pq;
+    if (bid == 0)
+        for (int e = nb + threadIdx.x; e < kRedBlocks; e += blockDim.x) partials[e] = 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -1291,6 +1370,14 @@ void var_init_resid(VarHier *H, const double *b, const double *x, double *r, int
 void var_update_p_q(VarHier *H, const double *s, const double *p_old, double *p_new, double *q, const KScalars *sc,
                     double *partials, hipStream_t st)
 {
+    const int gx = (H->nx + kPTX - 1) / kPTX, gy = (H->ny + kPTY - 1) / kPTY;
+    if (static_cast<long long>(gx) * gy <= kRedBlocks) {   // planes tiled, runs of planes per block
+        const int gz0 = std::max(1, std::min(H->nz, kRedBlocks / (gx * gy)));
+        const int kchunk = (H->nz + gz0 - 1) / gz0, gz = (H->nz + kchunk - 1) / kchunk;
+        hipLaunchKernelGGL(k_var_update_p_q_tiled, dim3(gx, gy, gz), dim3(kPThreads), 0, st, planes_of(*H, 0), s,
+                           p_old, p_new, q, sc, kchunk, partials);
+        return;
+    }
     hipLaunchKernelGGL(k_var_update_p_q, dim3(kRedBlocks), dim3(kB), 0, st, planes_of(*H, 0), s, p_old, p_new, q, sc,
                        static_cast<long long>(H->N), partials);
 }
