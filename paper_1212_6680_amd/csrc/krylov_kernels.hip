@@ -341,12 +341,16 @@ __global__ __launch_bounds__(kTileThreads) void k_matvec7_tiled(const double *x,
     const bool hin = hy >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
     const long long hc2 = static_cast<long long>(hj) * nx + hi;
     const double diag = 2.0 * (cx + cy + cz);
-    double xm = (in && k0 > 0 && k0 < nz) ? xr[(k0 - 1) * pl + c2] : 0.0;
-    double xc = (in && k0 < nz) ? xr[k0 * pl + c2] : 0.0;
+    // the column's values one plane ahead of their use and the halo one plane
+    // ahead of its staging, so a step's loads overlap the previous step
+    auto col = [&](int k) { return (in && k >= 0 && k < nz) ? xr[k * pl + c2] : 0.0; };
+    auto halo = [&](int k) { return (hin && k < k1) ? xr[k * pl + hc2] : 0.0; };
+    double xm = k0 > 0 ? col(k0 - 1) : 0.0;
+    double xc = col(k0), xn = col(k0 + 1), hv = halo(k0);
     for (int k = k0; k < k1; ++k) {
-        const double xn = (in && k + 1 < nz) ? xr[(k + 1) * pl + c2] : 0.0;
+        const double xnn = col(k + 2), hvn = halo(k + 1);
         tile[(ty + 1) * (kTX + 2) + tx + 1] = xc;
-        if (hy >= 0) tile[hy * (kTX + 2) + hx] = hin ? xr[k * pl + hc2] : 0.0;
+        if (hy >= 0) tile[hy * (kTX + 2) + hx] = hv;
         __syncthreads();
         if (in) {
             const int cc = (ty + 1) * (kTX + 2) + tx + 1;
@@ -356,6 +360,8 @@ __global__ __launch_bounds__(kTileThreads) void k_matvec7_tiled(const double *x,
         __syncthreads();
         xm = xc;
         xc = xn;
+        xn = xnn;
+        hv = hvn;
     }
 }
 
